@@ -1,0 +1,255 @@
+"""Seeded synthetic inputs shared by the tests, the benchmark and the oracle.
+
+This module holds no arithmetic of the method: it only lays out subpatch
+node coordinates, activity masks and side kinds, initial primitive states and
+random test data.  Geometry follows the shapes of the paper's workloads
+(Sec. 3 patch types, Sec. 7 test configurations); all inputs are synthetic.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+INTERNAL, INFLOW, OUTFLOW, SLIP, EXACT = 0, 1, 2, 3, 4
+GAMMA = 1.4
+SEED_BASE = 25061937
+
+
+def rng(config_index: int, salt: int = 0) -> np.random.Generator:
+    return np.random.Generator(np.random.PCG64(SEED_BASE + config_index + 7919 * salt))
+
+
+@dataclass
+class PatchSpec:
+    """One subpatch: node coordinates (n2, n1), optional activity mask,
+    side kinds W, E, S, N, kind of the mask boundary, inflow state."""
+    x: np.ndarray
+    y: np.ndarray
+    mask: np.ndarray | None = None
+    sides: dict = field(default_factory=lambda: {"W": INTERNAL, "E": INTERNAL, "S": INTERNAL, "N": INTERNAL})
+    notch: int = SLIP
+    inflow: tuple | None = None
+    kind: str = "I"
+
+    @property
+    def shape(self):
+        return self.x.shape
+
+    def npoints(self):
+        return int(self.x.size if self.mask is None else self.mask.sum())
+
+
+def box_patch(x0, x1, y0, y1, n1, n2, sides, kind="I", inflow=None):
+    """Cartesian subpatch on [x0, x1] x [y0, y1] with n1 x n2 nodes."""
+    xs = np.linspace(x0, x1, n1)
+    ys = np.linspace(y0, y1, n2)
+    X, Y = np.meshgrid(xs, ys)
+    return PatchSpec(X, Y, None, dict(sides), SLIP, inflow, kind)
+
+
+def lattice_patch(h, X0, X1, Y0, Y1, sides, kind="I", inflow=None, notch_box=None):
+    """Subpatch whose nodes are the lattice points (X h, Y h) for integer X in
+    [X0, X1], Y in [Y0, Y1]; ``notch_box`` = (Xa, Xb, Ya, Yb) masks the lattice
+    points with Xa <= X <= Xb and Ya <= Y <= Yb (the obstacle quadrant of an
+    L-shaped C1 corner subpatch)."""
+    Xi = np.arange(X0, X1 + 1)
+    Yi = np.arange(Y0, Y1 + 1)
+    XX, YY = np.meshgrid(Xi, Yi)
+    mask = None
+    if notch_box is not None:
+        Xa, Xb, Ya, Yb = notch_box
+        mask = ~((XX >= Xa) & (XX <= Xb) & (YY >= Ya) & (YY <= Yb))
+    return PatchSpec(XX * h, YY * h, mask, dict(sides), SLIP, inflow, kind)
+
+
+# ---------------------------------------------------------------- single-patch vortex
+def vortex_box(n=101, L=10.0):
+    """One Cartesian patch n x n over [0, L]^2 with exact-data sides (the
+    single-patch FP64 configuration)."""
+    s = {k: EXACT for k in "WESN"}
+    return [box_patch(0.0, L, 0.0, L, n, n, s, kind="I")]
+
+
+def vortex_multipatch(n=41):
+    """Four overlapping patches over [0, 10]^2 whose grids do not coincide:
+    the communication is a true interpolation."""
+    s = {k: EXACT for k in "WESN"}
+    out = []
+    h = 10.0 / (2 * n - 20)
+    # left column: spacing h; right column: spacing 0.93 h, shifted
+    for (xa, xb, nx) in ((0.0, (n - 1) * h, n), (10.0 - (n + 3) * 0.93 * h, 10.0, n + 4)):
+        for (ya, yb, ny) in ((0.0, (n - 1) * h, n), (10.0 - (n + 1) * 0.97 * h, 10.0, n + 2)):
+            sides = dict(s)
+            sides["E" if xa == 0.0 else "W"] = INTERNAL
+            sides["N" if ya == 0.0 else "S"] = INTERNAL
+            out.append(box_patch(xa, xb, ya, yb, nx, ny, sides))
+    return out
+
+
+def curved_patch(n1=48, n2=40, amp=0.05):
+    """A curvilinear patch (sinusoidally perturbed unit square), for
+    freestream-preservation checks."""
+    q1 = np.linspace(0, 1, n1)
+    q2 = np.linspace(0, 1, n2)
+    Q1, Q2 = np.meshgrid(q1, q2)
+    X = Q1 + amp * np.sin(2 * np.pi * Q2)
+    Y = Q2 + amp * np.sin(2 * np.pi * Q1) * 0.5 + 0.1 * Q1 * Q2
+    return [PatchSpec(X, Y, None, {k: EXACT for k in "WESN"}, SLIP, None, "I")]
+
+
+def annular_sector(n1=48, n2=32, r0=1.0, r1=2.0, th0=0.0, th1=np.pi / 3):
+    q1 = np.linspace(0, 1, n1)
+    q2 = np.linspace(0, 1, n2)
+    Q1, Q2 = np.meshgrid(q1, q2)
+    th = th0 + (th1 - th0) * Q1
+    r = r0 + (r1 - r0) * Q2
+    return [PatchSpec(r * np.cos(th), r * np.sin(th), None, {k: EXACT for k in "WESN"}, SLIP, None, "S")]
+
+
+# ---------------------------------------------------------------- Mach 3 step channel
+STEP_INFLOW = (1.4, 3.0, 0.0, 1.0)
+
+
+def step_channel(h_index=250):
+    """Mach 3 channel [0, 3] x [0, 1] with a step occupying [0.6, 3] x [0, 0.2]
+    (lattice spacing h = 1 / h_index).  Subpatches: an S/inflow column, a C2
+    corner patch at the foot of the step face, an L-shaped C1 corner patch at
+    the step corner, patches above it and two rows of patches over the step;
+    all share one lattice, so overlaps are exchanges."""
+    h = 1.0 / h_index
+    s = h_index / 250.0
+    I = lambda v: int(round(v * s))
+    XW, XS, YS, XE, YT = 0, I(150), I(50), I(750), I(250)  # x = 0, 0.6 ; y = 0.2 ; x = 3 ; y = 1
+    e = 8  # half overlap: neighbouring cores overlap by 2 e + 1 points
+    pts = []
+
+    def add(X0, X1, Y0, Y1, W, E, S, N, kind="I", notch=None):
+        pts.append(lattice_patch(h, X0, X1, Y0, Y1, {"W": W, "E": E, "S": S, "N": N}, kind,
+                                 STEP_INFLOW, notch))
+
+    A1 = I(110)
+    ylev = [0, YS, I(150), YT]
+    # inflow column x in [0, A1]: two columns of cores, three rows
+    xa = [XW, I(55), A1]
+    for c in range(2):
+        for r in range(3):
+            X0 = xa[c] - (e if c > 0 else 0)
+            X1 = xa[c + 1] + e
+            Y0 = ylev[r] - (e if r > 0 else 0)
+            Y1 = ylev[r + 1] + (e if r < 2 else 0)
+            add(X0, X1, Y0, Y1, INFLOW if c == 0 else INTERNAL, INTERNAL,
+                SLIP if r == 0 else INTERNAL, SLIP if r == 2 else INTERNAL,
+                "S" if (c == 0 or r in (0, 2)) else "I")
+    B0, B1 = A1 - e, I(190) + e
+    # C2 corner patch: step face (east) and bottom wall (south)
+    add(B0, XS, 0, YS, INTERNAL, SLIP, SLIP, INTERNAL, "C2")
+    # C1 L-shaped corner patch around (0.6, 0.2); the quadrant x > 0.6, y < 0.2 is the obstacle
+    Ly0, Ly1 = I(10), I(90) + e
+    add(B0, B1, Ly0, Ly1, INTERNAL, INTERNAL, INTERNAL, INTERNAL, "C1", notch=(XS + 1, B1, Ly0, YS - 1))
+    # above the L patch
+    add(B0, B1, I(90) - e, I(165) + e, INTERNAL, INTERNAL, INTERNAL, INTERNAL, "I")
+    add(B0, B1, I(165) - e, YT, INTERNAL, INTERNAL, INTERNAL, SLIP, "S")
+    # over the step: columns of cores between x = 0.76 and x = 3
+    xr = [I(190), I(285), I(380), I(475), I(570), I(660), XE]
+    yr = [YS, I(150), YT]
+    for c in range(len(xr) - 1):
+        last = c == len(xr) - 2
+        X0 = xr[c] - e
+        X1 = xr[c + 1] + (0 if last else e)
+        for r in range(2):
+            Y0 = yr[r] - (e if r > 0 else 0)
+            Y1 = yr[r + 1] + (e if r == 0 else 0)
+            add(X0, X1, Y0, Y1, INTERNAL, OUTFLOW if last else INTERNAL,
+                SLIP if r == 0 else INTERNAL, SLIP if r == 1 else INTERNAL, "S")
+    return pts
+
+
+def uniform_state(patch_list, prim):
+    return [np.broadcast_to(np.asarray(prim, dtype=float)[:, None, None], (4,) + p.shape).copy()
+            for p in patch_list]
+
+
+# ---------------------------------------------------------------- derivative sweep
+FIELD_OFFSET_SCALE = ((1.4, 0.14), (4.2, 0.42), (0.0, 0.42), (8.8, 0.88))
+
+
+def deriv_sweep(npatch=2000, nmin=64, nmax=256, config_index=3, seed_salt=0):
+    """Patches with sides drawn uniformly from [nmin, nmax] and four fields of
+    smooth random trigonometric sums (Mach-3 freestream magnitudes), with a
+    jump added along 5 % of the q^1 lines and 5 % of the q^2 lines.
+    Returns (sizes (npatch, 2) as (n1, n2), list of fields (4, n2, n1))."""
+    g = rng(config_index, seed_salt)
+    sizes = g.integers(nmin, nmax + 1, size=(npatch, 2))
+    fields = []
+    for (n1, n2) in sizes:
+        q1 = np.linspace(0, 1, n1)[None, :]
+        q2 = np.linspace(0, 1, n2)[:, None]
+        f = np.empty((4, n2, n1))
+        for c, (off, sc) in enumerate(FIELD_OFFSET_SCALE):
+            a = g.standard_normal(8) / np.sqrt(8)
+            k1 = g.uniform(-6, 6, 8)
+            k2 = g.uniform(-6, 6, 8)
+            ph = g.uniform(0, 2 * np.pi, 8)
+            v = np.zeros((n2, n1))
+            for k in range(8):
+                v += a[k] * np.cos(2 * np.pi * (k1[k] * q1 + k2[k] * q2) + ph[k])
+            rows = np.flatnonzero(g.random(n2) < 0.05)
+            for j in rows:
+                qj = g.uniform(0.1, 0.9)
+                v[j] += g.uniform(0.1, 1.0) * (q1[0] >= qj)
+            cols = np.flatnonzero(g.random(n1) < 0.05)
+            for i in cols:
+                qj = g.uniform(0.1, 0.9)
+                v[:, i] += g.uniform(0.1, 1.0) * (q2[:, 0] >= qj)
+            f[c] = off + sc * v
+        fields.append(f)
+    return sizes, fields
+
+
+# ---------------------------------------------------------------- classifier lines
+def classifier_lines(nlines, n=101, config_index=4, seed_salt=0):
+    """Raw synthetic lines for the smoothness classifier: smooth random
+    Fourier sums plus 0-2 jumps at uniform positions with log-uniform
+    amplitudes in [1e-3, 1] and random sign.  Returns (lines (nlines, n),
+    jump positions (nlines, 2) in index units, NaN when absent, jump
+    amplitudes (nlines, 2))."""
+    g = rng(config_index, seed_salt)
+    x = np.linspace(0, 1, n)
+    lines = np.zeros((nlines, n))
+    K = g.integers(1, 13, size=nlines)
+    for r in range(nlines):
+        b = g.standard_normal(K[r]) / np.arange(1, K[r] + 1)
+        ph = g.uniform(0, 2 * np.pi, K[r])
+        lines[r] = (b[:, None] * np.sin(2 * np.pi * np.arange(1, K[r] + 1)[:, None] * x[None, :] + ph[:, None])).sum(0)
+    nj = g.integers(0, 3, size=nlines)
+    pos = np.full((nlines, 2), np.nan)
+    amp = np.zeros((nlines, 2))
+    for r in range(nlines):
+        for k in range(nj[r]):
+            q = g.uniform(0.02, 0.98)
+            a = 10.0 ** g.uniform(-3, 0) * (1 if g.random() < 0.5 else -1)
+            pos[r, k] = q * (n - 1)
+            amp[r, k] = a
+            lines[r] += a * (x >= q)
+    return lines, pos, amp
+
+
+def window_labels(pos, amp, lines, n=101, rel_tol=1e-2):
+    """Class of the 16-point window of every point of every line: 2 when a
+    significant jump lies within 2 points of the point, 1 when one lies
+    elsewhere in the window, else 0 (a jump is significant when its amplitude
+    is at least rel_tol times the line's range)."""
+    nl = lines.shape[0]
+    start = np.clip(np.arange(n) - 8, 0, n - 16)
+    lab = np.zeros((nl, n), dtype=np.int64)
+    rngv = lines.max(axis=1) - lines.min(axis=1)
+    for k in range(pos.shape[1]):
+        p = pos[:, k]
+        sig = np.isfinite(p) & (np.abs(amp[:, k]) >= rel_tol * np.maximum(rngv, 1e-300))
+        pp = np.where(np.isfinite(p), p, -1e9)[:, None]
+        i = np.arange(n)[None, :]
+        inwin = (pp >= start[None, :]) & (pp <= start[None, :] + 15)
+        near = np.abs(pp - i) <= 2.0
+        lab = np.where(sig[:, None] & near, 2, np.where(sig[:, None] & inwin & (lab < 2), np.maximum(lab, 1), lab))
+    return lab
