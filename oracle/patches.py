@@ -144,6 +144,9 @@ class Grid:
         # error) uses the exact constant metrics.
         self.affine = bool(np.abs(met[:, m] - mean[:, None]).max() <= 1e-6 * scale)
         if self.affine:
+            # components below 1e-6 of the largest are zero (axis-aligned
+            # grids are then exactly Cartesian)
+            mean = np.where(np.abs(mean) <= 1e-6 * scale, 0.0, mean)
             met = np.where(m, mean[:, None, None], 0.0) * np.ones_like(met)
         else:
             met = np.where(m, met, 0.0)

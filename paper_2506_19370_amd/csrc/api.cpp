@@ -1,0 +1,1051 @@
+// C ABI of the solver: context creation (Alg. 2 on one GPU), workspace
+// layout, per-step and per-stage launch sequence (Alg. 1, 3, 4, 5), queries.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fcsdnn.h"
+#include "fc_builder.h"
+#include "gemm.h"
+#include "geometry.h"
+#include "kernels.h"
+#include "stage_kernels.h"
+#include "window_kernels.h"
+
+using namespace fcs;
+
+namespace {
+
+// SSPRK(5,4), Shu-Osher form (Spiteri & Ruuth); see the stage kernel.
+constexpr double kA0 = 0.391752226571890;
+constexpr double kB20 = 0.444370493651235, kB21 = 0.555629506348765, kA1 = 0.368410593050371;
+constexpr double kB30 = 0.620101851488403, kB32 = 0.379898148511597, kA2 = 0.251891774271694;
+constexpr double kB40 = 0.178079954393132, kB43 = 0.821920045606868, kA3 = 0.544974750228521;
+constexpr double kC2 = 0.517231671970585, kC3 = 0.096059710526147, kD3 = 0.063692468666290;
+constexpr double kC4 = 0.386708617503269, kD4 = 0.226007483236906;
+
+void stage_fractions(double* c) {
+  // stage outputs approximate the solution at t + c[s] dt (Butcher abscissae)
+  double a1 = kA0;
+  double a2[2] = {kB21 * a1, kA1};
+  double a3[3] = {kB32 * a2[0], kB32 * a2[1], kA2};
+  double a4[4] = {kB43 * a3[0], kB43 * a3[1], kB43 * a3[2], kA3};
+  c[0] = a1;
+  c[1] = a2[0] + a2[1];
+  c[2] = a3[0] + a3[1] + a3[2];
+  c[3] = a4[0] + a4[1] + a4[2] + a4[3];
+  c[4] = 1.0;
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct Carve {
+  size_t used = 0;
+  size_t take(size_t bytes) {
+    size_t o = used;
+    used = align_up(used + std::max<size_t>(bytes, 1));
+    return o;
+  }
+};
+
+// A contraction task before device pointers are known.
+struct TaskSpec {
+  int src_arr, dst_arr;  // array ids
+  int64_t src_off, dst_off;
+  int32_t row_stride, s_stride, nrow, ncomp, n, op;
+};
+
+enum ArrayId { A_U0, A_UA, A_UB, A_F, A_DF1, A_DF2, A_W1, A_W2, A_W11, A_W22, A_W12, A_MU, A_MU1, A_MU2, A_IN, A_NARR };
+
+enum Phase { PH_EULER, PH_CROSS, PH_MUGRAD, PH_FILT1, PH_FILT2, PH_N };
+
+struct OpKey {
+  int n, kind;
+  bool operator<(const OpKey& o) const { return n < o.n || (n == o.n && kind < o.kind); }
+};
+
+}  // namespace
+
+struct fcs_ctx {
+  fcs_params prm{};
+  std::vector<float> sdnn;  // bf16-rounded weights, FP32 biases
+  std::vector<Grid> grids;
+  int64_t P = 0, nactive = 0;
+  bool visc = false, cross = false;
+  std::string err;
+
+  // operators
+  std::map<OpKey, int> op_index;
+  std::vector<OpKey> ops;
+  std::vector<int64_t> op_off, op_roff;
+  int64_t op_elems = 0, op_rows = 0;
+
+  std::vector<TaskSpec> phase_tasks[PH_N];
+  std::vector<GemmTile> phase_tiles[PH_N];
+
+  // host tables
+  std::vector<uint8_t> flags;
+  std::vector<int32_t> pid;
+  std::vector<PatchDev> pdev;
+  std::vector<int2> rowrun, colrun;
+  std::vector<int64_t> copy_pairs, idst, icol, bdst, bcol;
+  std::vector<int32_t> iptr, bptr;
+  std::vector<double> ival, bval;
+  std::vector<SlipEntry> slip;
+  std::vector<DirichletEntry> dirich;
+  std::vector<ExactEntry> exact;
+  std::vector<double> metric_host[10];  // t1x t1y t2x t2y g11 g12 g22 lap1 lap2 hx
+  std::vector<double> basis, wdil;
+  std::vector<uint8_t> tau_host;
+
+  // device
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  hipStream_t stream = nullptr;
+  bool bound = false;
+  std::map<std::string, size_t> off;
+  double* arr[A_NARR] = {};
+  GemmTask* d_tasks[PH_N][3] = {};
+  GemmTile* d_tiles[PH_N] = {};
+  OpTables optab{};
+  int dt_blocks = 512;
+
+  // time stepping
+  int stage_in_step = 0;
+  int64_t steps = 0, stages = 0;
+  double t_host = 0.0;
+  double* cur = nullptr;  // buffer that holds the latest state
+
+  // profiling
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double prof_ms = 0.0;
+  int64_t prof_n = 0;
+
+  // graphs
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] step without filter, [1] with
+
+  template <typename T>
+  T* dptr(const char* name) {
+    return reinterpret_cast<T*>(ws + off.at(name));
+  }
+  fcs_status fail(fcs_status s, const std::string& m) {
+    err = m;
+    return s;
+  }
+};
+
+namespace {
+
+#define HIPCHK(ctx, call)                                                                   \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess) return (ctx)->fail(FCS_EHIP, std::string(#call) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint16_t host_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+float host_bf16_to_f(uint16_t h) {
+  uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+int op_id(fcs_ctx* c, int n, int kind) {
+  OpKey k{n, kind};
+  auto it = c->op_index.find(k);
+  if (it != c->op_index.end()) return it->second;
+  int id = static_cast<int>(c->ops.size());
+  c->ops.push_back(k);
+  c->op_index[k] = id;
+  return id;
+}
+
+// Tasks for all lines of one grid along one direction, grouped by runs.
+void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int src_arr, int src_comp0,
+                    int dst_arr, int dst_comp0, int ncomp) {
+  const int nl = dir == 0 ? g.n2 : g.n1;
+  const std::vector<Run>& runs = dir == 0 ? g.rows : g.cols;
+  int l = 0;
+  while (l < nl) {
+    if (!runs[l].len) {
+      ++l;
+      continue;
+    }
+    int l1 = l + 1;
+    while (l1 < nl && runs[l1].start == runs[l].start && runs[l1].len == runs[l].len) ++l1;
+    TaskSpec t;
+    t.src_arr = src_arr;
+    t.dst_arr = dst_arr;
+    int64_t first = dir == 0 ? (g.offset + static_cast<int64_t>(l) * g.n1 + runs[l].start)
+                             : (g.offset + static_cast<int64_t>(runs[l].start) * g.n1 + l);
+    t.src_off = static_cast<int64_t>(src_comp0) * c->P + first;
+    t.dst_off = static_cast<int64_t>(dst_comp0) * c->P + first;
+    t.row_stride = dir == 0 ? g.n1 : 1;
+    t.s_stride = dir == 0 ? 1 : g.n1;
+    t.nrow = l1 - l;
+    t.ncomp = ncomp;
+    t.n = runs[l].len;
+    t.op = op_id(c, runs[l].len, kind);
+    c->phase_tasks[ph].push_back(t);
+    l = l1;
+  }
+}
+
+void build_tiles(fcs_ctx* c) {
+  for (int ph = 0; ph < PH_N; ++ph) {
+    auto& tiles = c->phase_tiles[ph];
+    tiles.clear();
+    const auto& tasks = c->phase_tasks[ph];
+    for (size_t q = 0; q < tasks.size(); ++q) {
+      int nlines = tasks[q].nrow * tasks[q].ncomp;
+      for (int t0 = 0; t0 < tasks[q].n; t0 += 64)
+        for (int l0 = 0; l0 < nlines; l0 += 64) tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
+    }
+  }
+}
+
+double exact_flops(const std::vector<TaskSpec>& tasks) {
+  double f = 0;
+  for (const auto& t : tasks) f += 2.0 * t.n * t.n * static_cast<double>(t.nrow) * t.ncomp;
+  return f;
+}
+
+fcs_status upload(fcs_ctx* c, const char* name, const void* src, size_t bytes) {
+  if (!bytes) return FCS_OK;
+  HIPCHK(c, hipMemcpyAsync(c->ws + c->off.at(name), src, bytes, hipMemcpyHostToDevice, c->stream));
+  return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" int fcs_version(void) { return 100; }
+
+extern "C" const char* fcs_last_error(const fcs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fcs_patch_desc* patches,
+                                 fcs_ctx** out) {
+  if (!prm || !patches || !out || npatch <= 0) return FCS_EINVAL;
+  *out = nullptr;
+  std::unique_ptr<fcs_ctx> c(new (std::nothrow) fcs_ctx());
+  if (!c) return FCS_ENOMEM;
+  c->prm = *prm;
+  c->prm.sdnn_weights = nullptr;
+  const fcs_params& p = c->prm;
+  if (p.fc_d < 1 || p.fc_d > 12 || p.fc_C < 4 || p.fc_C > 64 || p.n_f < 1 || p.n_v < 1 || p.n_v > 64 ||
+      p.precision < 0 || p.precision > 2 || p.av_mode < 0 || p.av_mode > 3 || !(p.gamma > 1.0) ||
+      !(p.cfl > 0.0)) {
+    *out = c.release();
+    return (*out)->fail(FCS_EINVAL, "invalid solver parameters");
+  }
+  c->visc = p.av_mode != FCS_AV_OFF;
+  if (p.av_mode == FCS_AV_SDNN) {
+    if (!prm->sdnn_weights) {
+      *out = c.release();
+      return (*out)->fail(FCS_EINVAL, "SDNN viscosity needs weights");
+    }
+    c->sdnn.assign(prm->sdnn_weights, prm->sdnn_weights + FCS_SDNN_NPARAM);
+    // weights rounded to bf16 (the products' precision); biases stay FP32
+    const int wsec[3][2] = {{0, 64 * 16}, {64 * 16 + 64, 64 * 64}, {64 * 16 + 64 + 64 * 64 + 64, 3 * 64}};
+    for (auto& s : wsec)
+      for (int q = s[0]; q < s[0] + s[1]; ++q) c->sdnn[q] = host_bf16_to_f(host_bf16(c->sdnn[q]));
+  }
+  // grids
+  c->grids.resize(npatch);
+  int64_t offset = 0;
+  std::string err;
+  for (int q = 0; q < npatch; ++q) {
+    const fcs_patch_desc& d = patches[q];
+    Grid& g = c->grids[q];
+    if (d.n1 < 2 * p.fc_d || d.n2 < 2 * p.fc_d || d.n1 > 1024 || d.n2 > 1024 || !d.x || !d.y) {
+      *out = c.release();
+      return (*out)->fail(FCS_EINVAL, "subpatch " + std::to_string(q) + ": bad size or coordinates");
+    }
+    for (int s = 0; s < 4; ++s)
+      if (d.side[s] < 0 || d.side[s] > 4) {
+        *out = c.release();
+        return (*out)->fail(FCS_EINVAL, "bad side kind");
+      }
+    g.n1 = d.n1;
+    g.n2 = d.n2;
+    g.type = d.type;
+    size_t np = g.np();
+    g.x.assign(d.x, d.x + np);
+    g.y.assign(d.y, d.y + np);
+    if (d.mask) g.mask.assign(d.mask, d.mask + np);
+    for (int s = 0; s < 4; ++s) g.side[s] = d.side[s];
+    g.notch = d.notch;
+    for (int s = 0; s < 4; ++s) g.inflow[s] = d.inflow[s];
+    if (g.type == FCS_PATCH_C1 && !d.mask) {
+      *out = c.release();
+      return (*out)->fail(FCS_EINVAL, "C1 subpatch without mask");
+    }
+    g.offset = offset;
+    offset += static_cast<int64_t>(np);
+    if (!build_grid(g, p.fc_d, p.fc_C, p.n_f, err)) {
+      *out = c.release();
+      return (*out)->fail(FCS_EINVAL, "subpatch " + std::to_string(q) + ": " + err);
+    }
+  }
+  c->P = offset;
+  // per-point tables
+  const int64_t P = c->P;
+  c->flags.assign(P, 0);
+  c->pid.assign(P, 0);
+  for (auto& m : c->metric_host) m.assign(P, 0.0);
+  int rr = 0, cr = 0;
+  for (int q = 0; q < npatch; ++q) {
+    const Grid& g = c->grids[q];
+    PatchDev pd{};
+    pd.offset = g.offset;
+    pd.n1 = g.n1;
+    pd.n2 = g.n2;
+    pd.row_run = rr;
+    pd.col_run = cr;
+    pd.affine = g.affine;
+    c->pdev.push_back(pd);
+    for (const Run& r : g.rows) c->rowrun.push_back(make_int2(r.start, r.len));
+    for (const Run& r : g.cols) c->colrun.push_back(make_int2(r.start, r.len));
+    rr += g.n2;
+    cr += g.n1;
+    const std::vector<double>* src[10] = {&g.t1x, &g.t1y, &g.t2x, &g.t2y, &g.g11, &g.g12, &g.g22, &g.lap1, &g.lap2, &g.hx};
+    for (size_t k = 0; k < g.np(); ++k) {
+      int64_t gk = g.offset + static_cast<int64_t>(k);
+      uint8_t f = 0;
+      if (g.mask[k]) {
+        f |= kActive;
+        ++c->nactive;
+      }
+      if (g.fringe[k]) f |= kFringe;
+      if (g.xfringe[k]) f |= kXFringe;
+      if (g.affine) f |= kAffine;
+      c->flags[gk] = f;
+      c->pid[gk] = q;
+      for (int m = 0; m < 10; ++m) c->metric_host[m][gk] = (*src[m])[k];
+      if (g.mask[k] && g.g12[k] != 0.0) c->cross = true;
+    }
+    // boundary conditions: one slip entry per point, Dirichlet entries
+    std::map<int64_t, std::vector<std::pair<double, double>>> normals;
+    std::vector<int64_t> order;
+    for (const BoundaryEntry& b : g.bnd) {
+      size_t k = g.at(b.j, b.i);
+      int64_t gk = g.offset + static_cast<int64_t>(k);
+      if (b.kind == kSlip) {
+        double nx = b.dir == 0 ? g.t1x[k] : g.t2x[k];
+        double ny = b.dir == 0 ? g.t1y[k] : g.t2y[k];
+        double h = std::hypot(nx, ny);
+        if (!normals.count(gk)) order.push_back(gk);
+        normals[gk].push_back({nx / h, ny / h});
+      }
+    }
+    for (int64_t gk : order) {
+      const auto& ns = normals[gk];
+      SlipEntry e{};
+      e.k = gk;
+      e.nx = ns[0].first;
+      e.ny = ns[0].second;
+      e.corner = ns.size() > 1;
+      c->slip.push_back(e);
+    }
+    for (const BoundaryEntry& b : g.bnd) {
+      if (b.kind != kInflow) continue;
+      DirichletEntry e{};
+      e.k = g.offset + static_cast<int64_t>(g.at(b.j, b.i));
+      double r = g.inflow[0], u = g.inflow[1], v = g.inflow[2], pr = g.inflow[3];
+      e.e[0] = r;
+      e.e[1] = r * u;
+      e.e[2] = r * v;
+      e.e[3] = pr / (p.gamma - 1.0) + 0.5 * r * (u * u + v * v);
+      c->dirich.push_back(e);
+    }
+    for (size_t k = 0; k < g.np(); ++k)
+      if (g.xfringe[k]) c->exact.push_back({g.offset + static_cast<int64_t>(k), g.x[k], g.y[k]});
+  }
+  // communication tables
+  std::vector<InterpRow> rows;
+  if (npatch > 1 && !build_fringe_rows(c->grids, rows, err)) {
+    *out = c.release();
+    return (*out)->fail(FCS_EOVERLAP, err);
+  }
+  c->iptr.push_back(0);
+  for (const InterpRow& r : rows) {
+    if (r.ent.size() == 1 && r.ent[0].second == 1.0) {
+      c->copy_pairs.push_back(r.dst);
+      c->copy_pairs.push_back(r.ent[0].first);
+    } else {
+      c->idst.push_back(r.dst);
+      for (const auto& e : r.ent) {
+        c->icol.push_back(e.first);
+        c->ival.push_back(e.second);
+      }
+      c->iptr.push_back(static_cast<int32_t>(c->icol.size()));
+    }
+  }
+  c->bptr.push_back(0);
+  if (c->visc && npatch > 1) {
+    std::vector<InterpRow> brows;
+    build_blend_rows(c->grids, p.n_v, brows);
+    for (const InterpRow& r : brows) {
+      c->bdst.push_back(r.dst);
+      for (const auto& e : r.ent) {
+        c->bcol.push_back(e.first);
+        c->bval.push_back(e.second);
+      }
+      c->bptr.push_back(static_cast<int32_t>(c->bcol.size()));
+    }
+  }
+  // viscosity tables: dilation weights, modal basis
+  c->wdil.assign(p.n_v + 1, 0.0);
+  for (int o = 0; o < p.n_v; ++o) {
+    double t = static_cast<double>(o) / p.n_v;
+    c->wdil[o] = std::exp(1.0 - 1.0 / (1.0 - t * t));
+  }
+  c->basis.assign(256, 0.0);
+  modal_basis16(c->basis.data());
+  // contraction tasks
+  for (int q = 0; q < npatch; ++q) {
+    const Grid& g = c->grids[q];
+    if (g.affine) {
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_F, 0, A_DF1, 0, 4);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_F, 4, A_DF2, 4, 4);
+    } else {
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_F, 0, A_DF1, 0, 8);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_F, 0, A_DF2, 0, 8);
+    }
+    if (c->visc) {
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_IN, 0, A_W1, 0, 4);
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D2, A_IN, 0, A_W11, 0, 4);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_IN, 0, A_W2, 0, 4);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D2, A_IN, 0, A_W22, 0, 4);
+      if (c->cross) add_line_tasks(c.get(), PH_CROSS, g, 1, FCS_OP_D1, A_W1, 0, A_W12, 0, 4);
+      add_line_tasks(c.get(), PH_MUGRAD, g, 0, FCS_OP_D1, A_MU, 0, A_MU1, 0, 1);
+      add_line_tasks(c.get(), PH_MUGRAD, g, 1, FCS_OP_D1, A_MU, 0, A_MU2, 0, 1);
+    }
+    if (p.filter) {
+      add_line_tasks(c.get(), PH_FILT1, g, 0, FCS_OP_FILTER, A_F, 0, A_DF1, 0, 4);
+      add_line_tasks(c.get(), PH_FILT2, g, 1, FCS_OP_FILTER, A_DF1, 0, A_DF2, 0, 4);
+    }
+  }
+  build_tiles(c.get());
+  // operators
+  for (const OpKey& k : c->ops) {
+    c->op_off.push_back(c->op_elems);
+    c->op_roff.push_back(c->op_rows);
+    c->op_elems += static_cast<int64_t>(k.n) * k.n;
+    c->op_rows += k.n;
+  }
+  // workspace layout
+  Carve cv;
+  auto& o = c->off;
+  const size_t D = sizeof(double);
+  for (const char* n : {"U0", "UA", "UB", "ACC"}) o[n] = cv.take(4 * P * D);
+  for (const char* n : {"F", "DF1", "DF2"}) o[n] = cv.take(8 * P * D);
+  if (c->visc) {
+    for (const char* n : {"W1", "W2", "W11", "W22"}) o[n] = cv.take(4 * P * D);
+    o["W12"] = cv.take((c->cross ? 4 * P : 1) * D);
+    for (const char* n : {"MU", "MU1", "MU2", "MUHAT", "MUT", "TMP", "PHI", "SPD"}) o[n] = cv.take(P * D);
+    o["TAU"] = cv.take(2 * P);
+  }
+  for (int m = 0; m < 10; ++m) o["MET" + std::to_string(m)] = cv.take(P * D);
+  o["FLAGS"] = cv.take(P);
+  o["PID"] = cv.take(P * 4);
+  o["PATCH"] = cv.take(c->pdev.size() * sizeof(PatchDev));
+  o["ROWRUN"] = cv.take(c->rowrun.size() * sizeof(int2));
+  o["COLRUN"] = cv.take(c->colrun.size() * sizeof(int2));
+  o["OPOFF"] = cv.take(c->op_off.size() * 8);
+  o["OPROFF"] = cv.take(c->op_roff.size() * 8);
+  o["OPF64"] = cv.take(c->op_elems * D);
+  o["OPROW"] = cv.take(c->op_rows * D);
+  if (p.precision == FCS_PREC_FP32) o["OPF32"] = cv.take(c->op_elems * 4);
+  if (p.precision == FCS_PREC_BF16X3) {
+    o["OPBHI"] = cv.take(c->op_elems * 2);
+    o["OPBLO"] = cv.take(c->op_elems * 2);
+  }
+  for (int ph = 0; ph < PH_N; ++ph) {
+    for (int v = 0; v < 3; ++v)
+      o["TASK" + std::to_string(ph) + "_" + std::to_string(v)] = cv.take(c->phase_tasks[ph].size() * sizeof(GemmTask));
+    o["TILE" + std::to_string(ph)] = cv.take(c->phase_tiles[ph].size() * sizeof(GemmTile));
+  }
+  o["COPY"] = cv.take(c->copy_pairs.size() * 8);
+  o["IDST"] = cv.take(c->idst.size() * 8);
+  o["IPTR"] = cv.take(c->iptr.size() * 4);
+  o["ICOL"] = cv.take(c->icol.size() * 8);
+  o["IVAL"] = cv.take(c->ival.size() * D);
+  o["BDST"] = cv.take(c->bdst.size() * 8);
+  o["BPTR"] = cv.take(c->bptr.size() * 4);
+  o["BCOL"] = cv.take(c->bcol.size() * 8);
+  o["BVAL"] = cv.take(c->bval.size() * D);
+  o["SLIP"] = cv.take(c->slip.size() * sizeof(SlipEntry));
+  o["DIRI"] = cv.take(c->dirich.size() * sizeof(DirichletEntry));
+  o["EXACT"] = cv.take(c->exact.size() * sizeof(ExactEntry));
+  o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
+  o["BASIS"] = cv.take(256 * D);
+  o["WDIL"] = cv.take((p.n_v + 1) * D);
+  o["SCAL"] = cv.take(8 * D);  // t, dt, last_dt, bad flag
+  o["DTPART"] = cv.take(c->dt_blocks * D);
+  c->ws_need = cv.used;
+  c->tau_host.assign(2 * P, 0);
+  *out = c.release();
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_workspace_size(const fcs_ctx* ctx, size_t* bytes) {
+  if (!ctx || !bytes) return FCS_EINVAL;
+  *bytes = ctx->ws_need;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* stream) {
+  if (!c || !workspace) return FCS_EINVAL;
+  if (bytes < c->ws_need) return c->fail(FCS_ENOMEM, "workspace smaller than fcs_workspace_size");
+  if (reinterpret_cast<uintptr_t>(workspace) % kAlign) return c->fail(FCS_EINVAL, "workspace not 256-byte aligned");
+  c->ws = static_cast<char*>(workspace);
+  c->ws_bytes = bytes;
+  c->stream = static_cast<hipStream_t>(stream);
+  HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_need, c->stream));
+  const int64_t P = c->P;
+  // operators in every precision the context uses
+  std::vector<double> f64(c->op_elems), rows(c->op_rows);
+  for (size_t k = 0; k < c->ops.size(); ++k) {
+    const std::vector<double>* op = fc_operator(c->ops[k].n, c->prm.fc_d, c->prm.fc_C, c->ops[k].kind);
+    if (!op) return c->fail(FCS_EINVAL, "unsupported operator length");
+    std::copy(op->begin(), op->end(), f64.begin() + c->op_off[k]);
+    int n = c->ops[k].n;
+    for (int t = 0; t < n; ++t) {
+      double s = 0;
+      for (int q = 0; q < n; ++q) s += (*op)[static_cast<size_t>(t) * n + q];
+      rows[c->op_roff[k] + t] = s;
+    }
+  }
+  fcs_status st;
+  if ((st = upload(c, "OPF64", f64.data(), f64.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPROW", rows.data(), rows.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPOFF", c->op_off.data(), c->op_off.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPROFF", c->op_roff.data(), c->op_roff.size() * 8)) != FCS_OK) return st;
+  std::vector<float> f32;
+  std::vector<uint16_t> bhi, blo;
+  if (c->prm.precision == FCS_PREC_FP32) {
+    f32.resize(f64.size());
+    for (size_t q = 0; q < f64.size(); ++q) f32[q] = static_cast<float>(f64[q]);
+    if ((st = upload(c, "OPF32", f32.data(), f32.size() * 4)) != FCS_OK) return st;
+  }
+  if (c->prm.precision == FCS_PREC_BF16X3) {
+    bhi.resize(f64.size());
+    blo.resize(f64.size());
+    for (size_t q = 0; q < f64.size(); ++q) {
+      float f = static_cast<float>(f64[q]);
+      bhi[q] = host_bf16(f);
+      blo[q] = host_bf16(f - host_bf16_to_f(bhi[q]));
+    }
+    if ((st = upload(c, "OPBHI", bhi.data(), bhi.size() * 2)) != FCS_OK) return st;
+    if ((st = upload(c, "OPBLO", blo.data(), blo.size() * 2)) != FCS_OK) return st;
+  }
+  c->optab.off = c->dptr<int64_t>("OPOFF");
+  c->optab.roff = c->dptr<int64_t>("OPROFF");
+  c->optab.f64 = c->dptr<double>("OPF64");
+  c->optab.rowsum = c->dptr<double>("OPROW");
+  c->optab.f32 = c->prm.precision == FCS_PREC_FP32 ? c->dptr<float>("OPF32") : nullptr;
+  c->optab.bhi = c->prm.precision == FCS_PREC_BF16X3 ? c->dptr<uint16_t>("OPBHI") : nullptr;
+  c->optab.blo = c->prm.precision == FCS_PREC_BF16X3 ? c->dptr<uint16_t>("OPBLO") : nullptr;
+  // arrays
+  c->arr[A_U0] = c->dptr<double>("U0");
+  c->arr[A_UA] = c->dptr<double>("UA");
+  c->arr[A_UB] = c->dptr<double>("UB");
+  c->arr[A_F] = c->dptr<double>("F");
+  c->arr[A_DF1] = c->dptr<double>("DF1");
+  c->arr[A_DF2] = c->dptr<double>("DF2");
+  if (c->visc) {
+    c->arr[A_W1] = c->dptr<double>("W1");
+    c->arr[A_W2] = c->dptr<double>("W2");
+    c->arr[A_W11] = c->dptr<double>("W11");
+    c->arr[A_W22] = c->dptr<double>("W22");
+    c->arr[A_W12] = c->dptr<double>("W12");
+    c->arr[A_MU] = c->dptr<double>("MU");
+    c->arr[A_MU1] = c->dptr<double>("MU1");
+    c->arr[A_MU2] = c->dptr<double>("MU2");
+  }
+  // tasks: three variants by the stage input buffer (U0, UA, UB)
+  std::vector<GemmTask> staging_tasks[PH_N][3];
+  for (int ph = 0; ph < PH_N; ++ph)
+    for (int v = 0; v < 3; ++v) {
+      std::vector<GemmTask>& dt = staging_tasks[ph][v];
+      dt.clear();
+      for (const TaskSpec& s : c->phase_tasks[ph]) {
+        GemmTask t{};
+        double* sbase = s.src_arr == A_IN ? c->arr[A_U0 + v] : c->arr[s.src_arr];
+        t.src = sbase + s.src_off;
+        t.dst = c->arr[s.dst_arr] + s.dst_off;
+        t.comp_stride = P;
+        t.row_stride = s.row_stride;
+        t.s_stride = s.s_stride;
+        t.nrow = s.nrow;
+        t.ncomp = s.ncomp;
+        t.n = s.n;
+        t.op = s.op;
+        dt.push_back(t);
+      }
+      std::string name = "TASK" + std::to_string(ph) + "_" + std::to_string(v);
+      if ((st = upload(c, name.c_str(), dt.data(), dt.size() * sizeof(GemmTask))) != FCS_OK) return st;
+      c->d_tasks[ph][v] = c->dptr<GemmTask>(name.c_str());
+    }
+  for (int ph = 0; ph < PH_N; ++ph) {
+    std::string name = "TILE" + std::to_string(ph);
+    if ((st = upload(c, name.c_str(), c->phase_tiles[ph].data(), c->phase_tiles[ph].size() * sizeof(GemmTile))) !=
+        FCS_OK)
+      return st;
+    c->d_tiles[ph] = c->dptr<GemmTile>(name.c_str());
+  }
+  for (int m = 0; m < 10; ++m) {
+    std::string name = "MET" + std::to_string(m);
+    if ((st = upload(c, name.c_str(), c->metric_host[m].data(), P * 8)) != FCS_OK) return st;
+  }
+  struct {
+    const char* n;
+    const void* p;
+    size_t b;
+  } ups[] = {
+      {"FLAGS", c->flags.data(), c->flags.size()},
+      {"PID", c->pid.data(), c->pid.size() * 4},
+      {"PATCH", c->pdev.data(), c->pdev.size() * sizeof(PatchDev)},
+      {"ROWRUN", c->rowrun.data(), c->rowrun.size() * sizeof(int2)},
+      {"COLRUN", c->colrun.data(), c->colrun.size() * sizeof(int2)},
+      {"COPY", c->copy_pairs.data(), c->copy_pairs.size() * 8},
+      {"IDST", c->idst.data(), c->idst.size() * 8},
+      {"IPTR", c->iptr.data(), c->iptr.size() * 4},
+      {"ICOL", c->icol.data(), c->icol.size() * 8},
+      {"IVAL", c->ival.data(), c->ival.size() * 8},
+      {"BDST", c->bdst.data(), c->bdst.size() * 8},
+      {"BPTR", c->bptr.data(), c->bptr.size() * 4},
+      {"BCOL", c->bcol.data(), c->bcol.size() * 8},
+      {"BVAL", c->bval.data(), c->bval.size() * 8},
+      {"SLIP", c->slip.data(), c->slip.size() * sizeof(SlipEntry)},
+      {"DIRI", c->dirich.data(), c->dirich.size() * sizeof(DirichletEntry)},
+      {"EXACT", c->exact.data(), c->exact.size() * sizeof(ExactEntry)},
+      {"SDNN", c->sdnn.data(), c->sdnn.size() * 4},
+      {"BASIS", c->basis.data(), c->basis.size() * 8},
+      {"WDIL", c->wdil.data(), c->wdil.size() * 8},
+  };
+  for (auto& u : ups)
+    if ((st = upload(c, u.n, u.p, u.b)) != FCS_OK) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto& v : staging_tasks)
+    for (auto& w : v) std::vector<GemmTask>().swap(w);
+  c->bound = true;
+  c->cur = c->arr[A_U0];
+  double zero = c->t_host;
+  HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &zero, 8, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FCS_OK;
+}
+
+namespace {
+
+fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed) {
+  if (c->phase_tiles[ph].empty()) return FCS_OK;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (timed && c->prof && c->ev_used + 2 <= c->ev.size()) {
+    e0 = c->ev[c->ev_used++];
+    e1 = c->ev[c->ev_used++];
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+  }
+  HIPCHK(c, launch_gemm(precision, c->d_tasks[ph][variant], c->d_tiles[ph],
+                        static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->stream));
+  if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
+  return FCS_OK;
+}
+
+// Alg. 3 + blend + gradient of mu, filter (Alg. 4), adaptive step.
+fcs_status per_step(fcs_ctx* c) {
+  const int64_t P = c->P;
+  const fcs_params& p = c->prm;
+  double* U0 = c->arr[A_U0];
+  double* scal = c->dptr<double>("SCAL");
+  fcs_status st;
+  if (c->visc) {
+    ViscArgs v{};
+    v.P = P;
+    v.U = U0;
+    v.flags = c->dptr<uint8_t>("FLAGS");
+    v.pid = c->dptr<int32_t>("PID");
+    v.patches = c->dptr<PatchDev>("PATCH");
+    v.rowrun = c->dptr<int2>("ROWRUN");
+    v.colrun = c->dptr<int2>("COLRUN");
+    v.phi = c->dptr<double>("PHI");
+    v.spd = c->dptr<double>("SPD");
+    v.hx = c->dptr<double>("MET9");
+    v.tau = c->dptr<uint8_t>("TAU");
+    v.muhat = c->dptr<double>("MUHAT");
+    v.tmp = c->dptr<double>("TMP");
+    v.mut = c->dptr<double>("MUT");
+    v.mu = c->arr[A_MU];
+    v.mode = p.av_mode;
+    v.weights = c->dptr<float>("SDNN");
+    v.basis = c->dptr<double>("BASIS");
+    v.c_mu = p.c_mu;
+    v.gamma = p.gamma;
+    v.nv = p.n_v;
+    v.wdil = c->dptr<double>("WDIL");
+    v.nblend = static_cast<int>(c->bdst.size());
+    v.bdst = c->dptr<int64_t>("BDST");
+    v.bptr = c->dptr<int32_t>("BPTR");
+    v.bcol = c->dptr<int64_t>("BCOL");
+    v.bval = c->dptr<double>("BVAL");
+    HIPCHK(c, launch_viscosity(v, c->stream));
+    if ((st = run_gemm(c, PH_MUGRAD, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
+  }
+  if (p.filter && c->steps > 0) {
+    HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], c->dptr<uint8_t>("FLAGS"), P, p.gamma, c->stream));
+    if ((st = run_gemm(c, PH_FILT1, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
+    if ((st = run_gemm(c, PH_FILT2, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
+    HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, c->stream));
+  }
+  HIPCHK(c, launch_dt(U0, c->dptr<uint8_t>("FLAGS"), c->dptr<double>("MET9"), c->visc ? c->arr[A_MU] : nullptr,
+                      c->dptr<double>("DTPART"), c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, scal + 1, c->stream));
+  return FCS_OK;
+}
+
+fcs_status one_stage(fcs_ctx* c, int s) {
+  const int64_t P = c->P;
+  const fcs_params& p = c->prm;
+  static const int in_buf[5] = {A_U0, A_UA, A_UB, A_UA, A_UB};
+  static const int out_buf[5] = {A_UA, A_UB, A_UA, A_UB, A_U0};
+  double* in = c->arr[in_buf[s]];
+  double* outp = c->arr[out_buf[s]];
+  const int variant = in_buf[s] - A_U0;
+  const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
+  const double* met[10];
+  for (int m = 0; m < 10; ++m) met[m] = c->dptr<double>(("MET" + std::to_string(m)).c_str());
+  HIPCHK(c, launch_flux(in, c->arr[A_F], flags, met[0], met[1], met[2], met[3], P, p.gamma - 1.0, c->stream));
+  fcs_status st;
+  if ((st = run_gemm(c, PH_EULER, variant, p.precision, true)) != FCS_OK) return st;
+  if (c->visc && c->cross)
+    if ((st = run_gemm(c, PH_CROSS, 0, p.precision, false)) != FCS_OK) return st;
+  StageArgs a{};
+  a.P = P;
+  a.stage = s;
+  switch (s) {
+    case 0: a.c[0] = kA0; break;
+    case 1: a.c[1] = kB20; a.c[2] = kB21; a.c[3] = kA1; break;
+    case 2: a.c[1] = kB30; a.c[2] = kB32; a.c[3] = kA2; a.c[4] = kC2; break;
+    case 3: a.c[1] = kB40; a.c[2] = kB43; a.c[3] = kA3; a.c[4] = kC3; a.c[5] = kD3; break;
+    default: a.c[4] = kC4; a.c[5] = kD4; break;
+  }
+  a.gm1 = p.gamma - 1.0;
+  a.flags = flags;
+  a.in = in;
+  a.U0 = c->arr[A_U0];
+  a.out = outp;
+  a.acc = c->dptr<double>("ACC");
+  a.DF1 = c->arr[A_DF1];
+  a.DF2 = c->arr[A_DF2];
+  a.t1x = met[0];
+  a.t1y = met[1];
+  a.t2x = met[2];
+  a.t2y = met[3];
+  a.visc = c->visc;
+  if (c->visc) {
+    a.mu = c->arr[A_MU];
+    a.mu1 = c->arr[A_MU1];
+    a.mu2 = c->arr[A_MU2];
+    a.g11 = met[4];
+    a.g12 = met[5];
+    a.g22 = met[6];
+    a.lap1 = met[7];
+    a.lap2 = met[8];
+    a.W1 = c->arr[A_W1];
+    a.W2 = c->arr[A_W2];
+    a.W11 = c->arr[A_W11];
+    a.W22 = c->arr[A_W22];
+    a.W12 = c->cross ? c->arr[A_W12] : nullptr;
+  }
+  double* scal = c->dptr<double>("SCAL");
+  a.dt = scal + 1;
+  a.bad_flag = reinterpret_cast<int*>(scal + 3);
+  HIPCHK(c, launch_stage(a, c->stream));
+  double frac[5];
+  stage_fractions(frac);
+  VortexArgs vx{p.vortex[0], p.vortex[1], p.vortex[2], p.vortex[3], p.vortex[4]};
+  HIPCHK(c, launch_bc(outp, c->dptr<SlipEntry>("SLIP"), static_cast<int>(c->slip.size()),
+                      c->dptr<DirichletEntry>("DIRI"), static_cast<int>(c->dirich.size()),
+                      c->dptr<ExactEntry>("EXACT"), static_cast<int>(c->exact.size()), P, p.gamma, scal, scal + 1,
+                      frac[s], vx, c->stream));
+  HIPCHK(c, launch_fringe(outp, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
+                          c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
+                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), P, c->stream));
+  if (s == 4) HIPCHK(c, launch_time_advance(scal, scal + 1, scal + 2, c->stream));
+  c->cur = outp;
+  return FCS_OK;
+}
+
+fcs_status full_step_eager(fcs_ctx* c) {
+  fcs_status st;
+  if ((st = per_step(c)) != FCS_OK) return st;
+  for (int s = 0; s < 5; ++s)
+    if ((st = one_stage(c, s)) != FCS_OK) return st;
+  return FCS_OK;
+}
+
+fcs_status check_bad(fcs_ctx* c) {
+  int bad = 0;
+  HIPCHK(c, hipMemcpyAsync(&bad, c->dptr<double>("SCAL") + 3, 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (bad) return c->fail(FCS_ENONFINITE, "non-finite or non-physical state (rho <= 0 or p <= 0)");
+  return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, const double* src,
+                                    int32_t src_on_device) {
+  if (!c || !src) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_set_state before fcs_bind");
+  if (patch < 0 || patch >= static_cast<int32_t>(c->grids.size())) return c->fail(FCS_EINVAL, "bad patch index");
+  const Grid& g = c->grids[patch];
+  const size_t np = g.np();
+  std::vector<double> h(4 * np);
+  if (src_on_device) {
+    HIPCHK(c, hipMemcpyAsync(h.data(), src, 4 * np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::copy(src, src + 4 * np, h.begin());
+  }
+  const double gm = c->prm.gamma;
+  std::vector<double> e(4 * np, 0.0);
+  for (size_t k = 0; k < np; ++k) {
+    if (!g.mask[k]) continue;
+    if (vars == FCS_VARS_PRIM) {
+      double r = h[k], u = h[np + k], v = h[2 * np + k], pr = h[3 * np + k];
+      e[k] = r;
+      e[np + k] = r * u;
+      e[2 * np + k] = r * v;
+      e[3 * np + k] = pr / (gm - 1.0) + 0.5 * r * (u * u + v * v);
+    } else {
+      for (int q = 0; q < 4; ++q) e[q * np + k] = h[q * np + k];
+    }
+  }
+  // the state lives in U0 at step boundaries; a partial step is dropped
+  if (c->stage_in_step != 0) {
+    HIPCHK(c, hipMemcpyAsync(c->arr[A_U0], c->cur, 4 * c->P * 8, hipMemcpyDeviceToDevice, c->stream));
+    c->stage_in_step = 0;
+  }
+  for (int q = 0; q < 4; ++q)
+    HIPCHK(c, hipMemcpyAsync(c->arr[A_U0] + q * c->P + g.offset, e.data() + q * np, np * 8, hipMemcpyHostToDevice,
+                             c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->cur = c->arr[A_U0];
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_set_time(fcs_ctx* c, double t) {
+  if (!c) return FCS_EINVAL;
+  c->t_host = t;
+  if (c->bound) {
+    HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_set_tau(fcs_ctx* c, int32_t patch, const uint8_t* tau) {
+  if (!c || !tau) return FCS_EINVAL;
+  if (!c->bound || !c->visc) return c->fail(FCS_ESTATE, "fcs_set_tau needs a bound context with viscosity");
+  if (patch < 0 || patch >= static_cast<int32_t>(c->grids.size())) return c->fail(FCS_EINVAL, "bad patch index");
+  const Grid& g = c->grids[patch];
+  for (int dir = 0; dir < 2; ++dir) {
+    for (size_t k = 0; k < g.np(); ++k) {
+      if (tau[dir * g.np() + k] > 2) return c->fail(FCS_EINVAL, "tau values must be 0, 1 or 2");
+    }
+    HIPCHK(c, hipMemcpyAsync(c->dptr<uint8_t>("TAU") + dir * c->P + g.offset, tau + dir * g.np(), g.np(),
+                             hipMemcpyHostToDevice, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FCS_OK;
+}
+
+namespace {
+
+fcs_status capture_step(fcs_ctx* c, int with_filter) {
+  if (c->gexec[with_filter]) return FCS_OK;
+  hipGraph_t graph;
+  int64_t saved = c->steps;
+  c->steps = with_filter ? 1 : 0;
+  bool saved_prof = c->prof;
+  c->prof = false;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  fcs_status st = full_step_eager(c);
+  hipError_t e = hipStreamEndCapture(c->stream, &graph);
+  c->steps = saved;
+  c->prof = saved_prof;
+  if (st != FCS_OK) return st;
+  if (e != hipSuccess) return c->fail(FCS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  e = hipGraphInstantiate(&c->gexec[with_filter], graph, nullptr, nullptr, 0);
+  hipGraphDestroy(graph);
+  if (e != hipSuccess) return c->fail(FCS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
+  return FCS_OK;
+}
+
+}  // namespace
+
+extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
+  if (!c) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_advance before fcs_bind");
+  if (n_stages < 0) return c->fail(FCS_EINVAL, "negative stage count");
+  fcs_status st;
+  const bool graph = c->prm.use_graph && c->stream != nullptr && !c->prof;
+  while (n_stages > 0) {
+    if (c->stage_in_step == 0 && n_stages >= 5) {
+      int wf = (c->prm.filter && c->steps > 0) ? 1 : 0;
+      if (graph) {
+        if ((st = capture_step(c, wf)) != FCS_OK) return st;
+        HIPCHK(c, hipGraphLaunch(c->gexec[wf], c->stream));
+        c->cur = c->arr[A_U0];
+      } else {
+        if ((st = full_step_eager(c)) != FCS_OK) return st;
+      }
+      c->steps++;
+      c->stages += 5;
+      n_stages -= 5;
+      continue;
+    }
+    if (c->stage_in_step == 0)
+      if ((st = per_step(c)) != FCS_OK) return st;
+    if ((st = one_stage(c, c->stage_in_step)) != FCS_OK) return st;
+    c->stages++;
+    n_stages--;
+    if (++c->stage_in_step == 5) {
+      c->stage_in_step = 0;
+      c->steps++;
+    }
+  }
+  if (t_out) {
+    if ((st = check_bad(c)) != FCS_OK) return st;
+    HIPCHK(c, hipMemcpyAsync(&c->t_host, c->dptr<double>("SCAL"), 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *t_out = c->t_host;
+  }
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_get_field(fcs_ctx* c, int32_t patch, int32_t field, double* dst, int32_t dst_on_device) {
+  if (!c || !dst) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_get_field before fcs_bind");
+  if (patch < 0 || patch >= static_cast<int32_t>(c->grids.size())) return c->fail(FCS_EINVAL, "bad patch index");
+  if (field < 0 || field > FCS_FIELD_MUHAT) return c->fail(FCS_EINVAL, "bad field");
+  if (!c->visc && field >= FCS_FIELD_MU) return c->fail(FCS_EINVAL, "viscosity fields need av_mode != OFF");
+  const Grid& g = c->grids[patch];
+  const size_t np = g.np();
+  std::vector<double> h(np, 0.0);
+  if (field <= FCS_FIELD_MACH) {
+    std::vector<double> e(4 * np);
+    for (int q = 0; q < 4; ++q)
+      HIPCHK(c, hipMemcpyAsync(e.data() + q * np, c->cur + q * c->P + g.offset, np * 8, hipMemcpyDeviceToHost,
+                               c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const double gm = c->prm.gamma;
+    for (size_t k = 0; k < np; ++k) {
+      if (field <= FCS_FIELD_E) {
+        h[k] = e[field * np + k];
+      } else if (g.mask[k]) {
+        double r = e[k], mx = e[np + k], my = e[2 * np + k], E = e[3 * np + k];
+        double pr = (gm - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+        h[k] = field == FCS_FIELD_P ? pr : std::sqrt(mx * mx + my * my) / r * std::sqrt(r / (gm * pr));
+      }
+    }
+  } else if (field == FCS_FIELD_TAU0 || field == FCS_FIELD_TAU1) {
+    std::vector<uint8_t> t(np);
+    HIPCHK(c, hipMemcpyAsync(t.data(), c->dptr<uint8_t>("TAU") + (field - FCS_FIELD_TAU0) * c->P + g.offset, np,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (size_t k = 0; k < np; ++k) h[k] = t[k];
+  } else {
+    const double* src = field == FCS_FIELD_MU ? c->arr[A_MU] : c->dptr<double>("MUHAT");
+    HIPCHK(c, hipMemcpyAsync(h.data(), src + g.offset, np * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  if (dst_on_device) {
+    HIPCHK(c, hipMemcpyAsync(dst, h.data(), np * 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  } else {
+    std::copy(h.begin(), h.end(), dst);
+  }
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_stats(fcs_ctx* c, fcs_stats_t* out) {
+  if (!c || !out) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_stats before fcs_bind");
+  double scal[3];
+  std::vector<double> e(4 * c->P);
+  HIPCHK(c, hipMemcpyAsync(scal, c->dptr<double>("SCAL"), 24, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(e.data(), c->cur, 4 * c->P * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  out->steps = c->steps;
+  out->stages = c->stages;
+  out->t = scal[0];
+  out->dt = scal[2];
+  out->mass = out->energy = 0;
+  for (int64_t k = 0; k < c->P; ++k)
+    if (c->flags[k] & kActive) {
+      out->mass += e[k];
+      out->energy += e[3 * c->P + k];
+    }
+  out->npoints = c->nactive;
+  return check_bad(c);
+}
+
+extern "C" fcs_status fcs_profile_enable(fcs_ctx* c, int32_t on) {
+  if (!c) return FCS_EINVAL;
+  if (on && c->ev.empty()) {
+    c->ev.resize(8192);
+    for (auto& e : c->ev) HIPCHK(c, hipEventCreate(&e));
+  }
+  c->prof = on != 0;
+  c->ev_used = 0;
+  c->prof_ms = 0;
+  c->prof_n = 0;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops, double* bytes, int64_t* launches) {
+  if (!c) return FCS_EINVAL;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev[q], c->ev[q + 1]));
+    c->prof_ms += ms;
+    c->prof_n++;
+  }
+  c->ev_used = 0;
+  if (avg_ms) *avg_ms = c->prof_n ? c->prof_ms / c->prof_n : 0.0;
+  if (flops) *flops = exact_flops(c->phase_tasks[PH_EULER]);
+  if (bytes) {
+    // algorithmic bytes: each operand line read once, each output written once (FP64)
+    double b = 0;
+    for (const auto& t : c->phase_tasks[PH_EULER]) b += 2.0 * 8.0 * t.n * static_cast<double>(t.nrow) * t.ncomp;
+    *bytes = b;
+  }
+  if (launches) *launches = c->prof_n;
+  return FCS_OK;
+}
+
+extern "C" void fcs_destroy(fcs_ctx* c) {
+  if (!c) return;
+  for (auto& g : c->gexec)
+    if (g) hipGraphExecDestroy(g);
+  for (auto& e : c->ev) hipEventDestroy(e);
+  delete c;
+}

@@ -1,0 +1,394 @@
+// C ABI: FC operators on the host, the batched derivative sweep, standalone
+// window classification and line-wise operator application.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fcsdnn.h"
+#include "fc_builder.h"
+#include "gemm.h"
+#include "kernels.h"
+#include "sdnn_train.h"
+#include "window_kernels.h"
+
+using namespace fcs;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+uint16_t to_bf16(float f) {
+  uint32_t u;
+  std::memcpy(&u, &f, 4);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+float from_bf16(uint16_t h) {
+  uint32_t u = static_cast<uint32_t>(h) << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return f;
+}
+
+// Device operator tables for a set of (n, kind) operators in one precision.
+struct OpSet {
+  std::vector<int> n;
+  std::vector<int64_t> off, roff;
+  int64_t elems = 0, rows = 0;
+  int index(int len) {
+    for (size_t q = 0; q < n.size(); ++q)
+      if (n[q] == len) return static_cast<int>(q);
+    n.push_back(len);
+    off.push_back(elems);
+    roff.push_back(rows);
+    elems += static_cast<int64_t>(len) * len;
+    rows += len;
+    return static_cast<int>(n.size()) - 1;
+  }
+};
+
+}  // namespace
+
+extern "C" fcs_status fcs_fc_continuation(int32_t d, int32_t C, double* Q, double* A) {
+  if (!Q || !A) return FCS_EINVAL;
+  return fc_continuation(d, C, Q, A) ? FCS_OK : FCS_EINVAL;
+}
+
+extern "C" fcs_status fcs_fc_operator(int32_t n, int32_t d, int32_t C, int32_t kind, double* out) {
+  if (!out || d < 1 || d > 12 || C < 4 || C > 64) return FCS_EINVAL;
+  const std::vector<double>* op = fc_operator(n, d, C, kind);
+  if (!op) return FCS_EINVAL;
+  std::copy(op->begin(), op->end(), out);
+  return FCS_OK;
+}
+
+// ------------------------------------------------------------------ sweep
+struct fcs_sweep {
+  int npatch = 0, ncomp = 0, precision = 0, d = 0, C = 0;
+  std::vector<int32_t> n1, n2;
+  std::vector<int64_t> poff;  // element offset of each patch (ncomp * n1 * n2 per patch)
+  int64_t total = 0, npoints = 0;
+  OpSet ops;
+  std::vector<GemmTask> tasks;
+  std::vector<GemmTile> tiles;
+  char* ws = nullptr;
+  size_t need = 0;
+  size_t o_off = 0, o_roff = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
+  hipStream_t stream = nullptr;
+  const double* last_in = nullptr;
+  double *last_d1 = nullptr, *last_d2 = nullptr;
+  OpTables tab{};
+  bool prof = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  double ms = 0;
+  int64_t launches = 0;
+};
+
+extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int32_t ncomp, int32_t precision,
+                                       int32_t d, int32_t C, fcs_sweep** out) {
+  if (!out || !n1n2 || npatch <= 0 || ncomp <= 0 || ncomp > 64 || precision < 0 || precision > 2) return FCS_EINVAL;
+  if (d < 1 || d > 12 || C < 4 || C > 64) return FCS_EINVAL;
+  std::unique_ptr<fcs_sweep> s(new (std::nothrow) fcs_sweep());
+  if (!s) return FCS_ENOMEM;
+  s->npatch = npatch;
+  s->ncomp = ncomp;
+  s->precision = precision;
+  s->d = d;
+  s->C = C;
+  for (int p = 0; p < npatch; ++p) {
+    int a = n1n2[2 * p], b = n1n2[2 * p + 1];
+    if (a < 2 * d || b < 2 * d || a > 1024 || b > 1024) return FCS_EINVAL;
+    s->n1.push_back(a);
+    s->n2.push_back(b);
+    s->poff.push_back(s->total);
+    s->total += static_cast<int64_t>(ncomp) * a * b;
+    s->npoints += static_cast<int64_t>(a) * b;
+    s->ops.index(a);
+    s->ops.index(b);
+  }
+  // tasks: per patch, q^1 (all rows of all components) and q^2; the
+  // component stride is one (n2, n1) block
+  for (int p = 0; p < npatch; ++p) {
+    int a = s->n1[p], b = s->n2[p];
+    GemmTask t{};
+    t.comp_stride = static_cast<int64_t>(a) * b;
+    t.ncomp = ncomp;
+    // q^1 lines: row r of component c
+    t.row_stride = a;
+    t.s_stride = 1;
+    t.nrow = b;
+    t.n = a;
+    t.op = s->ops.index(a);
+    t.src = reinterpret_cast<const double*>(static_cast<intptr_t>(s->poff[p]));  // offsets; rebased at run
+    t.dst = reinterpret_cast<double*>(static_cast<intptr_t>(s->poff[p]));
+    s->tasks.push_back(t);
+    t.row_stride = 1;
+    t.s_stride = a;
+    t.nrow = a;
+    t.n = b;
+    t.op = s->ops.index(b);
+    s->tasks.push_back(t);
+  }
+  for (size_t q = 0; q < s->tasks.size(); ++q) {
+    int nl = s->tasks[q].nrow * s->tasks[q].ncomp;
+    for (int t0 = 0; t0 < s->tasks[q].n; t0 += 64)
+      for (int l0 = 0; l0 < nl; l0 += 64) s->tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
+  }
+  size_t u = 0;
+  auto take = [&](size_t b) {
+    size_t o = u;
+    u = align_up(u + std::max<size_t>(b, 1));
+    return o;
+  };
+  s->o_off = take(s->ops.off.size() * 8);
+  s->o_roff = take(s->ops.roff.size() * 8);
+  s->o_f64 = take(s->ops.elems * 8);
+  s->o_row = take(s->ops.rows * 8);
+  s->o_f32 = take(precision == 1 ? s->ops.elems * 4 : 0);
+  s->o_bhi = take(precision == 2 ? s->ops.elems * 2 : 0);
+  s->o_blo = take(precision == 2 ? s->ops.elems * 2 : 0);
+  s->o_task = take(s->tasks.size() * sizeof(GemmTask));
+  s->o_tile = take(s->tiles.size() * sizeof(GemmTile));
+  s->need = u;
+  *out = s.release();
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sweep_workspace_size(const fcs_sweep* s, size_t* bytes) {
+  if (!s || !bytes) return FCS_EINVAL;
+  *bytes = s->need;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sweep_points(const fcs_sweep* s, int64_t* npoints) {
+  if (!s || !npoints) return FCS_EINVAL;
+  *npoints = s->npoints;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes, void* stream) {
+  if (!s || !workspace || bytes < s->need || reinterpret_cast<uintptr_t>(workspace) % kAlign) return FCS_EINVAL;
+  s->ws = static_cast<char*>(workspace);
+  s->stream = static_cast<hipStream_t>(stream);
+  std::vector<double> f64(s->ops.elems), rows(s->ops.rows);
+  for (size_t q = 0; q < s->ops.n.size(); ++q) {
+    const std::vector<double>* op = fc_operator(s->ops.n[q], s->d, s->C, FCS_OP_D1);
+    if (!op) return FCS_EINVAL;
+    std::copy(op->begin(), op->end(), f64.begin() + s->ops.off[q]);
+    int n = s->ops.n[q];
+    for (int t = 0; t < n; ++t) {
+      double r = 0;
+      for (int k = 0; k < n; ++k) r += (*op)[static_cast<size_t>(t) * n + k];
+      rows[s->ops.roff[q] + t] = r;
+    }
+  }
+  std::vector<float> f32;
+  std::vector<uint16_t> bhi, blo;
+  hipStream_t st = s->stream;
+  if (hipMemcpyAsync(s->ws + s->o_off, s->ops.off.data(), s->ops.off.size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s->ws + s->o_roff, s->ops.roff.data(), s->ops.roff.size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s->ws + s->o_f64, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s->ws + s->o_row, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, st))
+    return FCS_EHIP;
+  if (s->precision == 1) {
+    f32.resize(f64.size());
+    for (size_t q = 0; q < f64.size(); ++q) f32[q] = static_cast<float>(f64[q]);
+    if (hipMemcpyAsync(s->ws + s->o_f32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, st)) return FCS_EHIP;
+  }
+  if (s->precision == 2) {
+    bhi.resize(f64.size());
+    blo.resize(f64.size());
+    for (size_t q = 0; q < f64.size(); ++q) {
+      float f = static_cast<float>(f64[q]);
+      bhi[q] = to_bf16(f);
+      blo[q] = to_bf16(f - from_bf16(bhi[q]));
+    }
+    if (hipMemcpyAsync(s->ws + s->o_bhi, bhi.data(), bhi.size() * 2, hipMemcpyHostToDevice, st) ||
+        hipMemcpyAsync(s->ws + s->o_blo, blo.data(), blo.size() * 2, hipMemcpyHostToDevice, st))
+      return FCS_EHIP;
+  }
+  if (hipMemcpyAsync(s->ws + s->o_tile, s->tiles.data(), s->tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice,
+                     st))
+    return FCS_EHIP;
+  if (hipStreamSynchronize(st)) return FCS_EHIP;
+  s->tab.off = reinterpret_cast<const int64_t*>(s->ws + s->o_off);
+  s->tab.roff = reinterpret_cast<const int64_t*>(s->ws + s->o_roff);
+  s->tab.f64 = reinterpret_cast<const double*>(s->ws + s->o_f64);
+  s->tab.rowsum = reinterpret_cast<const double*>(s->ws + s->o_row);
+  s->tab.f32 = reinterpret_cast<const float*>(s->ws + s->o_f32);
+  s->tab.bhi = reinterpret_cast<const uint16_t*>(s->ws + s->o_bhi);
+  s->tab.blo = reinterpret_cast<const uint16_t*>(s->ws + s->o_blo);
+  s->last_in = nullptr;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sweep_run(fcs_sweep* s, const double* in, double* d1, double* d2) {
+  if (!s || !in || !d1 || !d2 || !s->ws) return FCS_EINVAL;
+  if (in != s->last_in || d1 != s->last_d1 || d2 != s->last_d2) {
+    std::vector<GemmTask> t = s->tasks;
+    for (size_t q = 0; q < t.size(); ++q) {
+      int64_t o = static_cast<int64_t>(reinterpret_cast<intptr_t>(s->tasks[q].src));
+      t[q].src = in + o;
+      t[q].dst = (q % 2 == 0 ? d1 : d2) + o;
+    }
+    if (hipMemcpyAsync(s->ws + s->o_task, t.data(), t.size() * sizeof(GemmTask), hipMemcpyHostToDevice, s->stream) ||
+        hipStreamSynchronize(s->stream))
+      return FCS_EHIP;
+    s->last_in = in;
+    s->last_d1 = d1;
+    s->last_d2 = d2;
+  }
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (s->prof && s->ev_used + 2 <= s->ev.size()) {
+    e0 = s->ev[s->ev_used++];
+    e1 = s->ev[s->ev_used++];
+    if (hipEventRecord(e0, s->stream)) return FCS_EHIP;
+  }
+  if (launch_gemm(s->precision, reinterpret_cast<const GemmTask*>(s->ws + s->o_task),
+                  reinterpret_cast<const GemmTile*>(s->ws + s->o_tile), static_cast<int>(s->tiles.size()), s->tab,
+                  s->stream) != hipSuccess)
+    return FCS_EHIP;
+  if (e1 && hipEventRecord(e1, s->stream)) return FCS_EHIP;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_sweep_profile(fcs_sweep* s, int32_t on, double* avg_ms, double* flops, double* bytes,
+                                        int64_t* launches) {
+  if (!s) return FCS_EINVAL;
+  if (hipStreamSynchronize(s->stream)) return FCS_EHIP;
+  for (size_t q = 0; q + 1 < s->ev_used; q += 2) {
+    float ms = 0;
+    if (hipEventElapsedTime(&ms, s->ev[q], s->ev[q + 1])) return FCS_EHIP;
+    s->ms += ms;
+    s->launches++;
+  }
+  s->ev_used = 0;
+  if (avg_ms) *avg_ms = s->launches ? s->ms / s->launches : 0.0;
+  if (launches) *launches = s->launches;
+  double f = 0, b = 0;
+  for (const auto& t : s->tasks) {
+    f += 2.0 * t.n * t.n * static_cast<double>(t.nrow) * t.ncomp;
+    b += 2.0 * 8.0 * t.n * static_cast<double>(t.nrow) * t.ncomp;
+  }
+  if (flops) *flops = f;
+  if (bytes) *bytes = b;
+  if (on >= 0) {
+    if (on && s->ev.empty()) {
+      s->ev.resize(4096);
+      for (auto& e : s->ev)
+        if (hipEventCreate(&e)) return FCS_EHIP;
+    }
+    if (on != static_cast<int>(s->prof) || on) {
+      s->ms = 0;
+      s->launches = 0;
+    }
+    s->prof = on != 0;
+  }
+  return FCS_OK;
+}
+
+extern "C" void fcs_sweep_destroy(fcs_sweep* s) {
+  if (!s) return;
+  for (auto& e : s->ev) hipEventDestroy(e);
+  delete s;
+}
+
+// ------------------------------------------------------------------ classification
+extern "C" fcs_status fcs_sdnn_infer(const float* params, const double* windows, int64_t nwin, uint8_t* tau,
+                                     float* logits, void* stream) {
+  if (!params || (!windows && nwin) || (!tau && nwin) || nwin < 0) return FCS_EINVAL;
+  ModalBasis b{};
+  return launch_classify_windows(2, params, b, windows, nwin, tau, logits, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? FCS_OK
+             : FCS_EHIP;
+}
+
+extern "C" fcs_status fcs_modal_infer(const double* windows, int64_t nwin, uint8_t* tau, void* stream) {
+  if ((!windows && nwin) || (!tau && nwin) || nwin < 0) return FCS_EINVAL;
+  static ModalBasis b;
+  static bool init = false;
+  if (!init) {
+    modal_basis16(b.v);
+    init = true;
+  }
+  return launch_classify_windows(1, nullptr, b, windows, nwin, tau, nullptr, static_cast<hipStream_t>(stream)) ==
+                 hipSuccess
+             ? FCS_OK
+             : FCS_EHIP;
+}
+
+// ------------------------------------------------------------------ training
+extern "C" size_t fcs_sdnn_train_workspace(int32_t batch) {
+  if (batch <= 0) return 0;
+  return sdnn_train_floats(batch) * sizeof(float);
+}
+
+extern "C" fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int32_t t, float lr, const float* x,
+                                          const int32_t* labels, const float* class_weight, int32_t batch,
+                                          float* loss, float* grads, int32_t flags, void* workspace, size_t bytes,
+                                          void* stream) {
+  if (!params || !m || !v || !x || !labels || !class_weight || !loss || !workspace || batch <= 0 || t < 1 ||
+      batch > (1 << 22))
+    return FCS_EINVAL;
+  if (bytes < fcs_sdnn_train_workspace(batch)) return FCS_ENOMEM;
+  return launch_sdnn_train(params, m, v, t, lr, x, labels, class_weight, batch, loss, grads,
+                           static_cast<float*>(workspace), flags & 1, static_cast<hipStream_t>(stream)) == hipSuccess
+             ? FCS_OK
+             : FCS_EHIP;
+}
+
+// ------------------------------------------------------------------ lines
+extern "C" size_t fcs_lines_workspace(int32_t n, int64_t nlines) {
+  if (n <= 0 || nlines <= 0) return 0;
+  int64_t ntiles = ((nlines + 63) / 64) * ((n + 63) / 64);
+  return align_up(static_cast<size_t>(n) * n * 8) + align_up(64) + align_up(sizeof(GemmTask)) +
+         align_up(static_cast<size_t>(ntiles) * sizeof(GemmTile));
+}
+
+extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, int32_t d, int32_t C,
+                                      const double* in, double* out, void* workspace, size_t bytes, void* stream) {
+  if (!in || !out || !workspace || nlines <= 0 || nlines > (1ll << 31) / 1024) return FCS_EINVAL;
+  if (bytes < fcs_lines_workspace(n, nlines) || reinterpret_cast<uintptr_t>(workspace) % kAlign) return FCS_EINVAL;
+  const std::vector<double>* op = fc_operator(n, d, C, kind);
+  if (!op) return FCS_EINVAL;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* ws = static_cast<char*>(workspace);
+  size_t o_op = 0, o_off = align_up(static_cast<size_t>(n) * n * 8), o_task = o_off + align_up(64),
+         o_tile = o_task + align_up(sizeof(GemmTask));
+  int64_t zero[2] = {0, 0};
+  GemmTask t{};
+  t.src = in;
+  t.dst = out;
+  t.comp_stride = static_cast<int64_t>(nlines) * n;
+  t.row_stride = n;
+  t.s_stride = 1;
+  t.nrow = static_cast<int32_t>(nlines);
+  t.ncomp = 1;
+  t.n = n;
+  t.op = 0;
+  std::vector<GemmTile> tiles;
+  for (int t0 = 0; t0 < n; t0 += 64)
+    for (int64_t l0 = 0; l0 < nlines; l0 += 64) tiles.push_back({0, static_cast<int32_t>(l0), t0, 0});
+  if (hipMemcpyAsync(ws + o_op, op->data(), op->size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(ws + o_off, zero, 16, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(ws + o_task, &t, sizeof(t), hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(ws + o_tile, tiles.data(), tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice, st))
+    return FCS_EHIP;
+  OpTables tab{};
+  tab.off = reinterpret_cast<const int64_t*>(ws + o_off);
+  tab.roff = reinterpret_cast<const int64_t*>(ws + o_off);
+  tab.f64 = reinterpret_cast<const double*>(ws + o_op);
+  if (launch_gemm(0, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
+                  static_cast<int>(tiles.size()), tab, st) != hipSuccess)
+    return FCS_EHIP;
+  // the host staging vectors must outlive the copies
+  return hipStreamSynchronize(st) == hipSuccess ? FCS_OK : FCS_EHIP;
+}

@@ -1,0 +1,85 @@
+// Launch interface of the elementwise / stencil / gather kernels.
+#pragma once
+#include "kernels.h"
+
+namespace fcs {
+
+constexpr int FCS_SDNN_NPARAM_DEV = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
+
+struct VortexArgs {
+  double beta, x0, y0, u0, v0;
+};
+
+struct StageArgs {
+  int64_t P;
+  int stage;
+  double c[6];  // Shu-Osher coefficients of this stage (see ssprk table)
+  double gm1;
+  const uint8_t* flags;
+  const double *in, *U0;
+  double *out, *acc;
+  const double *DF1, *DF2;
+  const double *t1x, *t1y, *t2x, *t2y;
+  int visc;
+  const double *mu, *mu1, *mu2, *g11, *g12, *g22, *lap1, *lap2;
+  const double *W1, *W2, *W11, *W22, *W12;
+  const double* dt;
+  int* bad_flag;
+};
+
+struct ClassifyArgs {
+  int64_t P;
+  const uint8_t* flags;
+  const int32_t* pid;
+  const PatchDev* patches;
+  const int2 *rowrun, *colrun;
+  const double *phi, *spd, *hx;
+  uint8_t* tau;
+  double* muhat;
+  int mode;  // 1 modal, 2 sdnn, 3 frozen
+  const float* weights;
+  const double* basis;
+  double c_mu;
+};
+
+struct ViscArgs {
+  int64_t P;
+  const double* U;
+  const uint8_t* flags;
+  const int32_t* pid;
+  const PatchDev* patches;
+  const int2 *rowrun, *colrun;
+  double *phi, *spd;
+  const double* hx;
+  uint8_t* tau;
+  double *muhat, *tmp, *mut, *mu;
+  int mode;
+  const float* weights;
+  const double* basis;
+  double c_mu, gamma;
+  int nv;
+  const double* wdil;
+  int nblend;
+  const int64_t* bdst;
+  const int32_t* bptr;
+  const int64_t* bcol;
+  const double* bval;
+};
+
+hipError_t launch_flux(const double* U, double* F, const uint8_t* flags, const double* t1x, const double* t1y,
+                       const double* t2x, const double* t2y, int64_t P, double gm1, hipStream_t s);
+hipError_t launch_stage(const StageArgs& a, hipStream_t s);
+hipError_t launch_bc(double* U, const SlipEntry* slip, int nslip, const DirichletEntry* dir, int ndir,
+                     const ExactEntry* ex, int nex, int64_t P, double gamma, const double* t, const double* dt,
+                     double frac, const VortexArgs& v, hipStream_t s);
+hipError_t launch_fringe(double* U, const int64_t* copy_pairs, int ncopy, const int64_t* idst, const int32_t* iptr,
+                         const int64_t* icol, const double* ival, int ninterp, int64_t P, hipStream_t s);
+hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
+hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
+                             hipStream_t s);
+hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, hipStream_t s);
+hipError_t launch_dt(const double* U, const uint8_t* flags, const double* hx, const double* mu, double* part,
+                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* dt, hipStream_t s);
+hipError_t launch_time_advance(double* t, const double* dt, double* last_dt, hipStream_t s);
+
+}  // namespace fcs

@@ -1,0 +1,460 @@
+// Elementwise, stencil and gather kernels of one FC-SDNN step.
+//
+// Per stage (the stage algorithm of Sec. 5 and the stage loop of Alg. 1):
+// fluxes of the Euler system (Sec. 2) as contraction operands, assembly of
+// the spatial operator from the FC derivatives and the Jacobian of the
+// inverse mapping (chain rule; viscous term mu Lap(w) + grad mu . grad w),
+// the SSPRK(5,4) stage update in Shu-Osher form, boundary conditions, and the
+// fringe exchange/interpolation (Sec. 3.3).  Per step: proxy variable, window
+// classification, wave-speed bound and preliminary viscosity (Alg. 3), its
+// smoothing and blend across subpatches (Sec. 4), the filter's variable
+// change (Alg. 4; theta = p / ((gamma - 1) rho)) and the adaptive step.
+#include "stage_kernels.h"
+
+#include "classify.h"
+
+#include <cmath>
+
+namespace fcs {
+
+namespace {
+
+__device__ __forceinline__ double pressure(double r, double mx, double my, double E, double gm1) {
+  return gm1 * (E - 0.5 * (mx * mx + my * my) / r);
+}
+
+__global__ void k_flux(const double* __restrict__ U, double* __restrict__ F, const uint8_t* __restrict__ flags,
+                       const double* __restrict__ t1x, const double* __restrict__ t1y,
+                       const double* __restrict__ t2x, const double* __restrict__ t2y, int64_t P, double gm1) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  uint8_t f = flags[k];
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (f & kActive) {
+    double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+    double p = pressure(r, mx, my, E, gm1);
+    double u = mx / r, w = my / r;
+    double fx[4] = {mx, mx * u + p, mx * w, u * (E + p)};
+    double fy[4] = {my, my * u, my * w + p, w * (E + p)};
+    if (f & kAffine) {
+      double a = t1x[k], b = t1y[k], c = t2x[k], d = t2y[k];
+      for (int q = 0; q < 4; ++q) {
+        v[q] = a * fx[q] + b * fy[q];
+        v[4 + q] = c * fx[q] + d * fy[q];
+      }
+    } else {
+      for (int q = 0; q < 4; ++q) {
+        v[q] = fx[q];
+        v[4 + q] = fy[q];
+      }
+    }
+  }
+  for (int q = 0; q < 8; ++q) F[q * P + k] = v[q];
+}
+
+__global__ void k_stage(StageArgs a) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t P = a.P;
+  if (k >= P) return;
+  const uint8_t f = a.flags[k];
+  if (!(f & kActive)) {
+    for (int q = 0; q < 4; ++q) a.out[q * P + k] = 0.0;
+    return;
+  }
+  const double dt = *a.dt;
+  double L[4];
+  if (f & kAffine) {
+    for (int q = 0; q < 4; ++q) L[q] = -(a.DF1[q * P + k] + a.DF2[(4 + q) * P + k]);
+  } else {
+    double t1x = a.t1x[k], t1y = a.t1y[k], t2x = a.t2x[k], t2y = a.t2y[k];
+    for (int q = 0; q < 4; ++q)
+      L[q] = -(t1x * a.DF1[q * P + k] + t1y * a.DF1[(4 + q) * P + k] + t2x * a.DF2[q * P + k] +
+               t2y * a.DF2[(4 + q) * P + k]);
+  }
+  if (a.visc) {
+    double mu = a.mu[k], mu1 = a.mu1[k], mu2 = a.mu2[k];
+    double g11 = a.g11[k], g12 = a.g12[k], g22 = a.g22[k], l1 = a.lap1[k], l2 = a.lap2[k];
+    for (int q = 0; q < 4; ++q) {
+      double w1 = a.W1[q * P + k], w2 = a.W2[q * P + k], w11 = a.W11[q * P + k], w22 = a.W22[q * P + k];
+      double w12 = a.W12 ? a.W12[q * P + k] : 0.0;
+      double lap = g11 * w11 + 2.0 * g12 * w12 + g22 * w22 + l1 * w1 + l2 * w2;
+      double grad = g11 * mu1 * w1 + g12 * (mu1 * w2 + mu2 * w1) + g22 * mu2 * w2;
+      L[q] = L[q] + mu * lap + grad;
+    }
+  }
+  bool bad = false;
+  for (int q = 0; q < 4; ++q) {
+    const double in = a.in[q * P + k], u0 = a.U0[q * P + k];
+    double o;
+    switch (a.stage) {
+      case 0:
+        o = u0 + a.c[0] * dt * L[q];
+        break;
+      case 1:
+        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        break;
+      case 2:
+        a.acc[q * P + k] = a.c[4] * in;
+        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        break;
+      case 3: {
+        double acc = a.acc[q * P + k];
+        a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
+        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        break;
+      }
+      default:
+        o = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
+        break;
+    }
+    if (!isfinite(o)) bad = true;
+    a.out[q * P + k] = o;
+  }
+  if (!bad) {
+    double r = a.out[k];
+    double p = pressure(r, a.out[P + k], a.out[2 * P + k], a.out[3 * P + k], a.gm1);
+    bad = !(r > 0.0) || !(p > 0.0);
+  }
+  if (bad) *a.bad_flag = 1;
+}
+
+__global__ void k_slip(double* __restrict__ U, const SlipEntry* __restrict__ e, int n, int64_t P, double gm1) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const SlipEntry s = e[q];
+  const int64_t k = s.k;
+  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+  double p = gm1 * (E - 0.5 * (mx * mx + my * my) / r);
+  if (s.corner) {
+    mx = 0.0;
+    my = 0.0;
+  } else {
+    double mn = mx * s.nx + my * s.ny;
+    mx = mx - mn * s.nx;
+    my = my - mn * s.ny;
+  }
+  U[P + k] = mx;
+  U[2 * P + k] = my;
+  U[3 * P + k] = p / gm1 + 0.5 * (mx * mx + my * my) / r;
+}
+
+__global__ void k_dirichlet(double* __restrict__ U, const DirichletEntry* __restrict__ e, int n, int64_t P) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const DirichletEntry d = e[q];
+  for (int c = 0; c < 4; ++c) U[c * P + d.k] = d.e[c];
+}
+
+// Isentropic vortex (beta, x0, y0, u0, v0) at time t0 + frac * dt.
+__global__ void k_exact(double* __restrict__ U, const ExactEntry* __restrict__ e, int n, int64_t P,
+                        const double* __restrict__ tptr, const double* __restrict__ dtptr, double frac,
+                        VortexArgs v, double gamma) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const ExactEntry x = e[q];
+  const double t = *tptr + frac * *dtptr;
+  const double pi = 3.141592653589793;
+  double dx = x.x - v.x0 - v.u0 * t, dy = x.y - v.y0 - v.v0 * t;
+  double r2 = dx * dx + dy * dy;
+  double g = exp(0.5 * (1.0 - r2));
+  double du = -v.beta / (2 * pi) * g * dy, dv = v.beta / (2 * pi) * g * dx;
+  double T = 1.0 - (gamma - 1.0) * v.beta * v.beta / (8 * gamma * pi * pi) * exp(1.0 - r2);
+  double rho = pow(T, 1.0 / (gamma - 1.0));
+  double p = pow(rho, gamma);
+  double u = v.u0 + du, w = v.v0 + dv;
+  U[x.k] = rho;
+  U[P + x.k] = rho * u;
+  U[2 * P + x.k] = rho * w;
+  U[3 * P + x.k] = p / (gamma - 1.0) + 0.5 * rho * (u * u + w * w);
+}
+
+__global__ void k_copy_rows(double* __restrict__ U, const int64_t* __restrict__ pairs, int n, int64_t P,
+                            int ncomp) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  int64_t dst = pairs[2 * q], src = pairs[2 * q + 1];
+  for (int c = 0; c < ncomp; ++c) U[c * P + dst] = U[c * P + src];
+}
+
+__global__ void k_interp_rows(double* __restrict__ U, const int64_t* __restrict__ dst,
+                              const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
+                              const double* __restrict__ val, int n, int64_t P, int ncomp) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double s[4] = {0, 0, 0, 0};
+  for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
+    const double w = val[e];
+    const int64_t c = col[e];
+    for (int m = 0; m < ncomp; ++m) s[m] += w * U[m * P + c];
+  }
+  for (int m = 0; m < ncomp; ++m) U[m * P + dst[q]] = s[m];
+}
+
+// Proxy (Mach number) and |u| + a at every point.
+__global__ void k_proxy(const double* __restrict__ U, const uint8_t* __restrict__ flags, double* __restrict__ phi,
+                        double* __restrict__ spd, int64_t P, double gamma) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  if (!(flags[k] & kActive)) {
+    phi[k] = 0.0;
+    spd[k] = 0.0;
+    return;
+  }
+  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+  double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+  double speed = sqrt(mx * mx + my * my) / r;
+  phi[k] = speed * sqrt(r / (gamma * p));
+  spd[k] = speed + sqrt(gamma * p / r);
+}
+
+__global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
+  __shared__ float W[FCS_SDNN_NPARAM_DEV];
+  if (a.mode == 2) {
+    load_sdnn_params(a.weights, W, FCS_SDNN_NPARAM_DEV);
+    __syncthreads();
+  }
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.P) return;
+  const uint8_t f = a.flags[k];
+  const int pid = a.pid[k];
+  const PatchDev pd = a.patches[pid];
+  const int64_t loc = k - pd.offset;
+  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
+  int tau[2] = {0, 0};
+  double smax = 0.0;
+  const int2 rr = a.rowrun[pd.row_run + j];
+  const int2 cr = a.colrun[pd.col_run + i];
+  double v[16];
+  if (f & kActive) {
+    for (int dir = 0; dir < 2; ++dir) {
+      int2 run = dir == 0 ? rr : cr;
+      if (run.y < 16) continue;
+      int pos = dir == 0 ? i : j;
+      int ws = min(max(pos - 8, run.x), run.x + run.y - 16);
+      int64_t base = dir == 0 ? (pd.offset + static_cast<int64_t>(j) * pd.n1 + ws)
+                              : (pd.offset + static_cast<int64_t>(ws) * pd.n1 + i);
+      int64_t stride = dir == 0 ? 1 : pd.n1;
+      for (int m = 0; m < 16; ++m) smax = fmax(smax, a.spd[base + m * stride]);
+      if (a.mode == 3) {
+        tau[dir] = a.tau[dir * a.P + k];
+      } else {
+        for (int m = 0; m < 16; ++m) v[m] = a.phi[base + m * stride];
+        tau[dir] = a.mode == 2 ? classify_sdnn(v, W) : classify_modal(v, a.basis);
+      }
+    }
+  }
+  if (a.mode != 3) {
+    a.tau[k] = static_cast<uint8_t>(tau[0]);
+    a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
+  }
+  const double alpha[3] = {0.0, 0.5, 1.0};
+  double al = fmax(alpha[tau[0]], alpha[tau[1]]);
+  bool keep = (f & kActive) && !(f & (kFringe | kXFringe));
+  a.muhat[k] = keep ? a.c_mu * a.hx[k] * smax * al : 0.0;
+}
+
+// One pass of the windowed max: out(k) = max_off in(k + off * stride) w(|off|)
+// over the index box (dir 0 along q^1, 1 along q^2); the final pass zeroes
+// inactive points.
+__global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ pid,
+                         const PatchDev* __restrict__ patches, const uint8_t* __restrict__ flags, int64_t P, int dir,
+                         int nv, const double* __restrict__ w, int final_pass) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const PatchDev pd = patches[pid[k]];
+  const int64_t loc = k - pd.offset;
+  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
+  const int pos = dir == 0 ? i : j, len = dir == 0 ? pd.n1 : pd.n2;
+  const int64_t stride = dir == 0 ? 1 : pd.n1;
+  double best = 0.0;
+  for (int off = -nv; off <= nv; ++off) {
+    int q = pos + off;
+    if (q < 0 || q >= len) continue;
+    double val = in[k + off * stride] * w[off < 0 ? -off : off];
+    if (val > best) best = val;
+  }
+  if (final_pass && !(flags[k] & kActive)) best = 0.0;
+  out[k] = best;
+}
+
+__global__ void k_blend(const double* __restrict__ mut, double* __restrict__ mu, int64_t P) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  mu[k] = fmax(mut[k], 0.0);
+}
+
+__global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu, const int64_t* __restrict__ dst,
+                             const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
+                             const double* __restrict__ val, int n) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double s = 0.0;
+  for (int e = ptr[q]; e < ptr[q + 1]; ++e) s += val[e] * mut[col[e]];
+  mu[dst[q]] = fmax(s, 0.0);
+}
+
+__global__ void k_filter_pre(const double* __restrict__ U, double* __restrict__ Q, const uint8_t* __restrict__ flags,
+                             int64_t P, double gamma) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+  double th = 0.0;
+  if (flags[k] & kActive) {
+    double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+    th = p / ((gamma - 1.0) * r);
+  }
+  Q[k] = r;
+  Q[P + k] = mx;
+  Q[2 * P + k] = my;
+  Q[3 * P + k] = th;
+}
+
+__global__ void k_filter_post(const double* __restrict__ Q, double* __restrict__ U, const uint8_t* __restrict__ flags,
+                              int64_t P) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  if (!(flags[k] & kActive)) {
+    for (int c = 0; c < 4; ++c) U[c * P + k] = 0.0;
+    return;
+  }
+  double r = Q[k], mx = Q[P + k], my = Q[2 * P + k], th = Q[3 * P + k];
+  U[k] = r;
+  U[P + k] = mx;
+  U[2 * P + k] = my;
+  U[3 * P + k] = r * th + 0.5 * (mx * mx + my * my) / r;
+}
+
+__global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U, const uint8_t* __restrict__ flags,
+                                                    const double* __restrict__ hx, const double* __restrict__ mu,
+                                                    double* __restrict__ part, int64_t P, double gamma) {
+  __shared__ double red[256];
+  double best = INFINITY;
+  for (int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; k < P;
+       k += static_cast<int64_t>(gridDim.x) * blockDim.x) {
+    if (!(flags[k] & kActive)) continue;
+    double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+    double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+    double s = sqrt(mx * mx + my * my) / r + sqrt(gamma * p / r);
+    double h = hx[k];
+    best = fmin(best, h / s);
+    if (mu) {
+      double m = mu[k];
+      if (m > 0.0) best = fmin(best, h * h / m);
+    }
+  }
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_dt_final(const double* __restrict__ part, int n, double cfl, double dt_fixed,
+                           double* __restrict__ dt) {
+  __shared__ double red[256];
+  double best = INFINITY;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) best = fmin(best, part[q]);
+  red[threadIdx.x] = best;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *dt = dt_fixed > 0.0 ? dt_fixed : cfl * red[0];
+}
+
+__global__ void k_time_advance(double* __restrict__ t, const double* __restrict__ dt, double* __restrict__ last_dt) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    *t = *t + *dt;
+    *last_dt = *dt;
+  }
+}
+
+inline dim3 grid_for(int64_t n, int b = 256) { return dim3(static_cast<unsigned>((n + b - 1) / b)); }
+
+}  // namespace
+
+hipError_t launch_flux(const double* U, double* F, const uint8_t* flags, const double* t1x, const double* t1y,
+                       const double* t2x, const double* t2y, int64_t P, double gm1, hipStream_t s) {
+  hipLaunchKernelGGL(k_flux, grid_for(P), dim3(256), 0, s, U, F, flags, t1x, t1y, t2x, t2y, P, gm1);
+  return hipGetLastError();
+}
+
+hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_stage, grid_for(a.P), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc(double* U, const SlipEntry* slip, int nslip, const DirichletEntry* dir, int ndir,
+                     const ExactEntry* ex, int nex, int64_t P, double gamma, const double* t, const double* dt,
+                     double frac, const VortexArgs& v, hipStream_t s) {
+  if (nslip) hipLaunchKernelGGL(k_slip, grid_for(nslip), dim3(256), 0, s, U, slip, nslip, P, gamma - 1.0);
+  if (ndir) hipLaunchKernelGGL(k_dirichlet, grid_for(ndir), dim3(256), 0, s, U, dir, ndir, P);
+  if (nex) hipLaunchKernelGGL(k_exact, grid_for(nex), dim3(256), 0, s, U, ex, nex, P, t, dt, frac, v, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_fringe(double* U, const int64_t* copy_pairs, int ncopy, const int64_t* idst, const int32_t* iptr,
+                         const int64_t* icol, const double* ival, int ninterp, int64_t P, hipStream_t s) {
+  if (ncopy) hipLaunchKernelGGL(k_copy_rows, grid_for(ncopy), dim3(256), 0, s, U, copy_pairs, ncopy, P, 4);
+  if (ninterp)
+    hipLaunchKernelGGL(k_interp_rows, grid_for(ninterp), dim3(256), 0, s, U, idst, iptr, icol, ival, ninterp, P, 4);
+  return hipGetLastError();
+}
+
+hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_proxy, grid_for(v.P), dim3(256), 0, s, v.U, v.flags, v.phi, v.spd, v.P, v.gamma);
+  ClassifyArgs c;
+  c.P = v.P;
+  c.flags = v.flags;
+  c.pid = v.pid;
+  c.patches = v.patches;
+  c.rowrun = v.rowrun;
+  c.colrun = v.colrun;
+  c.phi = v.phi;
+  c.spd = v.spd;
+  c.hx = v.hx;
+  c.tau = v.tau;
+  c.muhat = v.muhat;
+  c.mode = v.mode;
+  c.weights = v.weights;
+  c.basis = v.basis;
+  c.c_mu = v.c_mu;
+  hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.patches, v.flags, v.P, 0,
+                     v.nv, v.wdil, 0);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.patches, v.flags, v.P, 1,
+                     v.nv, v.wdil, 1);
+  hipLaunchKernelGGL(k_blend, grid_for(v.P), dim3(256), 0, s, v.mut, v.mu, v.P);
+  if (v.nblend)
+    hipLaunchKernelGGL(k_blend_rows, grid_for(v.nblend), dim3(256), 0, s, v.mut, v.mu, v.bdst, v.bptr, v.bcol,
+                       v.bval, v.nblend);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_pre, grid_for(P), dim3(256), 0, s, U, Q, flags, P, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_post, grid_for(P), dim3(256), 0, s, Q, U, flags, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt(const double* U, const uint8_t* flags, const double* hx, const double* mu, double* part,
+                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_dt_partial, dim3(nblocks), dim3(256), 0, s, U, flags, hx, mu, part, P, gamma);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, part, nblocks, cfl, dt_fixed, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_time_advance(double* t, const double* dt, double* last_dt, hipStream_t s) {
+  hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(64), 0, s, t, dt, last_dt);
+  return hipGetLastError();
+}
+
+}  // namespace fcs
