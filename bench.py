@@ -1,0 +1,200 @@
+"""Benchmark of the FC-SDNN per-stage hot path on one MI355X.
+
+Workload: the Mach-3 step channel ([0, 3] x [0, 1] with a step over
+[0.6, 3] x [0, 0.2]; 22 overlapping subpatches of up to 112 x 109 points on a
+h = 1/250 lattice, with one L-shaped C1 corner patch and one C2 corner patch;
+inflow rho = 1.4, p = 1, u = 3; slip walls; SDNN artificial viscosity with
+a classifier trained on the GPU by the library's own kernels at set-up;
+spectral filter; adaptive step at CFL 0.5).  One benchmark step is one
+solver time step: viscosity (classification, smoothing, blend), filter,
+step size and the five SSPRK stages (fluxes, grouped FC derivative
+contractions, viscous terms, update, boundary conditions, fringe
+interpolation), replayed as one captured hipGraph.
+
+Prints one JSON line: point-stage updates/s of the plain FP64 form (the
+configuration as stated) and, in ``mixed``, of the split-BF16 contraction
+form with its error against the FP64 run at equal step counts; the roofline
+of the dominant kernel (the grouped contraction, timed with HIP events on
+the solver stream) and the CPU oracle timed on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
+HBM_PEAK = 8.0e12
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=3)
+    return ap.parse_args()
+
+
+def train_classifier(F, W, torch, steps=300, batch=4096):
+    """Seeded training of the smoothness classifier on the GPU: synthetic
+    lines through the solver's FC filter (d = 2, C = 27), 16-point windows,
+    class-weighted Adam with the library's training kernels."""
+    lines, pos, amp = W.classifier_lines(3000, seed_salt=51)
+    filt = F.lines_apply(torch.tensor(lines, device="cuda"), "filter", 2, 27)
+    lab = W.window_labels(pos, amp, lines)
+    n = lines.shape[1]
+    start = np.clip(np.arange(n) - 8, 0, n - 16)
+    idx = torch.tensor(start[:, None] + np.arange(16)[None, :], device="cuda")
+    wins = filt[:, idx].reshape(-1, 16)
+    lo = wins.min(dim=1, keepdim=True).values
+    hi = wins.max(dim=1, keepdim=True).values
+    am = wins.abs().max(dim=1, keepdim=True).values
+    rng_ = hi - lo
+    keep = (rng_ >= 1e-3 * torch.clamp(am, min=1.0)).squeeze(1)
+    x = ((wins - lo) / torch.where(rng_ > 0, rng_, torch.ones_like(rng_)))[keep].float().contiguous()
+    y = torch.tensor(lab.reshape(-1), device="cuda")[keep].int().contiguous()
+    counts = torch.bincount(y, minlength=3).double()
+    cw = (counts.sum() / (3.0 * torch.clamp(counts, min=1.0))).float()
+    g = W.rng(4, 52)
+    params = torch.tensor(W.sdnn_blob(W.sdnn_init(g)), device="cuda")
+    tr = F.SdnnTrainer(params, batch=batch, lr=2e-3)
+    for _ in range(steps):
+        sel = torch.tensor(g.integers(0, y.numel(), batch), device="cuda")
+        tr.step(x[sel].contiguous(), y[sel].contiguous(), cw)
+    torch.cuda.synchronize()
+    return params.cpu().numpy()
+
+
+def make_solver(F, W, torch, weights, precision, stream):
+    specs = W.step_channel()
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=True,
+                         precision=precision, sdnn_weights=weights)
+    with torch.cuda.stream(stream):
+        S = F.Solver(specs, prm, stream=stream)
+        w = W.uniform_state(specs, W.STEP_INFLOW)
+        for p in range(len(specs)):
+            S.set_state(p, w[p])
+    return S, specs
+
+
+def timed_run(S, torch, stream, steps, warmup):
+    S.advance(5 * warmup, sync=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    S.advance(5 * steps)
+    stream.synchronize()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    S.advance(0, sync=True)  # raises if the state became non-finite
+    return el
+
+
+def field_errors(ref_solver, solver, specs):
+    """Per-field max and RMS difference over all active points, relative to
+    the field's largest magnitude in the reference run."""
+    errs = {}
+    for name in ("rho", "mx", "my", "E"):
+        sel = [specs[p].mask if specs[p].mask is not None else np.ones(specs[p].shape, bool)
+               for p in range(len(specs))]
+        ref = np.concatenate([ref_solver.field(p, name)[sel[p]] for p in range(len(specs))])
+        got = np.concatenate([solver.field(p, name)[sel[p]] for p in range(len(specs))])
+        d = got - ref
+        scale = max(np.abs(ref).max(), 1e-300)
+        errs[name] = {"max_rel": float(np.abs(d).max() / scale), "rms_rel": float(np.sqrt((d * d).mean()) / scale)}
+    return errs
+
+
+def contraction_profile(S, torch, nsteps=20):
+    """Average duration of the grouped derivative contraction, from HIP events
+    recorded around each launch on the solver stream (eager replay)."""
+    S.profile(True)
+    S.advance(5 * nsteps, sync=True)
+    r = S.profile_read()
+    S.profile(False)
+    return r
+
+
+def cpu_baseline(W, steps):
+    from threadpoolctl import threadpool_limits
+    from oracle import solver as osolver
+    specs = W.step_channel()
+    with threadpool_limits(limits=1):
+        O = osolver.Solver(osolver.patches_from_specs(specs),
+                           osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
+        O.set_prim(W.uniform_state(specs, W.STEP_INFLOW))
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            O.step()
+        el = time.perf_counter() - t0
+    npts = int(sum(s.npoints() for s in specs))
+    return {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"step channel, first {steps} steps (modal-indicator viscosity, filter), "
+                      f"{npts} points, FP64 NumPy, 1 thread, {el:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
+                                   "note, not an implemented path)"}))
+        sys.exit(2)
+    import torch
+    import paper_2506_19370_amd as F
+    import workloads as W
+
+    weights = train_classifier(F, W, torch)
+    stream = torch.cuda.Stream()
+    S, specs = make_solver(F, W, torch, weights, "fp64", stream)
+    npts = int(sum(s.npoints() for s in specs))
+    el = timed_run(S, torch, stream, a.steps, a.warmup)
+    value = npts * 5 * a.steps / el
+    prof = contraction_profile(S, torch)
+    achieved = prof["flops"] / (prof["avg_ms"] * 1e-3)
+    out = {
+        "metric": "point-stage updates/s, plain FP64 vs mixed-precision batched form at stated error",
+        "value": value, "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+        "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "Mach-3 step channel [0,3]x[0,1], step [0.6,3]x[0,0.2], 22 subpatches "
+                               "(C1 L-shaped + C2 corner patches), %d points, SDNN viscosity (GPU-trained), "
+                               "filter, CFL 0.5, FC-Gram d=2 C=27" % npts,
+                   "points": npts, "stages_per_step": 5},
+        "roofline": {"bound": "mfma", "kernel": "grouped FC contraction (k_gemm_f64)",
+                     "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "avg_launch_ms": prof["avg_ms"], "flops_per_launch": prof["flops"],
+                     "algorithmic_bytes_per_launch": prof["bytes"], "launches_timed": prof["launches"]},
+    }
+    if not a.no_mixed:
+        Sm, _ = make_solver(F, W, torch, weights, "bf16x3", stream)
+        elm = timed_run(Sm, torch, stream, a.steps, a.warmup)
+        pm = contraction_profile(Sm, torch)
+        err_long = field_errors(S, Sm, specs)
+        # short horizon: fresh runs of 10 steps
+        S10, _ = make_solver(F, W, torch, weights, "fp64", stream)
+        M10, _ = make_solver(F, W, torch, weights, "bf16x3", stream)
+        S10.advance(50, sync=True)
+        M10.advance(50, sync=True)
+        out["mixed"] = {"precision": "split-BF16 x3 contractions, FP32 accumulate, FP64 state", "batched": "hipGraph",
+                        "value": npts * 5 * a.steps / elm, "ms_per_step": elm / a.steps * 1e3,
+                        "speedup_vs_fp64": el / elm,
+                        "error_vs_fp64_after_10_steps": field_errors(S10, M10, specs),
+                        "error_vs_fp64_after_%d_steps" % (a.steps + a.warmup + 20): err_long,
+                        "contraction_avg_ms": pm["avg_ms"]}
+    if not a.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(W, a.cpu_steps)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

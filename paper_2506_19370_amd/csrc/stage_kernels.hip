@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U
     best = fmin(best, h / s);
     if (mu) {
       double m = mu[k];
-      if (m > 0.0) best = fmin(best, h * h / m);
+      if (m > 0.0) best = fmin(best, h * h / (4.0 * m));
     }
   }
   red[threadIdx.x] = best;

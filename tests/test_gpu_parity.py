@@ -1,0 +1,269 @@
+"""GPU parity of the HIP path against the CPU oracle (MI355X, gfx950).
+
+Tolerances (FP64 paths): the library builds its FC operators in quad
+precision on the host, the oracle in 256-bit mpmath followed by an FP64 FFT
+of the unit vectors; the two operators differ by <= 3e-12 (d = 5, where the
+continuation values reach ~5e3 and the FFT rounds them) and <= 1e-14
+(d = 2).  A contraction then differs by about that times max|f|, a stage
+update by that times dt / h; the tolerances below are a few times those
+bounds and are stated per test.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import paper_2506_19370_amd as F  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle import exact, fcgram, solver as osolver  # noqa: E402
+
+
+def _sweep_ref(fields):
+    out1, out2 = [], []
+    for f in fields:
+        out1.append(fcgram.fc_apply(f, 5, 27, "d1"))
+        out2.append(np.swapaxes(fcgram.fc_apply(np.swapaxes(f, -1, -2), 5, 27, "d1"), -1, -2))
+    return out1, out2
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 2e-12), ("fp32", 2e-6), ("bf16x3", 1e-4)])
+def test_sweep_parity(prec, tol):
+    """Grouped contraction over uneven patches (several 64 x 64 tiles and
+    ragged tails) vs the oracle's FFT derivative; error relative to the
+    largest field value of the component (the operator error multiplies the
+    data, not its derivative).  FP32: unit roundoff 6e-8 times the operator's
+    row sums of |entries| (<= 18) and the accumulation length; split BF16:
+    two 8-bit halves leave ~2^-16 per product on the offset-free data."""
+    sizes, fields = W.deriv_sweep(npatch=12, nmin=20, nmax=200, seed_salt=1)
+    flat = np.concatenate([f.ravel() for f in fields])
+    sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
+    x = torch.tensor(flat, device="cuda")
+    d1 = torch.zeros_like(x)
+    d2 = torch.zeros_like(x)
+    sw.run(x, d1, d2)
+    torch.cuda.synchronize()
+    g1, g2 = d1.cpu().numpy(), d2.cpu().numpy()
+    r1, r2 = _sweep_ref(fields)
+    off = 0
+    for f, a, b in zip(fields, r1, r2):
+        n = f.size
+        for c in range(4):
+            scale = np.abs(f[c]).max()
+            e1 = np.abs(g1[off:off + n].reshape(f.shape)[c] - a[c]).max() / scale
+            e2 = np.abs(g2[off:off + n].reshape(f.shape)[c] - b[c]).max() / scale
+            assert e1 < tol and e2 < tol, (prec, f.shape, c, e1, e2)
+        off += n
+
+
+def test_sweep_full_size_sampled():
+    """The full derivative-sweep workload (2000 patches, 64..256) in the
+    launch configuration the benchmark times: sampled patches against the
+    oracle, FP64."""
+    sizes, fields = W.deriv_sweep(npatch=2000)
+    flat = np.concatenate([f.ravel() for f in fields])
+    sw = F.DerivSweep(sizes, 4, "fp64", d=5, C=27)
+    x = torch.tensor(flat, device="cuda")
+    d1 = torch.zeros_like(x)
+    d2 = torch.zeros_like(x)
+    sw.run(x, d1, d2)
+    torch.cuda.synchronize()
+    offs = np.concatenate([[0], np.cumsum([f.size for f in fields])])
+    for p in (0, 7, 999, 1999):
+        f = fields[p]
+        r1, r2 = _sweep_ref([f])
+        a = d1[offs[p]:offs[p + 1]].cpu().numpy().reshape(f.shape)
+        b = d2[offs[p]:offs[p + 1]].cpu().numpy().reshape(f.shape)
+        scale = np.abs(f).max()
+        assert np.abs(a - r1[0]).max() < 2e-12 * scale and np.abs(b - r2[0]).max() < 2e-12 * scale
+
+
+def _vortex_pair(specs, d=5, av="off", n_f=5):
+    prm = F.SolverParams(fc_d=d, fc_C=27, n_f=n_f, av=av)
+    S = F.Solver(specs, prm)
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=d, fc_C=27, n_f=n_f, av=av),
+                       exact=lambda x, y, t: exact.isentropic_vortex(x, y, t))
+    w = [exact.isentropic_vortex(s.x, s.y, 0.0) for s in specs]
+    for p, wp in enumerate(w):
+        S.set_state(p, wp)
+    O.set_prim(w)
+    return S, O
+
+
+def _rel(S, O, specs):
+    err = 0.0
+    scale = np.abs(O.U).max()
+    for p in range(len(specs)):
+        err = max(err, np.abs(S.cons(p) - O.view(O.U, p)).max())
+    return err / scale
+
+
+def test_vortex_single_patch_steps():
+    specs = W.vortex_box(61)
+    S, O = _vortex_pair(specs)
+    for _ in range(3):
+        t = S.advance(5, sync=True)
+        O.step()
+        assert abs(t - O.t) < 1e-14
+    assert _rel(S, O, specs) < 1e-12
+
+
+def test_vortex_partial_steps_match_full_steps():
+    specs = W.vortex_box(41)
+    S1, _ = _vortex_pair(specs)
+    S2, _ = _vortex_pair(specs)
+    S1.advance(10, sync=True)
+    for n in (3, 4, 1, 2):
+        S2.advance(n)
+    S2.advance(0, sync=True)
+    assert np.array_equal(S1.cons(0), S2.cons(0))
+
+
+def test_vortex_multipatch_interpolation():
+    """Four overlapping patches whose grids do not coincide: the fringe is
+    filled by degree-5 interpolation every stage."""
+    specs = W.vortex_multipatch(41)
+    S, O = _vortex_pair(specs)
+    for _ in range(2):
+        S.advance(5, sync=True)
+        O.step()
+    assert _rel(S, O, specs) < 1e-12
+
+
+def test_step_channel_no_viscosity():
+    """Mach-3 step channel (C1 L-shaped and C2 corner subpatches, slip walls,
+    inflow, outflow), FP64, d = 2."""
+    specs = W.step_channel()
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5)
+    S = F.Solver(specs, prm)
+    w = W.uniform_state(specs, W.STEP_INFLOW)
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=2, fc_C=27, cfl=0.5))
+    O.set_prim(w)
+    for _ in range(3):
+        S.advance(5, sync=True)
+        O.step()
+    assert _rel(S, O, specs) < 1e-12
+
+
+def _jump_state(specs):
+    """Step-channel state with a density and pressure jump at x = 0.3."""
+    out = []
+    for s in specs:
+        w = np.broadcast_to(np.asarray(W.STEP_INFLOW, float)[:, None, None], (4,) + s.shape).copy()
+        right = s.x > 0.3
+        w[0] = np.where(right, 2.8, w[0])
+        w[3] = np.where(right, 2.5, w[3])
+        out.append(w)
+    return out
+
+
+@pytest.mark.parametrize("filt", [False, True])
+def test_step_channel_modal_viscosity(filt):
+    """Artificial viscosity with the modal indicator (FP64 on both sides):
+    classes must agree exactly, then the viscosity and states."""
+    specs = W.step_channel()
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=filt)
+    S = F.Solver(specs, prm)
+    w = _jump_state(specs)
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal",
+                                                                         filter=filt))
+    O.set_prim(w)
+    for step in range(2):
+        S.advance(5, sync=True)
+        O.step()
+        nz = 0
+        for p in range(len(specs)):
+            t0, t1 = S.field(p, "tau0"), S.field(p, "tau1")
+            assert np.array_equal(t0, O.last_tau[p][0]) and np.array_equal(t1, O.last_tau[p][1]), (step, p)
+            mu = S.field(p, "mu")
+            mref = O.field(O.mu[0], p)
+            assert np.abs(mu - mref).max() <= 1e-12 * max(1e-300, np.abs(O.mu[0]).max())
+            nz += int((mref > 0).sum())
+        assert nz > 100  # the viscosity is active around the jump
+    assert _rel(S, O, specs) < 1e-11
+
+
+def _sector():
+    spec = W.annular_sector(48, 40)[0]
+    spec.sides = {k: W.OUTFLOW for k in "WESN"}
+    return [spec]
+
+
+def test_curvilinear_freestream_preserved():
+    specs = _sector()
+    w = np.broadcast_to(np.array([1.4, 0.5, 0.2, 1.0])[:, None, None], (4,) + specs[0].shape).copy()
+    S = F.Solver(specs, F.SolverParams(fc_d=5, fc_C=27, dt_fixed=1e-3))
+    S.set_state(0, w)
+    e0 = S.cons(0)
+    S.advance(10, sync=True)
+    assert np.abs(S.cons(0) - e0).max() < 1e-9 * np.abs(e0).max()
+
+
+def test_curvilinear_viscous_parity_frozen_classes():
+    """Non-affine metrics (16 line products per stage, Laplacian of the index
+    coordinates, cross derivatives) with a non-zero viscosity: classes are
+    prescribed (frozen) identically on both sides."""
+    specs = _sector()
+    s = specs[0]
+    r = np.hypot(s.x, s.y)
+    w = np.stack([1.4 + 0.2 * np.exp(-40 * (r - 1.5) ** 2), 0.5 + 0 * r, 0.2 + 0 * r, 1.0 + 0.1 * np.exp(-40 * (r - 1.5) ** 2)])
+    tau = np.zeros((2,) + s.shape, dtype=np.uint8)
+    tau[0, 15:25, 10:30] = 2
+    tau[1, 18:22, 20:40] = 1
+    S = F.Solver(specs, F.SolverParams(fc_d=5, fc_C=27, av="frozen", dt_fixed=2e-4))
+    S.set_state(0, w)
+    S.set_tau(0, tau)
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=5, fc_C=27, av="modal", dt_fixed=2e-4))
+    O.set_prim([w])
+    O.tau_override = [tau.astype(np.int64)]
+    for _ in range(2):
+        S.advance(5, sync=True)
+        O.step()
+    assert np.abs(O.mu[0]).max() > 0
+    assert np.abs(S.field(0, "mu") - O.field(O.mu[0], 0)).max() < 1e-12 * np.abs(O.mu[0]).max()
+    assert _rel(S, O, specs) < 1e-12
+
+
+def test_graph_replay_equals_eager():
+    specs = W.step_channel()
+    w = W.uniform_state(specs, W.STEP_INFLOW)
+    out = []
+    for graph in (False, True):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, av="modal", filter=True, use_graph=graph),
+                         stream=stream)
+            for p in range(len(specs)):
+                S.set_state(p, w[p])
+            for _ in range(3):  # replays with host synchronizations in between
+                S.advance(10, sync=True)
+            out.append([S.cons(p) for p in range(len(specs))])
+    for a, b in zip(*out):
+        assert np.array_equal(a, b)
+
+
+def test_nonfinite_is_reported():
+    specs = W.vortex_box(41)
+    S = F.Solver(specs, F.SolverParams(fc_d=5, fc_C=27))
+    w = exact.isentropic_vortex(specs[0].x, specs[0].y, 0.0)
+    w[0, 20, 20] = -1.0
+    S.set_state(0, w)
+    with pytest.raises(F.FcsError) as ei:
+        S.advance(5, sync=True)
+    assert ei.value.status == 4
+
+
+def test_overlap_violation_rejected():
+    specs = W.step_channel()
+    # drop the L-shaped corner patch: its neighbours' fringes lose their donors
+    bad = [s for s in specs if s.kind != "C1"]
+    with pytest.raises(F.FcsError) as ei:
+        F.Solver(bad, F.SolverParams(fc_d=2, fc_C=27))
+    assert ei.value.status == 2

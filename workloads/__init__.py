@@ -207,6 +207,35 @@ def deriv_sweep(npatch=2000, nmin=64, nmax=256, config_index=3, seed_salt=0):
     return sizes, fields
 
 
+# ---------------------------------------------------------------- classifier weights
+SDNN_SHAPES = (("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (3, 64)), ("b3", (3,)))
+
+
+def sdnn_init(g: np.random.Generator):
+    """Seeded He-normal initial parameters of the 16-64-64-3 classifier,
+    FP32 values; biases zero."""
+    out = {}
+    for name, shape in SDNN_SHAPES:
+        if name.startswith("b"):
+            out[name] = np.zeros(shape, dtype=np.float32)
+        else:
+            out[name] = (g.standard_normal(shape) * np.sqrt(2.0 / shape[1])).astype(np.float32)
+    return out
+
+
+def sdnn_blob(params) -> np.ndarray:
+    return np.concatenate([np.asarray(params[k], dtype=np.float32).ravel() for k, _ in SDNN_SHAPES])
+
+
+def sdnn_unblob(blob) -> dict:
+    out, o = {}, 0
+    for k, shape in SDNN_SHAPES:
+        n = int(np.prod(shape))
+        out[k] = np.asarray(blob[o:o + n], dtype=np.float64).reshape(shape)
+        o += n
+    return out
+
+
 # ---------------------------------------------------------------- classifier lines
 def classifier_lines(nlines, n=101, config_index=4, seed_salt=0):
     """Raw synthetic lines for the smoothness classifier: smooth random
