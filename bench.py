@@ -78,7 +78,7 @@ def train_classifier(F, W, torch, steps=300, batch=4096):
 def make_solver(F, W, torch, weights, precision, stream):
     specs = W.step_channel()
     prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=True,
-                         precision=precision, sdnn_weights=weights)
+                         precision=precision, sdnn_weights=weights, autotune=True)
     with torch.cuda.stream(stream):
         S = F.Solver(specs, prm, stream=stream)
         w = W.uniform_state(specs, W.STEP_INFLOW)

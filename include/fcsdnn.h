@@ -99,6 +99,8 @@ typedef struct {
   int32_t av_mode;     /* FCS_AV_*                                           */
   int32_t filter;      /* nonzero: spectral filter every step t > 0 (Alg. 4) */
   int32_t use_graph;   /* nonzero: replay whole steps as a captured hipGraph */
+  int32_t autotune;    /* nonzero: time the contraction tile shapes on the
+                          first advance and keep the fastest               */
   const float* sdnn_weights; /* host, FCS_SDNN_NPARAM floats; copied        */
   double vortex[5];    /* EXACT sides: beta, x0, y0, u0, v0 of the isentropic
                           vortex (background rho = p = 1)                    */
@@ -213,6 +215,11 @@ fcs_status fcs_sweep_run(fcs_sweep* s, const double* in, double* d1, double* d2)
 fcs_status fcs_sweep_profile(fcs_sweep* s, int32_t on, double* avg_ms, double* flops, double* bytes,
                              int64_t* launches);
 fcs_status fcs_sweep_points(const fcs_sweep* s, int64_t* npoints);
+/* Autotuner: runs every candidate tile shape of the contraction kernel on
+ * the given device arrays (results overwritten), keeps the fastest, and
+ * writes the per-candidate ms (up to 8 doubles, host) to ms if non-NULL.
+ * Synchronizes. */
+fcs_status fcs_sweep_autotune(fcs_sweep* s, const double* in, double* d1, double* d2, double* ms);
 void fcs_sweep_destroy(fcs_sweep* s);
 
 /* ---------------------------------------------------------------------

@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("dt_fixed", ctypes.c_double),
         ("fc_d", ctypes.c_int32), ("fc_C", ctypes.c_int32), ("n_f", ctypes.c_int32), ("n_v", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("av_mode", ctypes.c_int32), ("filter", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
         ("sdnn_weights", ctypes.POINTER(ctypes.c_float)),
         ("vortex", ctypes.c_double * 5),
     ]
@@ -103,6 +103,7 @@ fcs_sweep_profile = _sig("fcs_sweep_profile", _i, [vp, _i, ctypes.POINTER(_d), c
                                                    ctypes.POINTER(_d), ctypes.POINTER(_i64)])
 fcs_sweep_points = _sig("fcs_sweep_points", _i, [vp, ctypes.POINTER(_i64)])
 fcs_sweep_destroy = _sig("fcs_sweep_destroy", None, [vp])
+fcs_sweep_autotune = _sig("fcs_sweep_autotune", _i, [vp, vp, vp, vp, vp])
 fcs_sdnn_infer = _sig("fcs_sdnn_infer", _i, [vp, vp, _i64, vp, vp, vp])
 fcs_modal_infer = _sig("fcs_modal_infer", _i, [vp, _i64, vp, vp])
 fcs_sdnn_train_workspace = _sig("fcs_sdnn_train_workspace", _sz, [_i])
@@ -116,7 +117,7 @@ EXPORTED = [
     "fcs_set_tau", "fcs_advance", "fcs_get_field", "fcs_stats", "fcs_profile_enable", "fcs_profile_read",
     "fcs_last_error", "fcs_destroy", "fcs_fc_continuation", "fcs_fc_operator", "fcs_sweep_create",
     "fcs_sweep_workspace_size", "fcs_sweep_bind", "fcs_sweep_run", "fcs_sweep_profile", "fcs_sweep_points",
-    "fcs_sweep_destroy", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",
+    "fcs_sweep_destroy", "fcs_sweep_autotune", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",
     "fcs_lines_workspace", "fcs_lines_apply",
 ]
 

@@ -34,6 +34,7 @@ class SolverParams:
     av: str = "off"
     filter: bool = False
     use_graph: bool = False
+    autotune: bool = False
     sdnn_weights: np.ndarray | None = None
     vortex: tuple = (5.0, 5.0, 5.0, 1.0, 1.0)
 
@@ -55,6 +56,7 @@ class Solver:
         cp.av_mode = L.AV[prm.av]
         cp.filter = int(bool(prm.filter))
         cp.use_graph = int(bool(prm.use_graph))
+        cp.autotune = int(bool(prm.autotune))
         if prm.sdnn_weights is not None:
             w = np.ascontiguousarray(prm.sdnn_weights, dtype=np.float32)
             if w.size != L.SDNN_NPARAM:
@@ -178,6 +180,12 @@ class DerivSweep:
                 raise ValueError("sweep arrays must be contiguous FP64 device tensors of the sweep's size")
         L.check(L.fcs_sweep_run(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d1.data_ptr()),
                                 ctypes.c_void_p(d2.data_ptr())))
+
+    def autotune(self, x: torch.Tensor, d1: torch.Tensor, d2: torch.Tensor):
+        ms = np.zeros(8)
+        L.check(L.fcs_sweep_autotune(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d1.data_ptr()),
+                                     ctypes.c_void_p(d2.data_ptr()), ms.ctypes.data))
+        return ms
 
     def profile(self, on: int):
         ms, fl, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()

@@ -61,6 +61,8 @@ struct TaskSpec {
   int src_arr, dst_arr;  // array ids
   int64_t src_off, dst_off;
   int32_t row_stride, s_stride, nrow, ncomp, n, op;
+  int32_t flux = 0;
+  double fa = 0, fb = 0;
 };
 
 enum ArrayId { A_U0, A_UA, A_UB, A_F, A_DF1, A_DF2, A_W1, A_W2, A_W11, A_W22, A_W12, A_MU, A_MU1, A_MU2, A_IN, A_NARR };
@@ -99,9 +101,8 @@ struct fcs_ctx {
   std::vector<int64_t> copy_pairs, idst, icol, bdst, bcol;
   std::vector<int32_t> iptr, bptr;
   std::vector<double> ival, bval;
-  std::vector<SlipEntry> slip;
-  std::vector<DirichletEntry> dirich;
-  std::vector<ExactEntry> exact;
+  std::vector<BcEntry> bc;
+  bool flux_kernel = false;  // some subpatch is not affine
   std::vector<double> metric_host[10];  // t1x t1y t2x t2y g11 g12 g22 lap1 lap2 hx
   std::vector<double> basis, wdil;
   std::vector<uint8_t> tau_host;
@@ -117,6 +118,10 @@ struct fcs_ctx {
   GemmTile* d_tiles[PH_N] = {};
   OpTables optab{};
   int dt_blocks = 512;
+  GemmVariant var[PH_N];
+  size_t tile_cap[PH_N] = {};
+  bool tuned = false;
+  float tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
 
   // time stepping
   int stage_in_step = 0;
@@ -175,6 +180,12 @@ int op_id(fcs_ctx* c, int n, int kind) {
   return id;
 }
 
+size_t first_active(const Grid& g) {
+  for (size_t k = 0; k < g.np(); ++k)
+    if (g.mask[k]) return k;
+  return 0;
+}
+
 // Tasks for all lines of one grid along one direction, grouped by runs.
 void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int src_arr, int src_comp0,
                     int dst_arr, int dst_comp0, int ncomp) {
@@ -206,17 +217,15 @@ void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int 
   }
 }
 
-void build_tiles(fcs_ctx* c) {
-  for (int ph = 0; ph < PH_N; ++ph) {
-    auto& tiles = c->phase_tiles[ph];
-    tiles.clear();
-    const auto& tasks = c->phase_tasks[ph];
-    for (size_t q = 0; q < tasks.size(); ++q) {
-      int nlines = tasks[q].nrow * tasks[q].ncomp;
-      for (int t0 = 0; t0 < tasks[q].n; t0 += 64)
-        for (int l0 = 0; l0 < nlines; l0 += 64) tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
-    }
+void build_tiles(fcs_ctx* c, int ph) {
+  const auto& tasks = c->phase_tasks[ph];
+  std::vector<int32_t> n(tasks.size()), nl(tasks.size());
+  for (size_t q = 0; q < tasks.size(); ++q) {
+    n[q] = tasks[q].n;
+    nl[q] = tasks[q].nrow * tasks[q].ncomp;
   }
+  const int prec = (ph == PH_EULER || ph == PH_CROSS) ? c->prm.precision : FCS_PREC_FP64;
+  gemm_build_tiles(prec, c->var[ph], n.data(), nl.data(), tasks.size(), c->phase_tiles[ph]);
 }
 
 double exact_flops(const std::vector<TaskSpec>& tasks) {
@@ -338,9 +347,18 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       for (int m = 0; m < 10; ++m) c->metric_host[m][gk] = (*src[m])[k];
       if (g.mask[k] && g.g12[k] != 0.0) c->cross = true;
     }
-    // boundary conditions: one slip entry per point, Dirichlet entries
-    std::map<int64_t, std::vector<std::pair<double, double>>> normals;
-    std::vector<int64_t> order;
+    // boundary conditions: one entry per point (slip normal or corner, then
+    // inflow or exact-vortex data)
+    std::map<int64_t, size_t> at;
+    auto entry = [&](int64_t gk) -> BcEntry& {
+      auto it = at.find(gk);
+      if (it != at.end()) return c->bc[it->second];
+      at[gk] = c->bc.size();
+      BcEntry e{};
+      e.k = gk;
+      c->bc.push_back(e);
+      return c->bc.back();
+    };
     for (const BoundaryEntry& b : g.bnd) {
       size_t k = g.at(b.j, b.i);
       int64_t gk = g.offset + static_cast<int64_t>(k);
@@ -348,32 +366,33 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
         double nx = b.dir == 0 ? g.t1x[k] : g.t2x[k];
         double ny = b.dir == 0 ? g.t1y[k] : g.t2y[k];
         double h = std::hypot(nx, ny);
-        if (!normals.count(gk)) order.push_back(gk);
-        normals[gk].push_back({nx / h, ny / h});
+        BcEntry& e = entry(gk);
+        if (e.slip == 0) {
+          e.slip = 1;
+          e.nx = nx / h;
+          e.ny = ny / h;
+        } else {
+          e.slip = 2;
+        }
       }
-    }
-    for (int64_t gk : order) {
-      const auto& ns = normals[gk];
-      SlipEntry e{};
-      e.k = gk;
-      e.nx = ns[0].first;
-      e.ny = ns[0].second;
-      e.corner = ns.size() > 1;
-      c->slip.push_back(e);
     }
     for (const BoundaryEntry& b : g.bnd) {
       if (b.kind != kInflow) continue;
-      DirichletEntry e{};
-      e.k = g.offset + static_cast<int64_t>(g.at(b.j, b.i));
+      BcEntry& e = entry(g.offset + static_cast<int64_t>(g.at(b.j, b.i)));
       double r = g.inflow[0], u = g.inflow[1], v = g.inflow[2], pr = g.inflow[3];
+      e.dirichlet = 1;
       e.e[0] = r;
       e.e[1] = r * u;
       e.e[2] = r * v;
       e.e[3] = pr / (p.gamma - 1.0) + 0.5 * r * (u * u + v * v);
-      c->dirich.push_back(e);
     }
     for (size_t k = 0; k < g.np(); ++k)
-      if (g.xfringe[k]) c->exact.push_back({g.offset + static_cast<int64_t>(k), g.x[k], g.y[k]});
+      if (g.xfringe[k]) {
+        BcEntry& e = entry(g.offset + static_cast<int64_t>(k));
+        e.dirichlet = 2;
+        e.x = g.x[k];
+        e.y = g.y[k];
+      }
   }
   // communication tables
   std::vector<InterpRow> rows;
@@ -419,7 +438,9 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   // contraction tasks
   for (int q = 0; q < npatch; ++q) {
     const Grid& g = c->grids[q];
+    c->flux_kernel = true;
     if (g.affine) {
+      // contravariant fluxes a f_x + b f_y with the constant metric terms
       add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_F, 0, A_DF1, 0, 4);
       add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_F, 4, A_DF2, 4, 4);
     } else {
@@ -440,7 +461,10 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_FILT2, g, 1, FCS_OP_FILTER, A_DF1, 0, A_DF2, 0, 4);
     }
   }
-  build_tiles(c.get());
+  for (int ph = 0; ph < PH_N; ++ph) {
+    build_tiles(c.get(), ph);  // default variant: the largest tile count
+    c->tile_cap[ph] = c->phase_tiles[ph].size();
+  }
   // operators
   for (const OpKey& k : c->ops) {
     c->op_off.push_back(c->op_elems);
@@ -478,7 +502,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   for (int ph = 0; ph < PH_N; ++ph) {
     for (int v = 0; v < 3; ++v)
       o["TASK" + std::to_string(ph) + "_" + std::to_string(v)] = cv.take(c->phase_tasks[ph].size() * sizeof(GemmTask));
-    o["TILE" + std::to_string(ph)] = cv.take(c->phase_tiles[ph].size() * sizeof(GemmTile));
+    o["TILE" + std::to_string(ph)] = cv.take(c->tile_cap[ph] * sizeof(GemmTile));
   }
   o["COPY"] = cv.take(c->copy_pairs.size() * 8);
   o["IDST"] = cv.take(c->idst.size() * 8);
@@ -489,9 +513,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BPTR"] = cv.take(c->bptr.size() * 4);
   o["BCOL"] = cv.take(c->bcol.size() * 8);
   o["BVAL"] = cv.take(c->bval.size() * D);
-  o["SLIP"] = cv.take(c->slip.size() * sizeof(SlipEntry));
-  o["DIRI"] = cv.take(c->dirich.size() * sizeof(DirichletEntry));
-  o["EXACT"] = cv.take(c->exact.size() * sizeof(ExactEntry));
+  o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
   o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
   o["BASIS"] = cv.take(256 * D);
   o["WDIL"] = cv.take((p.n_v + 1) * D);
@@ -596,6 +618,10 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
         t.ncomp = s.ncomp;
         t.n = s.n;
         t.op = s.op;
+        t.flux = s.flux;
+        t.fa = s.fa;
+        t.fb = s.fb;
+        t.gm1 = c->prm.gamma - 1.0;
         dt.push_back(t);
       }
       std::string name = "TASK" + std::to_string(ph) + "_" + std::to_string(v);
@@ -632,9 +658,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"BPTR", c->bptr.data(), c->bptr.size() * 4},
       {"BCOL", c->bcol.data(), c->bcol.size() * 8},
       {"BVAL", c->bval.data(), c->bval.size() * 8},
-      {"SLIP", c->slip.data(), c->slip.size() * sizeof(SlipEntry)},
-      {"DIRI", c->dirich.data(), c->dirich.size() * sizeof(DirichletEntry)},
-      {"EXACT", c->exact.data(), c->exact.size() * sizeof(ExactEntry)},
+      {"BC", c->bc.data(), c->bc.size() * sizeof(BcEntry)},
       {"SDNN", c->sdnn.data(), c->sdnn.size() * 4},
       {"BASIS", c->basis.data(), c->basis.size() * 8},
       {"WDIL", c->wdil.data(), c->wdil.size() * 8},
@@ -646,8 +670,8 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
     for (auto& w : v) std::vector<GemmTask>().swap(w);
   c->bound = true;
   c->cur = c->arr[A_U0];
-  double zero = c->t_host;
-  HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &zero, 8, hipMemcpyHostToDevice, c->stream));
+  double scal0[5] = {c->t_host, 0.0, 0.0, 0.0, c->t_host};
+  HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), scal0, sizeof(scal0), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   return FCS_OK;
 }
@@ -662,7 +686,7 @@ fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed) 
     e1 = c->ev[c->ev_used++];
     HIPCHK(c, hipEventRecord(e0, c->stream));
   }
-  HIPCHK(c, launch_gemm(precision, c->d_tasks[ph][variant], c->d_tiles[ph],
+  HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
                         static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->stream));
   if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
   return FCS_OK;
@@ -714,7 +738,7 @@ fcs_status per_step(fcs_ctx* c) {
     HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, c->stream));
   }
   HIPCHK(c, launch_dt(U0, c->dptr<uint8_t>("FLAGS"), c->dptr<double>("MET9"), c->visc ? c->arr[A_MU] : nullptr,
-                      c->dptr<double>("DTPART"), c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, scal + 1, c->stream));
+                      c->dptr<double>("DTPART"), c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, scal, c->stream));
   return FCS_OK;
 }
 
@@ -729,7 +753,8 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
   const double* met[10];
   for (int m = 0; m < 10; ++m) met[m] = c->dptr<double>(("MET" + std::to_string(m)).c_str());
-  HIPCHK(c, launch_flux(in, c->arr[A_F], flags, met[0], met[1], met[2], met[3], P, p.gamma - 1.0, c->stream));
+  if (c->flux_kernel)
+    HIPCHK(c, launch_flux(in, c->arr[A_F], flags, met[0], met[1], met[2], met[3], P, p.gamma - 1.0, c->stream));
   fcs_status st;
   if ((st = run_gemm(c, PH_EULER, variant, p.precision, true)) != FCS_OK) return st;
   if (c->visc && c->cross)
@@ -779,14 +804,11 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   double frac[5];
   stage_fractions(frac);
   VortexArgs vx{p.vortex[0], p.vortex[1], p.vortex[2], p.vortex[3], p.vortex[4]};
-  HIPCHK(c, launch_bc(outp, c->dptr<SlipEntry>("SLIP"), static_cast<int>(c->slip.size()),
-                      c->dptr<DirichletEntry>("DIRI"), static_cast<int>(c->dirich.size()),
-                      c->dptr<ExactEntry>("EXACT"), static_cast<int>(c->exact.size()), P, p.gamma, scal, scal + 1,
+  HIPCHK(c, launch_bc(outp, c->dptr<BcEntry>("BC"), static_cast<int>(c->bc.size()), P, p.gamma, scal, scal + 1,
                       frac[s], vx, c->stream));
   HIPCHK(c, launch_fringe(outp, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
                           c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
                           c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), P, c->stream));
-  if (s == 4) HIPCHK(c, launch_time_advance(scal, scal + 1, scal + 2, c->stream));
   c->cur = outp;
   return FCS_OK;
 }
@@ -855,6 +877,7 @@ extern "C" fcs_status fcs_set_time(fcs_ctx* c, double t) {
   c->t_host = t;
   if (c->bound) {
     HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL") + 4, &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   return FCS_OK;
@@ -900,11 +923,64 @@ fcs_status capture_step(fcs_ctx* c, int with_filter) {
 
 }  // namespace
 
+namespace {
+
+// Autotuner of the contraction tile shape: times every candidate variant on
+// the stage contraction (current state, stage-0 operands) with HIP events
+// and keeps the fastest for the stage and cross-derivative launches.
+fcs_status autotune(fcs_ctx* c) {
+  c->tuned = true;
+  if (!c->prm.autotune || c->phase_tiles[PH_EULER].empty()) return FCS_OK;
+  int nv = 0;
+  const GemmVariant* cand = gemm_variants(c->prm.precision, &nv);
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best = 1e30f;
+  GemmVariant bestv = c->var[PH_EULER];
+  for (int q = 0; q < nv; ++q) {
+    c->var[PH_EULER] = cand[q];
+    build_tiles(c, PH_EULER);
+    if (c->phase_tiles[PH_EULER].size() > c->tile_cap[PH_EULER]) continue;
+    fcs_status st = upload(c, "TILE0", c->phase_tiles[PH_EULER].data(),
+                           c->phase_tiles[PH_EULER].size() * sizeof(GemmTile));
+    if (st != FCS_OK) return st;
+    if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < 5; ++r)
+      if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    c->tune_ms[q] = ms / 5;
+    if (ms < best) {
+      best = ms;
+      bestv = cand[q];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  for (int ph : {PH_EULER, PH_CROSS}) {
+    c->var[ph] = bestv;
+    build_tiles(c, ph);
+    if (c->phase_tiles[ph].empty()) continue;
+    std::string name = "TILE" + std::to_string(ph);
+    fcs_status st = upload(c, name.c_str(), c->phase_tiles[ph].data(), c->phase_tiles[ph].size() * sizeof(GemmTile));
+    if (st != FCS_OK) return st;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return FCS_OK;
+}
+
+}  // namespace
+
 extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
   if (!c) return FCS_EINVAL;
   if (!c->bound) return c->fail(FCS_ESTATE, "fcs_advance before fcs_bind");
   if (n_stages < 0) return c->fail(FCS_EINVAL, "negative stage count");
   fcs_status st;
+  if (!c->tuned && (st = autotune(c)) != FCS_OK) return st;
   const bool graph = c->prm.use_graph && c->stream != nullptr && !c->prof;
   while (n_stages > 0) {
     if (c->stage_in_step == 0 && n_stages >= 5) {
@@ -933,7 +1009,9 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
   }
   if (t_out) {
     if ((st = check_bad(c)) != FCS_OK) return st;
-    HIPCHK(c, hipMemcpyAsync(&c->t_host, c->dptr<double>("SCAL"), 8, hipMemcpyDeviceToHost, c->stream));
+    // time after the completed stages: end of the step at a step boundary
+    const double* tp = c->dptr<double>("SCAL") + (c->stage_in_step == 0 ? 4 : 0);
+    HIPCHK(c, hipMemcpyAsync(&c->t_host, tp, 8, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *t_out = c->t_host;
   }
@@ -988,14 +1066,14 @@ extern "C" fcs_status fcs_get_field(fcs_ctx* c, int32_t patch, int32_t field, do
 extern "C" fcs_status fcs_stats(fcs_ctx* c, fcs_stats_t* out) {
   if (!c || !out) return FCS_EINVAL;
   if (!c->bound) return c->fail(FCS_ESTATE, "fcs_stats before fcs_bind");
-  double scal[3];
+  double scal[5];
   std::vector<double> e(4 * c->P);
-  HIPCHK(c, hipMemcpyAsync(scal, c->dptr<double>("SCAL"), 24, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(scal, c->dptr<double>("SCAL"), 40, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemcpyAsync(e.data(), c->cur, 4 * c->P * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   out->steps = c->steps;
   out->stages = c->stages;
-  out->t = scal[0];
+  out->t = c->stage_in_step == 0 ? scal[4] : scal[0];
   out->dt = scal[2];
   out->mass = out->energy = 0;
   for (int64_t k = 0; k < c->P; ++k)

@@ -89,7 +89,20 @@ struct fcs_sweep {
   size_t ev_used = 0;
   double ms = 0;
   int64_t launches = 0;
+  GemmVariant var;
+  size_t tile_cap = 0;
 };
+
+namespace {
+void sweep_tiles(fcs_sweep* s) {
+  std::vector<int32_t> n(s->tasks.size()), nl(s->tasks.size());
+  for (size_t q = 0; q < s->tasks.size(); ++q) {
+    n[q] = s->tasks[q].n;
+    nl[q] = s->tasks[q].nrow * s->tasks[q].ncomp;
+  }
+  gemm_build_tiles(s->precision, s->var, n.data(), nl.data(), s->tasks.size(), s->tiles);
+}
+}  // namespace
 
 extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int32_t ncomp, int32_t precision,
                                        int32_t d, int32_t C, fcs_sweep** out) {
@@ -136,11 +149,8 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     t.op = s->ops.index(b);
     s->tasks.push_back(t);
   }
-  for (size_t q = 0; q < s->tasks.size(); ++q) {
-    int nl = s->tasks[q].nrow * s->tasks[q].ncomp;
-    for (int t0 = 0; t0 < s->tasks[q].n; t0 += 64)
-      for (int l0 = 0; l0 < nl; l0 += 64) s->tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
-  }
+  sweep_tiles(s.get());
+  s->tile_cap = s->tiles.size();
   size_t u = 0;
   auto take = [&](size_t b) {
     size_t o = u;
@@ -251,11 +261,60 @@ extern "C" fcs_status fcs_sweep_run(fcs_sweep* s, const double* in, double* d1, 
     e1 = s->ev[s->ev_used++];
     if (hipEventRecord(e0, s->stream)) return FCS_EHIP;
   }
-  if (launch_gemm(s->precision, reinterpret_cast<const GemmTask*>(s->ws + s->o_task),
+  if (launch_gemm(s->precision, s->var, reinterpret_cast<const GemmTask*>(s->ws + s->o_task),
                   reinterpret_cast<const GemmTile*>(s->ws + s->o_tile), static_cast<int>(s->tiles.size()), s->tab,
                   s->stream) != hipSuccess)
     return FCS_EHIP;
   if (e1 && hipEventRecord(e1, s->stream)) return FCS_EHIP;
+  return FCS_OK;
+}
+
+// Time every candidate tile shape on the given arrays and keep the fastest.
+extern "C" fcs_status fcs_sweep_autotune(fcs_sweep* s, const double* in, double* d1, double* d2, double* ms_out) {
+  if (!s || !s->ws) return FCS_EINVAL;
+  int nv = 0;
+  const GemmVariant* cand = gemm_variants(s->precision, &nv);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) || hipEventCreate(&e1)) return FCS_EHIP;
+  float best = 1e30f;
+  GemmVariant bestv = s->var;
+  bool saved = s->prof;
+  s->prof = false;
+  fcs_status st = FCS_OK;
+  for (int q = 0; q < nv && st == FCS_OK; ++q) {
+    s->var = cand[q];
+    sweep_tiles(s);
+    if (s->tiles.size() > s->tile_cap) continue;
+    if (hipMemcpyAsync(s->ws + s->o_tile, s->tiles.data(), s->tiles.size() * sizeof(GemmTile),
+                       hipMemcpyHostToDevice, s->stream) ||
+        hipStreamSynchronize(s->stream)) {
+      st = FCS_EHIP;
+      break;
+    }
+    if ((st = fcs_sweep_run(s, in, d1, d2)) != FCS_OK) break;
+    hipEventRecord(e0, s->stream);
+    for (int r = 0; r < 3 && st == FCS_OK; ++r) st = fcs_sweep_run(s, in, d1, d2);
+    hipEventRecord(e1, s->stream);
+    hipEventSynchronize(e1);
+    float ms = 0;
+    hipEventElapsedTime(&ms, e0, e1);
+    ms /= 3;
+    if (ms_out) ms_out[q] = ms;
+    if (ms < best) {
+      best = ms;
+      bestv = cand[q];
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  s->prof = saved;
+  if (st != FCS_OK) return st;
+  s->var = bestv;
+  sweep_tiles(s);
+  if (hipMemcpyAsync(s->ws + s->o_tile, s->tiles.data(), s->tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice,
+                     s->stream) ||
+      hipStreamSynchronize(s->stream))
+    return FCS_EHIP;
   return FCS_OK;
 }
 
@@ -375,8 +434,8 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
   t.n = n;
   t.op = 0;
   std::vector<GemmTile> tiles;
-  for (int t0 = 0; t0 < n; t0 += 64)
-    for (int64_t l0 = 0; l0 < nlines; l0 += 64) tiles.push_back({0, static_cast<int32_t>(l0), t0, 0});
+  for (int t0 = 0; t0 < n; t0 += gemm_outputs_per_tile(GemmVariant{}))
+    for (int64_t l0 = 0; l0 < nlines; l0 += gemm_lines_per_tile()) tiles.push_back({0, static_cast<int32_t>(l0), t0, 0});
   if (hipMemcpyAsync(ws + o_op, op->data(), op->size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(ws + o_off, zero, 16, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(ws + o_task, &t, sizeof(t), hipMemcpyHostToDevice, st) ||
@@ -386,7 +445,7 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
   tab.off = reinterpret_cast<const int64_t*>(ws + o_off);
   tab.roff = reinterpret_cast<const int64_t*>(ws + o_off);
   tab.f64 = reinterpret_cast<const double*>(ws + o_op);
-  if (launch_gemm(0, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
+  if (launch_gemm(0, GemmVariant{}, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
                   static_cast<int>(tiles.size()), tab, st) != hipSuccess)
     return FCS_EHIP;
   // the host staging vectors must outlive the copies

@@ -7,8 +7,12 @@
 namespace fcs {
 
 // One set of lines that share a line length, run position and operator:
-// out[line][t] = sum_s Op[t][s] in[line][s].  line = c * nrow + r addresses
-// element base + c * comp_stride + r * row_stride + s * s_stride.
+// out[line][t] = sum_s Op[t][s] in[line][s].  Lines are numbered with the
+// component fastest: line = r * ncomp + c addresses element
+// base + c * comp_stride + r * row_stride + s * s_stride.
+// flux != 0: the operand is not read but computed from the conserved state
+// (src = state, 4 components): component c of a fx + b fy (the Euler fluxes
+// of Sec. 2 contracted with constant metric terms of an affine subpatch).
 struct GemmTask {
   const double* src;
   double* dst;
@@ -17,6 +21,10 @@ struct GemmTask {
   int32_t nrow, ncomp;
   int32_t n;       // line length = operator size
   int32_t op;      // operator index (into the operator tables)
+  int32_t flux;    // 0: plain operand; 1: affine Euler flux from the state
+  int32_t pad;
+  double fa, fb;   // metric pair of the flux operand
+  double gm1;      // gamma - 1
 };
 
 struct GemmTile {
@@ -32,7 +40,7 @@ struct OpTables {
   const float* f32;
   const uint16_t* bhi;
   const uint16_t* blo;
-  const double* rowsum;     // offset off[k] / n ... (n entries at roff[k])
+  const double* rowsum;     // row sums of operator k at roff[k]
   const int64_t* roff;
 };
 
@@ -48,20 +56,15 @@ struct PatchDev {
 // Per-point flags.
 enum : uint8_t { kActive = 1, kFringe = 2, kXFringe = 4, kAffine = 8 };
 
-struct SlipEntry {
+// Boundary conditions of one point (Sec. 5 item 4): slip (zero normal
+// momentum, pressure kept; both momentum components zero at a corner of two
+// slip sides), then Dirichlet data (inflow state or exact vortex).
+struct BcEntry {
   int64_t k;
   double nx, ny;
-  int32_t corner;
-  int32_t pad;
-};
-
-struct DirichletEntry {
-  int64_t k;
+  int32_t slip;      // 0 none, 1 projection, 2 corner
+  int32_t dirichlet; // 0 none, 1 fixed state e[], 2 exact vortex at (x, y)
   double e[4];
-};
-
-struct ExactEntry {
-  int64_t k;
   double x, y;
 };
 

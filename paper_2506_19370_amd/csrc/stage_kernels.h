@@ -69,17 +69,16 @@ struct ViscArgs {
 hipError_t launch_flux(const double* U, double* F, const uint8_t* flags, const double* t1x, const double* t1y,
                        const double* t2x, const double* t2y, int64_t P, double gm1, hipStream_t s);
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-hipError_t launch_bc(double* U, const SlipEntry* slip, int nslip, const DirichletEntry* dir, int ndir,
-                     const ExactEntry* ex, int nex, int64_t P, double gamma, const double* t, const double* dt,
-                     double frac, const VortexArgs& v, hipStream_t s);
+hipError_t launch_bc(double* U, const BcEntry* bc, int nbc, int64_t P, double gamma, const double* t,
+                     const double* dt, double frac, const VortexArgs& v, hipStream_t s);
 hipError_t launch_fringe(double* U, const int64_t* copy_pairs, int ncopy, const int64_t* idst, const int32_t* iptr,
                          const int64_t* icol, const double* ival, int ninterp, int64_t P, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);
 hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, hipStream_t s);
+// scal: device scalars [t, dt, last dt, bad flag, t + dt]
 hipError_t launch_dt(const double* U, const uint8_t* flags, const double* hx, const double* mu, double* part,
-                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* dt, hipStream_t s);
-hipError_t launch_time_advance(double* t, const double* dt, double* last_dt, hipStream_t s);
+                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* scal, hipStream_t s);
 
 }  // namespace fcs

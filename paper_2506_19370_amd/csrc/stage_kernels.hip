@@ -118,54 +118,49 @@ __global__ void k_stage(StageArgs a) {
   if (bad) *a.bad_flag = 1;
 }
 
-__global__ void k_slip(double* __restrict__ U, const SlipEntry* __restrict__ e, int n, int64_t P, double gm1) {
+// Boundary conditions of one point: slip (normal momentum removed, pressure
+// kept; zero momentum at a corner of two slip sides), then Dirichlet data
+// (fixed state, or the isentropic vortex at t0 + frac * dt).
+__global__ void k_bc(double* __restrict__ U, const BcEntry* __restrict__ e, int n, int64_t P, double gamma,
+                     const double* __restrict__ tptr, const double* __restrict__ dtptr, double frac, VortexArgs v) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
-  const SlipEntry s = e[q];
-  const int64_t k = s.k;
-  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
-  double p = gm1 * (E - 0.5 * (mx * mx + my * my) / r);
-  if (s.corner) {
-    mx = 0.0;
-    my = 0.0;
-  } else {
-    double mn = mx * s.nx + my * s.ny;
-    mx = mx - mn * s.nx;
-    my = my - mn * s.ny;
+  const BcEntry b = e[q];
+  const int64_t k = b.k;
+  const double gm1 = gamma - 1.0;
+  if (b.slip) {
+    double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+    double p = gm1 * (E - 0.5 * (mx * mx + my * my) / r);
+    if (b.slip == 2) {
+      mx = 0.0;
+      my = 0.0;
+    } else {
+      double mn = mx * b.nx + my * b.ny;
+      mx = mx - mn * b.nx;
+      my = my - mn * b.ny;
+    }
+    U[P + k] = mx;
+    U[2 * P + k] = my;
+    U[3 * P + k] = p / gm1 + 0.5 * (mx * mx + my * my) / r;
   }
-  U[P + k] = mx;
-  U[2 * P + k] = my;
-  U[3 * P + k] = p / gm1 + 0.5 * (mx * mx + my * my) / r;
-}
-
-__global__ void k_dirichlet(double* __restrict__ U, const DirichletEntry* __restrict__ e, int n, int64_t P) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const DirichletEntry d = e[q];
-  for (int c = 0; c < 4; ++c) U[c * P + d.k] = d.e[c];
-}
-
-// Isentropic vortex (beta, x0, y0, u0, v0) at time t0 + frac * dt.
-__global__ void k_exact(double* __restrict__ U, const ExactEntry* __restrict__ e, int n, int64_t P,
-                        const double* __restrict__ tptr, const double* __restrict__ dtptr, double frac,
-                        VortexArgs v, double gamma) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const ExactEntry x = e[q];
-  const double t = *tptr + frac * *dtptr;
-  const double pi = 3.141592653589793;
-  double dx = x.x - v.x0 - v.u0 * t, dy = x.y - v.y0 - v.v0 * t;
-  double r2 = dx * dx + dy * dy;
-  double g = exp(0.5 * (1.0 - r2));
-  double du = -v.beta / (2 * pi) * g * dy, dv = v.beta / (2 * pi) * g * dx;
-  double T = 1.0 - (gamma - 1.0) * v.beta * v.beta / (8 * gamma * pi * pi) * exp(1.0 - r2);
-  double rho = pow(T, 1.0 / (gamma - 1.0));
-  double p = pow(rho, gamma);
-  double u = v.u0 + du, w = v.v0 + dv;
-  U[x.k] = rho;
-  U[P + x.k] = rho * u;
-  U[2 * P + x.k] = rho * w;
-  U[3 * P + x.k] = p / (gamma - 1.0) + 0.5 * rho * (u * u + w * w);
+  if (b.dirichlet == 1) {
+    for (int c = 0; c < 4; ++c) U[c * P + k] = b.e[c];
+  } else if (b.dirichlet == 2) {
+    const double t = *tptr + frac * *dtptr;
+    const double pi = 3.141592653589793;
+    double dx = b.x - v.x0 - v.u0 * t, dy = b.y - v.y0 - v.v0 * t;
+    double r2 = dx * dx + dy * dy;
+    double g = exp(0.5 * (1.0 - r2));
+    double du = -v.beta / (2 * pi) * g * dy, dv = v.beta / (2 * pi) * g * dx;
+    double T = 1.0 - (gamma - 1.0) * v.beta * v.beta / (8 * gamma * pi * pi) * exp(1.0 - r2);
+    double rho = pow(T, 1.0 / (gamma - 1.0));
+    double p = pow(rho, gamma);
+    double u = v.u0 + du, w = v.v0 + dv;
+    U[k] = rho;
+    U[P + k] = rho * u;
+    U[2 * P + k] = rho * w;
+    U[3 * P + k] = p / (gamma - 1.0) + 0.5 * rho * (u * u + w * w);
+  }
 }
 
 __global__ void k_copy_rows(double* __restrict__ U, const int64_t* __restrict__ pairs, int n, int64_t P,
@@ -351,8 +346,11 @@ __global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// Minimum of the per-block partial minima; also commits the time reached by
+// the previous step: scal[0] = t (start of this step), scal[1] = dt,
+// scal[2] = dt of the previous step, scal[4] = t + dt (end of this step).
 __global__ void k_dt_final(const double* __restrict__ part, int n, double cfl, double dt_fixed,
-                           double* __restrict__ dt) {
+                           double* __restrict__ scal) {
   __shared__ double red[256];
   double best = INFINITY;
   for (int q = threadIdx.x; q < n; q += blockDim.x) best = fmin(best, part[q]);
@@ -362,16 +360,19 @@ __global__ void k_dt_final(const double* __restrict__ part, int n, double cfl, d
     if (threadIdx.x < s) red[threadIdx.x] = fmin(red[threadIdx.x], red[threadIdx.x + s]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) *dt = dt_fixed > 0.0 ? dt_fixed : cfl * red[0];
-}
-
-__global__ void k_time_advance(double* __restrict__ t, const double* __restrict__ dt, double* __restrict__ last_dt) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    *t = *t + *dt;
-    *last_dt = *dt;
+  if (threadIdx.x == 0) {
+    const double t = scal[4];
+    const double dt = dt_fixed > 0.0 ? dt_fixed : cfl * red[0];
+    scal[2] = scal[1];
+    scal[0] = t;
+    scal[1] = dt;
+    scal[4] = t + dt;
   }
 }
 
+}  // namespace
+
+namespace {
 inline dim3 grid_for(int64_t n, int b = 256) { return dim3(static_cast<unsigned>((n + b - 1) / b)); }
 
 }  // namespace
@@ -387,12 +388,9 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bc(double* U, const SlipEntry* slip, int nslip, const DirichletEntry* dir, int ndir,
-                     const ExactEntry* ex, int nex, int64_t P, double gamma, const double* t, const double* dt,
-                     double frac, const VortexArgs& v, hipStream_t s) {
-  if (nslip) hipLaunchKernelGGL(k_slip, grid_for(nslip), dim3(256), 0, s, U, slip, nslip, P, gamma - 1.0);
-  if (ndir) hipLaunchKernelGGL(k_dirichlet, grid_for(ndir), dim3(256), 0, s, U, dir, ndir, P);
-  if (nex) hipLaunchKernelGGL(k_exact, grid_for(nex), dim3(256), 0, s, U, ex, nex, P, t, dt, frac, v, gamma);
+hipError_t launch_bc(double* U, const BcEntry* bc, int nbc, int64_t P, double gamma, const double* t,
+                     const double* dt, double frac, const VortexArgs& v, hipStream_t s) {
+  if (nbc) hipLaunchKernelGGL(k_bc, grid_for(nbc), dim3(256), 0, s, U, bc, nbc, P, gamma, t, dt, frac, v);
   return hipGetLastError();
 }
 
@@ -446,14 +444,9 @@ hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, 
 }
 
 hipError_t launch_dt(const double* U, const uint8_t* flags, const double* hx, const double* mu, double* part,
-                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* dt, hipStream_t s) {
+                     int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* scal, hipStream_t s) {
   hipLaunchKernelGGL(k_dt_partial, dim3(nblocks), dim3(256), 0, s, U, flags, hx, mu, part, P, gamma);
-  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, part, nblocks, cfl, dt_fixed, dt);
-  return hipGetLastError();
-}
-
-hipError_t launch_time_advance(double* t, const double* dt, double* last_dt, hipStream_t s) {
-  hipLaunchKernelGGL(k_time_advance, dim3(1), dim3(64), 0, s, t, dt, last_dt);
+  hipLaunchKernelGGL(k_dt_final, dim3(1), dim3(256), 0, s, part, nblocks, cfl, dt_fixed, scal);
   return hipGetLastError();
 }
 
