@@ -169,7 +169,7 @@ def main():
                                "(C1 L-shaped + C2 corner patches), %d points, SDNN viscosity (GPU-trained), "
                                "filter, CFL 0.5, FC-Gram d=2 C=27" % npts,
                    "points": npts, "stages_per_step": 5},
-        "roofline": {"bound": "mfma", "kernel": "grouped FC contraction (k_gemm_f64)",
+        "roofline": {"bound": "mfma", "kernel": "grouped FC stage contraction (k_gemm_fp<double>, autotuned tile)",
                      "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp64"], "traffic": None,
                      "avg_launch_ms": prof["avg_ms"], "flops_per_launch": prof["flops"],

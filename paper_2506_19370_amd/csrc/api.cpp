@@ -136,8 +136,13 @@ struct fcs_ctx {
   double prof_ms = 0.0;
   int64_t prof_n = 0;
 
-  // graphs
-  hipGraphExec_t gexec[2] = {nullptr, nullptr};  // [0] step without filter, [1] with
+  // graphs: [0] step without filter, [1] with; the profiled copies carry
+  // external event-record nodes around each stage contraction
+  hipGraphExec_t gexec[2] = {nullptr, nullptr};
+  hipGraphExec_t pgexec[2] = {nullptr, nullptr};
+  hipEvent_t pev[2][10] = {};
+  bool capturing_prof = false;
+  int prof_wf = 0, prof_stage = 0;
 
   template <typename T>
   T* dptr(const char* name) {
@@ -678,17 +683,44 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
 
 namespace {
 
+// Adds an event-record node to the graph being captured on the context's
+// stream, after everything captured so far, and makes it the new frontier.
+fcs_status record_in_capture(fcs_ctx* c, hipEvent_t ev) {
+  hipStreamCaptureStatus cs;
+  hipGraph_t g = nullptr;
+  const hipGraphNode_t* deps = nullptr;
+  size_t nd = 0;
+  HIPCHK(c, hipStreamGetCaptureInfo_v2(c->stream, &cs, nullptr, &g, &deps, &nd));
+  if (cs != hipStreamCaptureStatusActive) return c->fail(FCS_EHIP, "event node requested outside a capture");
+  hipGraphNode_t node;
+  HIPCHK(c, hipGraphAddEventRecordNode(&node, g, deps, nd, ev));
+  HIPCHK(c, hipStreamUpdateCaptureDependencies(c->stream, &node, 1, hipStreamSetCaptureDependencies));
+  return FCS_OK;
+}
+
 fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed) {
   if (c->phase_tiles[ph].empty()) return FCS_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (timed && c->prof && c->ev_used + 2 <= c->ev.size()) {
+  if (timed && c->capturing_prof) {
+    // inside a profiled graph: one event pair per stage, recorded as graph nodes
+    e0 = c->pev[c->prof_wf][2 * c->prof_stage];
+    e1 = c->pev[c->prof_wf][2 * c->prof_stage + 1];
+    fcs_status st = record_in_capture(c, e0);
+    if (st != FCS_OK) return st;
+  } else if (timed && c->prof && c->ev_used + 2 <= c->ev.size()) {
     e0 = c->ev[c->ev_used++];
     e1 = c->ev[c->ev_used++];
     HIPCHK(c, hipEventRecord(e0, c->stream));
   }
   HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
                         static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->stream));
-  if (e1) HIPCHK(c, hipEventRecord(e1, c->stream));
+  if (e1) {
+    if (c->capturing_prof) {
+      fcs_status st = record_in_capture(c, e1);
+      if (st != FCS_OK) return st;
+    } else
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+  }
   return FCS_OK;
 }
 
@@ -756,6 +788,7 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   if (c->flux_kernel)
     HIPCHK(c, launch_flux(in, c->arr[A_F], flags, met[0], met[1], met[2], met[3], P, p.gamma - 1.0, c->stream));
   fcs_status st;
+  c->prof_stage = s;
   if ((st = run_gemm(c, PH_EULER, variant, p.precision, true)) != FCS_OK) return st;
   if (c->visc && c->cross)
     if ((st = run_gemm(c, PH_CROSS, 0, p.precision, false)) != FCS_OK) return st;
@@ -901,21 +934,28 @@ extern "C" fcs_status fcs_set_tau(fcs_ctx* c, int32_t patch, const uint8_t* tau)
 
 namespace {
 
-fcs_status capture_step(fcs_ctx* c, int with_filter) {
-  if (c->gexec[with_filter]) return FCS_OK;
+fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
+  hipGraphExec_t* slot = profiled ? &c->pgexec[with_filter] : &c->gexec[with_filter];
+  if (*slot) return FCS_OK;
+  if (profiled)
+    for (auto& e : c->pev[with_filter])
+      if (!e) HIPCHK(c, hipEventCreate(&e));
   hipGraph_t graph;
   int64_t saved = c->steps;
   c->steps = with_filter ? 1 : 0;
   bool saved_prof = c->prof;
   c->prof = false;
+  c->capturing_prof = profiled;
+  c->prof_wf = with_filter;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   fcs_status st = full_step_eager(c);
   hipError_t e = hipStreamEndCapture(c->stream, &graph);
   c->steps = saved;
   c->prof = saved_prof;
+  c->capturing_prof = false;
   if (st != FCS_OK) return st;
   if (e != hipSuccess) return c->fail(FCS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
-  e = hipGraphInstantiate(&c->gexec[with_filter], graph, nullptr, nullptr, 0);
+  e = hipGraphInstantiate(slot, graph, nullptr, nullptr, 0);
   hipGraphDestroy(graph);
   if (e != hipSuccess) return c->fail(FCS_EHIP, std::string("graph instantiate: ") + hipGetErrorString(e));
   return FCS_OK;
@@ -981,14 +1021,24 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
   if (n_stages < 0) return c->fail(FCS_EINVAL, "negative stage count");
   fcs_status st;
   if (!c->tuned && (st = autotune(c)) != FCS_OK) return st;
-  const bool graph = c->prm.use_graph && c->stream != nullptr && !c->prof;
+  const bool graph = c->prm.use_graph && c->stream != nullptr;
   while (n_stages > 0) {
     if (c->stage_in_step == 0 && n_stages >= 5) {
       int wf = (c->prm.filter && c->steps > 0) ? 1 : 0;
       if (graph) {
-        if ((st = capture_step(c, wf)) != FCS_OK) return st;
-        HIPCHK(c, hipGraphLaunch(c->gexec[wf], c->stream));
+        if ((st = capture_step(c, wf, c->prof)) != FCS_OK) return st;
+        HIPCHK(c, hipGraphLaunch(c->prof ? c->pgexec[wf] : c->gexec[wf], c->stream));
         c->cur = c->arr[A_U0];
+        if (c->prof) {
+          // the events of a profiled graph are re-recorded by every replay
+          HIPCHK(c, hipStreamSynchronize(c->stream));
+          for (int q = 0; q < 5; ++q) {
+            float ms = 0;
+            HIPCHK(c, hipEventElapsedTime(&ms, c->pev[wf][2 * q], c->pev[wf][2 * q + 1]));
+            c->prof_ms += ms;
+            c->prof_n++;
+          }
+        }
       } else {
         if ((st = full_step_eager(c)) != FCS_OK) return st;
       }
@@ -1124,6 +1174,11 @@ extern "C" void fcs_destroy(fcs_ctx* c) {
   if (!c) return;
   for (auto& g : c->gexec)
     if (g) hipGraphExecDestroy(g);
+  for (auto& g : c->pgexec)
+    if (g) hipGraphExecDestroy(g);
+  for (auto& row : c->pev)
+    for (auto& e : row)
+      if (e) hipEventDestroy(e);
   for (auto& e : c->ev) hipEventDestroy(e);
   delete c;
 }
