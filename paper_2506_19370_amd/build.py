@@ -18,7 +18,7 @@ OUT = os.path.join(HERE, "libfcsdnn.so")
 BUILD = os.path.join(HERE, "_build")
 
 GXX_SOURCES = ["fc_builder.cpp", "geometry.cpp"]
-HIP_SOURCES = ["gemm.hip", "gemm_os.hip", "stage_kernels.hip", "window_kernels.hip", "sdnn_train.hip", "api.cpp", "aux_api.cpp"]
+HIP_SOURCES = ["gemm.hip", "stage_kernels.hip", "window_kernels.hip", "sdnn_train.hip", "api.cpp", "aux_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -61,18 +61,11 @@ struct TaskSpec {
   int src_arr, dst_arr;  // array ids
   int64_t src_off, dst_off;
   int32_t row_stride, s_stride, nrow, ncomp, n, op;
-  int32_t flux = 0;
-  double fa = 0, fb = 0;
 };
 
 enum ArrayId { A_U0, A_UA, A_UB, A_F, A_DF1, A_DF2, A_W1, A_W2, A_W11, A_W22, A_W12, A_MU, A_MU1, A_MU2, A_IN, A_NARR };
 
 enum Phase { PH_EULER, PH_CROSS, PH_MUGRAD, PH_FILT1, PH_FILT2, PH_N };
-
-struct OpKey {
-  int n, kind;
-  bool operator<(const OpKey& o) const { return n < o.n || (n == o.n && kind < o.kind); }
-};
 
 }  // namespace
 
@@ -84,11 +77,8 @@ struct fcs_ctx {
   bool visc = false, cross = false;
   std::string err;
 
-  // operators
-  std::map<OpKey, int> op_index;
-  std::vector<OpKey> ops;
-  std::vector<int64_t> op_off, op_roff;
-  int64_t op_elems = 0, op_rows = 0;
+  // operators (zero-padded tables shared by all precisions)
+  OpPack opk;
 
   std::vector<TaskSpec> phase_tasks[PH_N];
   std::vector<GemmTile> phase_tiles[PH_N];
@@ -176,13 +166,7 @@ float host_bf16_to_f(uint16_t h) {
 }
 
 int op_id(fcs_ctx* c, int n, int kind) {
-  OpKey k{n, kind};
-  auto it = c->op_index.find(k);
-  if (it != c->op_index.end()) return it->second;
-  int id = static_cast<int>(c->ops.size());
-  c->ops.push_back(k);
-  c->op_index[k] = id;
-  return id;
+  return c->opk.add(n, kind);
 }
 
 size_t first_active(const Grid& g) {
@@ -230,7 +214,7 @@ void build_tiles(fcs_ctx* c, int ph) {
     nl[q] = tasks[q].nrow * tasks[q].ncomp;
   }
   const int prec = (ph == PH_EULER || ph == PH_CROSS) ? c->prm.precision : FCS_PREC_FP64;
-  gemm_build_tiles(prec, c->var[ph], n.data(), nl.data(), tasks.size(), c->phase_tiles[ph]);
+  gemm_build_tiles(c->var[ph], n.data(), nl.data(), tasks.size(), c->phase_tiles[ph]);
 }
 
 double exact_flops(const std::vector<TaskSpec>& tasks) {
@@ -470,13 +454,6 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     build_tiles(c.get(), ph);  // default variant: the largest tile count
     c->tile_cap[ph] = c->phase_tiles[ph].size();
   }
-  // operators
-  for (const OpKey& k : c->ops) {
-    c->op_off.push_back(c->op_elems);
-    c->op_roff.push_back(c->op_rows);
-    c->op_elems += static_cast<int64_t>(k.n) * k.n;
-    c->op_rows += k.n;
-  }
   // workspace layout
   Carve cv;
   auto& o = c->off;
@@ -495,14 +472,15 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["PATCH"] = cv.take(c->pdev.size() * sizeof(PatchDev));
   o["ROWRUN"] = cv.take(c->rowrun.size() * sizeof(int2));
   o["COLRUN"] = cv.take(c->colrun.size() * sizeof(int2));
-  o["OPOFF"] = cv.take(c->op_off.size() * 8);
-  o["OPROFF"] = cv.take(c->op_roff.size() * 8);
-  o["OPF64"] = cv.take(c->op_elems * D);
-  o["OPROW"] = cv.take(c->op_rows * D);
-  if (p.precision == FCS_PREC_FP32) o["OPF32"] = cv.take(c->op_elems * 4);
+  o["OPOFF"] = cv.take(c->opk.off.size() * 8);
+  o["OPROFF"] = cv.take(c->opk.roff.size() * 8);
+  o["OPLD"] = cv.take(c->opk.ld.size() * 4);
+  o["OPF64"] = cv.take(c->opk.elems * D);
+  o["OPROW"] = cv.take(c->opk.rows * D);
+  if (p.precision == FCS_PREC_FP32) o["OPF32"] = cv.take(c->opk.elems * 4);
   if (p.precision == FCS_PREC_BF16X3) {
-    o["OPBHI"] = cv.take(c->op_elems * 2);
-    o["OPBLO"] = cv.take(c->op_elems * 2);
+    o["OPBHI"] = cv.take(c->opk.elems * 2);
+    o["OPBLO"] = cv.take(c->opk.elems * 2);
   }
   for (int ph = 0; ph < PH_N; ++ph) {
     for (int v = 0; v < 3; ++v)
@@ -546,42 +524,27 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
   HIPCHK(c, hipMemsetAsync(c->ws, 0, c->ws_need, c->stream));
   const int64_t P = c->P;
   // operators in every precision the context uses
-  std::vector<double> f64(c->op_elems), rows(c->op_rows);
-  for (size_t k = 0; k < c->ops.size(); ++k) {
-    const std::vector<double>* op = fc_operator(c->ops[k].n, c->prm.fc_d, c->prm.fc_C, c->ops[k].kind);
-    if (!op) return c->fail(FCS_EINVAL, "unsupported operator length");
-    std::copy(op->begin(), op->end(), f64.begin() + c->op_off[k]);
-    int n = c->ops[k].n;
-    for (int t = 0; t < n; ++t) {
-      double s = 0;
-      for (int q = 0; q < n; ++q) s += (*op)[static_cast<size_t>(t) * n + q];
-      rows[c->op_roff[k] + t] = s;
-    }
-  }
+  std::vector<double> f64, rows;
+  if (!c->opk.fill(c->prm.fc_d, c->prm.fc_C, f64, rows)) return c->fail(FCS_EINVAL, "unsupported operator length");
   fcs_status st;
   if ((st = upload(c, "OPF64", f64.data(), f64.size() * 8)) != FCS_OK) return st;
   if ((st = upload(c, "OPROW", rows.data(), rows.size() * 8)) != FCS_OK) return st;
-  if ((st = upload(c, "OPOFF", c->op_off.data(), c->op_off.size() * 8)) != FCS_OK) return st;
-  if ((st = upload(c, "OPROFF", c->op_roff.data(), c->op_roff.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPOFF", c->opk.off.data(), c->opk.off.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPROFF", c->opk.roff.data(), c->opk.roff.size() * 8)) != FCS_OK) return st;
+  if ((st = upload(c, "OPLD", c->opk.ld.data(), c->opk.ld.size() * 4)) != FCS_OK) return st;
   std::vector<float> f32;
   std::vector<uint16_t> bhi, blo;
   if (c->prm.precision == FCS_PREC_FP32) {
-    f32.resize(f64.size());
-    for (size_t q = 0; q < f64.size(); ++q) f32[q] = static_cast<float>(f64[q]);
+    f32.assign(f64.begin(), f64.end());
     if ((st = upload(c, "OPF32", f32.data(), f32.size() * 4)) != FCS_OK) return st;
   }
   if (c->prm.precision == FCS_PREC_BF16X3) {
-    bhi.resize(f64.size());
-    blo.resize(f64.size());
-    for (size_t q = 0; q < f64.size(); ++q) {
-      float f = static_cast<float>(f64[q]);
-      bhi[q] = host_bf16(f);
-      blo[q] = host_bf16(f - host_bf16_to_f(bhi[q]));
-    }
+    split_bf16(f64, bhi, blo);
     if ((st = upload(c, "OPBHI", bhi.data(), bhi.size() * 2)) != FCS_OK) return st;
     if ((st = upload(c, "OPBLO", blo.data(), blo.size() * 2)) != FCS_OK) return st;
   }
   c->optab.off = c->dptr<int64_t>("OPOFF");
+  c->optab.ld = c->dptr<int32_t>("OPLD");
   c->optab.roff = c->dptr<int64_t>("OPROFF");
   c->optab.f64 = c->dptr<double>("OPF64");
   c->optab.rowsum = c->dptr<double>("OPROW");
@@ -623,10 +586,6 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
         t.ncomp = s.ncomp;
         t.n = s.n;
         t.op = s.op;
-        t.flux = s.flux;
-        t.fa = s.fa;
-        t.fb = s.fb;
-        t.gm1 = c->prm.gamma - 1.0;
         dt.push_back(t);
       }
       std::string name = "TASK" + std::to_string(ph) + "_" + std::to_string(v);

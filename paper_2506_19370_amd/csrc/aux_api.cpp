@@ -23,36 +23,6 @@ namespace {
 constexpr size_t kAlign = 256;
 size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 
-uint16_t to_bf16(float f) {
-  uint32_t u;
-  std::memcpy(&u, &f, 4);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-float from_bf16(uint16_t h) {
-  uint32_t u = static_cast<uint32_t>(h) << 16;
-  float f;
-  std::memcpy(&f, &u, 4);
-  return f;
-}
-
-// Device operator tables for a set of (n, kind) operators in one precision.
-struct OpSet {
-  std::vector<int> n;
-  std::vector<int64_t> off, roff;
-  int64_t elems = 0, rows = 0;
-  int index(int len) {
-    for (size_t q = 0; q < n.size(); ++q)
-      if (n[q] == len) return static_cast<int>(q);
-    n.push_back(len);
-    off.push_back(elems);
-    roff.push_back(rows);
-    elems += static_cast<int64_t>(len) * len;
-    rows += len;
-    return static_cast<int>(n.size()) - 1;
-  }
-};
-
 }  // namespace
 
 extern "C" fcs_status fcs_fc_continuation(int32_t d, int32_t C, double* Q, double* A) {
@@ -74,12 +44,12 @@ struct fcs_sweep {
   std::vector<int32_t> n1, n2;
   std::vector<int64_t> poff;  // element offset of each patch (ncomp * n1 * n2 per patch)
   int64_t total = 0, npoints = 0;
-  OpSet ops;
+  OpPack ops;
   std::vector<GemmTask> tasks;
   std::vector<GemmTile> tiles;
   char* ws = nullptr;
   size_t need = 0;
-  size_t o_off = 0, o_roff = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
+  size_t o_off = 0, o_roff = 0, o_ld = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
   hipStream_t stream = nullptr;
   const double* last_in = nullptr;
   double *last_d1 = nullptr, *last_d2 = nullptr;
@@ -100,7 +70,7 @@ void sweep_tiles(fcs_sweep* s) {
     n[q] = s->tasks[q].n;
     nl[q] = s->tasks[q].nrow * s->tasks[q].ncomp;
   }
-  gemm_build_tiles(s->precision, s->var, n.data(), nl.data(), s->tasks.size(), s->tiles);
+  gemm_build_tiles(s->var, n.data(), nl.data(), s->tasks.size(), s->tiles);
 }
 }  // namespace
 
@@ -123,8 +93,8 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     s->poff.push_back(s->total);
     s->total += static_cast<int64_t>(ncomp) * a * b;
     s->npoints += static_cast<int64_t>(a) * b;
-    s->ops.index(a);
-    s->ops.index(b);
+    s->ops.add(a, FCS_OP_D1);
+    s->ops.add(b, FCS_OP_D1);
   }
   // tasks: per patch, q^1 (all rows of all components) and q^2; the
   // component stride is one (n2, n1) block
@@ -138,7 +108,7 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     t.s_stride = 1;
     t.nrow = b;
     t.n = a;
-    t.op = s->ops.index(a);
+    t.op = s->ops.add(a, FCS_OP_D1);
     t.src = reinterpret_cast<const double*>(static_cast<intptr_t>(s->poff[p]));  // offsets; rebased at run
     t.dst = reinterpret_cast<double*>(static_cast<intptr_t>(s->poff[p]));
     s->tasks.push_back(t);
@@ -146,7 +116,7 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     t.s_stride = a;
     t.nrow = a;
     t.n = b;
-    t.op = s->ops.index(b);
+    t.op = s->ops.add(b, FCS_OP_D1);
     s->tasks.push_back(t);
   }
   sweep_tiles(s.get());
@@ -159,6 +129,7 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
   };
   s->o_off = take(s->ops.off.size() * 8);
   s->o_roff = take(s->ops.roff.size() * 8);
+  s->o_ld = take(s->ops.ld.size() * 4);
   s->o_f64 = take(s->ops.elems * 8);
   s->o_row = take(s->ops.rows * 8);
   s->o_f32 = take(precision == 1 ? s->ops.elems * 4 : 0);
@@ -187,39 +158,23 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   if (!s || !workspace || bytes < s->need || reinterpret_cast<uintptr_t>(workspace) % kAlign) return FCS_EINVAL;
   s->ws = static_cast<char*>(workspace);
   s->stream = static_cast<hipStream_t>(stream);
-  std::vector<double> f64(s->ops.elems), rows(s->ops.rows);
-  for (size_t q = 0; q < s->ops.n.size(); ++q) {
-    const std::vector<double>* op = fc_operator(s->ops.n[q], s->d, s->C, FCS_OP_D1);
-    if (!op) return FCS_EINVAL;
-    std::copy(op->begin(), op->end(), f64.begin() + s->ops.off[q]);
-    int n = s->ops.n[q];
-    for (int t = 0; t < n; ++t) {
-      double r = 0;
-      for (int k = 0; k < n; ++k) r += (*op)[static_cast<size_t>(t) * n + k];
-      rows[s->ops.roff[q] + t] = r;
-    }
-  }
+  std::vector<double> f64, rows;
+  if (!s->ops.fill(s->d, s->C, f64, rows)) return FCS_EINVAL;
   std::vector<float> f32;
   std::vector<uint16_t> bhi, blo;
   hipStream_t st = s->stream;
   if (hipMemcpyAsync(s->ws + s->o_off, s->ops.off.data(), s->ops.off.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_roff, s->ops.roff.data(), s->ops.roff.size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(s->ws + s->o_ld, s->ops.ld.data(), s->ops.ld.size() * 4, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_f64, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_row, rows.data(), rows.size() * 8, hipMemcpyHostToDevice, st))
     return FCS_EHIP;
   if (s->precision == 1) {
-    f32.resize(f64.size());
-    for (size_t q = 0; q < f64.size(); ++q) f32[q] = static_cast<float>(f64[q]);
+    f32.assign(f64.begin(), f64.end());
     if (hipMemcpyAsync(s->ws + s->o_f32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, st)) return FCS_EHIP;
   }
   if (s->precision == 2) {
-    bhi.resize(f64.size());
-    blo.resize(f64.size());
-    for (size_t q = 0; q < f64.size(); ++q) {
-      float f = static_cast<float>(f64[q]);
-      bhi[q] = to_bf16(f);
-      blo[q] = to_bf16(f - from_bf16(bhi[q]));
-    }
+    split_bf16(f64, bhi, blo);
     if (hipMemcpyAsync(s->ws + s->o_bhi, bhi.data(), bhi.size() * 2, hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(s->ws + s->o_blo, blo.data(), blo.size() * 2, hipMemcpyHostToDevice, st))
       return FCS_EHIP;
@@ -230,6 +185,7 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   if (hipStreamSynchronize(st)) return FCS_EHIP;
   s->tab.off = reinterpret_cast<const int64_t*>(s->ws + s->o_off);
   s->tab.roff = reinterpret_cast<const int64_t*>(s->ws + s->o_roff);
+  s->tab.ld = reinterpret_cast<const int32_t*>(s->ws + s->o_ld);
   s->tab.f64 = reinterpret_cast<const double*>(s->ws + s->o_f64);
   s->tab.rowsum = reinterpret_cast<const double*>(s->ws + s->o_row);
   s->tab.f32 = reinterpret_cast<const float*>(s->ws + s->o_f32);
@@ -407,8 +363,8 @@ extern "C" fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int
 // ------------------------------------------------------------------ lines
 extern "C" size_t fcs_lines_workspace(int32_t n, int64_t nlines) {
   if (n <= 0 || nlines <= 0) return 0;
-  int64_t ntiles = ((nlines + 63) / 64) * ((n + 63) / 64);
-  return align_up(static_cast<size_t>(n) * n * 8) + align_up(64) + align_up(sizeof(GemmTask)) +
+  const int64_t ntiles = ((nlines + 63) / 64) * ((n + 63) / 64);
+  return align_up(static_cast<size_t>(op_rows(n)) * op_ld(n) * 8) + align_up(64) + align_up(sizeof(GemmTask)) +
          align_up(static_cast<size_t>(ntiles) * sizeof(GemmTile));
 }
 
@@ -416,13 +372,20 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
                                       const double* in, double* out, void* workspace, size_t bytes, void* stream) {
   if (!in || !out || !workspace || nlines <= 0 || nlines > (1ll << 31) / 1024) return FCS_EINVAL;
   if (bytes < fcs_lines_workspace(n, nlines) || reinterpret_cast<uintptr_t>(workspace) % kAlign) return FCS_EINVAL;
-  const std::vector<double>* op = fc_operator(n, d, C, kind);
-  if (!op) return FCS_EINVAL;
+  if (d < 1 || d > 12 || C < 4 || C > 64 || kind < FCS_OP_D1 || kind > FCS_OP_FILTER) return FCS_EINVAL;
+  OpPack pk;
+  pk.add(n, kind);
+  std::vector<double> f64, rows;
+  if (!pk.fill(d, C, f64, rows)) return FCS_EINVAL;
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* ws = static_cast<char*>(workspace);
-  size_t o_op = 0, o_off = align_up(static_cast<size_t>(n) * n * 8), o_task = o_off + align_up(64),
-         o_tile = o_task + align_up(sizeof(GemmTask));
-  int64_t zero[2] = {0, 0};
+  // small tables: operator offset (8 B), row-sum offset (8 B), leading dimension (4 B)
+  struct {
+    int64_t off, roff;
+    int32_t ld, pad;
+  } small{0, 0, pk.ld[0], 0};
+  const size_t o_op = 0, o_small = align_up(f64.size() * 8), o_task = o_small + align_up(64),
+               o_tile = o_task + align_up(sizeof(GemmTask));
   GemmTask t{};
   t.src = in;
   t.dst = out;
@@ -434,18 +397,20 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
   t.n = n;
   t.op = 0;
   std::vector<GemmTile> tiles;
-  for (int t0 = 0; t0 < n; t0 += gemm_outputs_per_tile(GemmVariant{}))
+  const GemmVariant v{};
+  for (int t0 = 0; t0 < n; t0 += gemm_outputs_per_tile(v))
     for (int64_t l0 = 0; l0 < nlines; l0 += gemm_lines_per_tile()) tiles.push_back({0, static_cast<int32_t>(l0), t0, 0});
-  if (hipMemcpyAsync(ws + o_op, op->data(), op->size() * 8, hipMemcpyHostToDevice, st) ||
-      hipMemcpyAsync(ws + o_off, zero, 16, hipMemcpyHostToDevice, st) ||
+  if (hipMemcpyAsync(ws + o_op, f64.data(), f64.size() * 8, hipMemcpyHostToDevice, st) ||
+      hipMemcpyAsync(ws + o_small, &small, sizeof(small), hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(ws + o_task, &t, sizeof(t), hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(ws + o_tile, tiles.data(), tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice, st))
     return FCS_EHIP;
   OpTables tab{};
-  tab.off = reinterpret_cast<const int64_t*>(ws + o_off);
-  tab.roff = reinterpret_cast<const int64_t*>(ws + o_off);
+  tab.off = reinterpret_cast<const int64_t*>(ws + o_small);
+  tab.roff = reinterpret_cast<const int64_t*>(ws + o_small + 8);
+  tab.ld = reinterpret_cast<const int32_t*>(ws + o_small + 16);
   tab.f64 = reinterpret_cast<const double*>(ws + o_op);
-  if (launch_gemm(0, GemmVariant{}, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
+  if (launch_gemm(0, v, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
                   static_cast<int>(tiles.size()), tab, st) != hipSuccess)
     return FCS_EHIP;
   // the host staging vectors must outlive the copies

@@ -1,4 +1,5 @@
-// Launch interface of the grouped FC contraction kernels.
+// Launch interface of the grouped FC contraction kernels and the host-side
+// packing of their operator tables.
 #pragma once
 #include <cstddef>
 #include <vector>
@@ -6,35 +7,43 @@
 #include "kernels.h"
 
 namespace fcs {
-// precision: 0 FP64, 1 FP32, 2 split BF16 (see gemm.hip).
-// Tile shape of a contraction launch: tb 16-output blocks per wave (a
-// workgroup covers 64 lines x 64 tb outputs), register prefetch on or off.
-// kind 1: lines in registers (each wave owns 16 lines and nb 16-output
-// blocks; the workgroup covers 64 lines x 16 nb outputs).
-// kind 2: operator-stationary (the workgroup keeps an operator tile of up to
-// lds_kb KiB in LDS and streams `group` 64-line blocks through it).
+
+// Operator tables are stored zero-padded: operator k occupies
+// op_rows(n) x op_ld(n) elements (row-major, leading dimension op_ld), so a
+// contraction tile never tests operator bounds.  The padding is sized for the
+// largest tile (128 outputs) and the deepest chunk (32 columns).
+constexpr int kOpRowPad = 128;
+constexpr int kOpColPad = 32;
+inline int op_ld(int n) { return (n + kOpColPad - 1) / kOpColPad * kOpColPad; }
+inline int op_rows(int n) { return (n + kOpRowPad - 1) / kOpRowPad * kOpRowPad; }
+
+// A set of distinct (length, kind) operators and their packed layout.
+struct OpPack {
+  std::vector<int32_t> n, kind, ld;
+  std::vector<int64_t> off, roff;  // element offset of each operator, of its row sums
+  int64_t elems = 0, rows = 0;
+  int add(int len, int k);  // index of (len, k), appended if new
+  // FP64 tables (padded operators and row sums) for FC parameters (d, C);
+  // false if an operator cannot be built.
+  bool fill(int d, int C, std::vector<double>& f64, std::vector<double>& rowsum) const;
+};
+// Round-to-nearest-even split of x (as FP32) into bf16 hi + lo.
+void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::vector<uint16_t>& lo);
+
+// Tile shape of a contraction launch: a workgroup covers 64 lines and 64 tb
+// outputs (tb = 1 or 2) and walks the operator depth in chunks of kc
+// (16 or 32; the split-BF16 kernel always uses 32).
 struct GemmVariant {
   int tb = 1;
-  bool prefetch = false;
-  int kind = 0;
-  int nb = 4;
-  int lds_kb = 64;
-  int group = 4;
-  size_t dyn_lds = 0;  // set by gemm_build_tiles
+  int kc = 16;
 };
-// Tiles of one task set (operator sizes n, lines nrow * ncomp per task) for
-// a variant; kind 2 encodes the output range and the line-block count in
-// the tile and sets v.dyn_lds.
-void gemm_build_tiles(int precision, GemmVariant& v, const int32_t* n, const int32_t* nlines, size_t ntasks,
-                      std::vector<GemmTile>& tiles);
-hipError_t launch_gemm_os(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
-                          int ntiles, const OpTables& ops, hipStream_t stream);
-// Output rows of an operator-stationary tile for a line length n.
-int gemm_os_rows(int precision, const GemmVariant& v, int n);
 hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
                        int ntiles, const OpTables& ops, hipStream_t stream);
 int gemm_lines_per_tile();
 int gemm_outputs_per_tile(const GemmVariant& v);
+// Tiles of one task set (operator sizes n, lines nrow * ncomp per task).
+void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nlines, size_t ntasks,
+                      std::vector<GemmTile>& tiles);
 // Candidate variants for the autotuner.
 const GemmVariant* gemm_variants(int precision, int* count);
 }  // namespace fcs

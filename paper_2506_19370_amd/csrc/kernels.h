@@ -8,11 +8,9 @@ namespace fcs {
 
 // One set of lines that share a line length, run position and operator:
 // out[line][t] = sum_s Op[t][s] in[line][s].  Lines are numbered with the
-// component fastest: line = r * ncomp + c addresses element
-// base + c * comp_stride + r * row_stride + s * s_stride.
-// flux != 0: the operand is not read but computed from the conserved state
-// (src = state, 4 components): component c of a fx + b fy (the Euler fluxes
-// of Sec. 2 contracted with constant metric terms of an affine subpatch).
+// row fastest: line = c * nrow + r addresses element
+// base + c * comp_stride + r * row_stride + s * s_stride, so that along q^2
+// (row_stride 1) neighbouring lines are neighbouring doubles.
 struct GemmTask {
   const double* src;
   double* dst;
@@ -21,21 +19,18 @@ struct GemmTask {
   int32_t nrow, ncomp;
   int32_t n;       // line length = operator size
   int32_t op;      // operator index (into the operator tables)
-  int32_t flux;    // 0: plain operand; 1: affine Euler flux from the state
-  int32_t pad;
-  double fa, fb;   // metric pair of the flux operand
-  double gm1;      // gamma - 1
 };
 
 struct GemmTile {
   int32_t task, line0, t0, pad;
 };
 
-// Operator tables: FP64, FP32 and split BF16 copies of every dense operator,
-// and FP64 row sums (used to take the line offset out of the split-BF16
-// products exactly).
+// Operator tables: FP64, FP32 and split BF16 copies of every dense operator
+// (zero-padded, row-major with leading dimension ld[k]), and FP64 row sums
+// (used to take the line offset out of the split-BF16 products exactly).
 struct OpTables {
-  const int64_t* off;       // element offset of operator k (n*n elements)
+  const int64_t* off;       // element offset of operator k
+  const int32_t* ld;        // leading dimension of operator k
   const double* f64;
   const float* f32;
   const uint16_t* bhi;
