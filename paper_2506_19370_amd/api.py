@@ -39,6 +39,57 @@ class SolverParams:
     vortex: tuple = (5.0, 5.0, 5.0, 1.0, 1.0)
 
 
+def create_context(specs, prm: SolverParams) -> ctypes.c_void_p:
+    """fcs_create for a list of subpatch specs (host only: grids, metrics,
+    operators and connectivity; no device memory).  Returns the context
+    handle; the caller releases it with fcs_destroy (Solver does)."""
+    keep = []
+    cp = L.Params()
+    cp.gamma, cp.cfl, cp.c_mu, cp.dt_fixed = prm.gamma, prm.cfl, prm.c_mu, prm.dt_fixed
+    cp.fc_d, cp.fc_C, cp.n_f, cp.n_v = prm.fc_d, prm.fc_C, prm.n_f, prm.n_v
+    cp.precision = L.PREC[prm.precision]
+    cp.av_mode = L.AV[prm.av]
+    cp.filter = int(bool(prm.filter))
+    cp.use_graph = int(bool(prm.use_graph))
+    cp.autotune = int(bool(prm.autotune))
+    if prm.sdnn_weights is not None:
+        w = np.ascontiguousarray(prm.sdnn_weights, dtype=np.float32)
+        if w.size != L.SDNN_NPARAM:
+            raise ValueError("SDNN weights must hold %d floats" % L.SDNN_NPARAM)
+        keep.append(w)
+        cp.sdnn_weights = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+    cp.vortex = (ctypes.c_double * 5)(*prm.vortex)
+    descs = (L.PatchDesc * len(specs))()
+    for q, s in enumerate(specs):
+        x = np.ascontiguousarray(s.x, dtype=np.float64)
+        y = np.ascontiguousarray(s.y, dtype=np.float64)
+        keep += [x, y]
+        d = descs[q]
+        d.type = L.PATCH.get(getattr(s, "kind", "I"), 0)
+        d.n2, d.n1 = x.shape
+        d.x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        d.y = y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        if s.mask is not None:
+            m = np.ascontiguousarray(s.mask, dtype=np.uint8)
+            keep.append(m)
+            d.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+        for k, side in enumerate("WESN"):
+            v = s.sides[side]
+            d.side[k] = L.SIDE[v] if isinstance(v, str) else int(v)
+        d.notch = L.SIDE[s.notch] if isinstance(s.notch, str) else int(s.notch)
+        inflow = s.inflow if s.inflow is not None else (1.0, 0.0, 0.0, 1.0)
+        for k in range(4):
+            d.inflow[k] = float(inflow[k])
+    h = ctypes.c_void_p()
+    st = L.fcs_create(ctypes.byref(cp), len(specs), descs, ctypes.byref(h))
+    if st != L.FCS_OK:
+        msg = L.fcs_last_error(h).decode() if h.value else ""
+        if h.value:
+            L.fcs_destroy(h)
+        raise L.FcsError(st, msg)
+    return h
+
+
 class Solver:
     """Subpatch set + state on one GPU (create / bind / set state / advance /
     query).  ``specs``: objects with x, y (n2, n1), mask, sides (dict W/E/S/N
@@ -48,53 +99,9 @@ class Solver:
         self.prm = prm
         self.specs = list(specs)
         self.device = torch.device(device)
-        self._keep = []
-        cp = L.Params()
-        cp.gamma, cp.cfl, cp.c_mu, cp.dt_fixed = prm.gamma, prm.cfl, prm.c_mu, prm.dt_fixed
-        cp.fc_d, cp.fc_C, cp.n_f, cp.n_v = prm.fc_d, prm.fc_C, prm.n_f, prm.n_v
-        cp.precision = L.PREC[prm.precision]
-        cp.av_mode = L.AV[prm.av]
-        cp.filter = int(bool(prm.filter))
-        cp.use_graph = int(bool(prm.use_graph))
-        cp.autotune = int(bool(prm.autotune))
-        if prm.sdnn_weights is not None:
-            w = np.ascontiguousarray(prm.sdnn_weights, dtype=np.float32)
-            if w.size != L.SDNN_NPARAM:
-                raise ValueError("SDNN weights must hold %d floats" % L.SDNN_NPARAM)
-            self._keep.append(w)
-            cp.sdnn_weights = w.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
-        cp.vortex = (ctypes.c_double * 5)(*prm.vortex)
-        descs = (L.PatchDesc * len(self.specs))()
-        for q, s in enumerate(self.specs):
-            x = np.ascontiguousarray(s.x, dtype=np.float64)
-            y = np.ascontiguousarray(s.y, dtype=np.float64)
-            self._keep += [x, y]
-            d = descs[q]
-            d.type = L.PATCH.get(getattr(s, "kind", "I"), 0)
-            d.n2, d.n1 = x.shape
-            d.x = x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            d.y = y.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
-            if s.mask is not None:
-                m = np.ascontiguousarray(s.mask, dtype=np.uint8)
-                self._keep.append(m)
-                d.mask = m.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
-            for k, side in enumerate("WESN"):
-                v = s.sides[side]
-                d.side[k] = L.SIDE[v] if isinstance(v, str) else int(v)
-            d.notch = L.SIDE[s.notch] if isinstance(s.notch, str) else int(s.notch)
-            inflow = s.inflow if s.inflow is not None else (1.0, 0.0, 0.0, 1.0)
-            for k in range(4):
-                d.inflow[k] = float(inflow[k])
-        h = ctypes.c_void_p()
-        st = L.fcs_create(ctypes.byref(cp), len(self.specs), descs, ctypes.byref(h))
+        self.h = None
+        h = create_context(self.specs, prm)
         self.h = h
-        if st != L.FCS_OK:
-            msg = L.fcs_last_error(h).decode() if h.value else ""
-            if h.value:
-                L.fcs_destroy(h)
-            self.h = None
-            raise L.FcsError(st, msg)
-        self._keep = []
         nbytes = ctypes.c_size_t()
         L.check(L.fcs_workspace_size(h, ctypes.byref(nbytes)), h)
         self.workspace = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.device)

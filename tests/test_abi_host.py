@@ -1,0 +1,117 @@
+"""Host-side checks of the C ABI (no GPU): every symbol the header declares
+is exported, the host FC construction agrees with the oracle's independent
+construction, and subpatch-set creation validates its input."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fcsdnn.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    names = set()
+    for decl in text.split(";"):
+        if "typedef" in decl or "enum" in decl or "struct" in decl and "{" in decl:
+            continue
+        m = re.search(r"\b(fcs_\w+)\s*\(", decl)
+        if m:
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_header_declares_the_entry_points():
+    names = header_functions()
+    for required in ("fcs_create", "fcs_bind", "fcs_set_state", "fcs_advance", "fcs_get_field", "fcs_destroy",
+                     "fcs_sweep_run", "fcs_sdnn_train_step", "fcs_sdnn_infer"):
+        assert required in names
+    assert len(names) >= 25
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2506_19370_amd import _lib as L
+    lib = ctypes.CDLL(L.LIBPATH)
+    missing = [n for n in header_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+@pytest.mark.parametrize("d", [2, 5])
+def test_fc_continuation_matches_oracle(d):
+    from oracle import fcgram
+    import paper_2506_19370_amd as F
+    Q, A = F.fc_continuation(d, 27)
+    ref = fcgram.continuation_data(d, 27)
+    # Q^T Q = I, and the continuation of raw matching values B = A Q^T is
+    # independent of the sign convention of the Gram polynomials.  The
+    # continuation points lie between the two fitted intervals, where the
+    # least-squares fit is ill-conditioned: the library solves it in 113-bit
+    # arithmetic, the oracle in 256-bit, and single entries then agree to
+    # about 1e-10 of the largest one (d = 2) while the fits themselves match
+    # to 1e-16.
+    assert np.abs(Q.T @ Q - np.eye(d)).max() < 1e-13
+    B = A @ Q.T
+    scale = np.abs(ref["B"]).max()
+    assert np.abs(B - ref["B"]).max() < 1e-9 * scale
+
+
+@pytest.mark.parametrize("n,d,kind", [(12, 2, "d1"), (37, 5, "d1"), (101, 2, "d1"), (101, 5, "d2"),
+                                      (64, 2, "filter"), (150, 5, "d1")])
+def test_fc_operator_matches_oracle(n, d, kind):
+    from oracle import fcgram
+    import paper_2506_19370_amd as F
+    got = F.fc_operator(n, d, 27, kind)
+    ref = fcgram.dense_operator(n, d, 27, kind)
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() < 1e-11 * scale
+
+
+def test_fc_operator_rejects_bad_arguments():
+    from paper_2506_19370_amd import _lib as L
+    out = np.zeros(16)
+    assert L.fcs_fc_operator(4, 0, 27, 0, out.ctypes.data) == L.FCS_EINVAL
+    assert L.fcs_fc_operator(4, 2, 200, 0, out.ctypes.data) == L.FCS_EINVAL
+    assert L.fcs_fc_operator(4, 2, 27, 0, None) == L.FCS_EINVAL
+
+
+def _create(specs, **kw):
+    from paper_2506_19370_amd.api import SolverParams, create_context
+    return create_context(specs, SolverParams(**kw))
+
+
+def test_create_step_channel_and_workspace_size():
+    from paper_2506_19370_amd import _lib as L
+    specs = W.step_channel()
+    h = _create(specs, fc_d=2, fc_C=27, av="modal", filter=True)
+    try:
+        nbytes = ctypes.c_size_t()
+        assert L.fcs_workspace_size(h, ctypes.byref(nbytes)) == L.FCS_OK
+        npts = sum(s.npoints() for s in specs)
+        # at least the three state copies, fluxes and derivatives in FP64
+        assert nbytes.value > (3 * 4 + 3 * 8) * 8 * npts
+    finally:
+        L.fcs_destroy(h)
+
+
+def test_create_reports_missing_donors():
+    from paper_2506_19370_amd import _lib as L
+    specs = [s for s in W.step_channel() if s.kind != "C1"]
+    with pytest.raises(L.FcsError) as e:
+        _create(specs, fc_d=2, fc_C=27)
+    assert e.value.status == L.FCS_EOVERLAP
+
+
+def test_create_rejects_invalid_parameters():
+    from paper_2506_19370_amd import _lib as L
+    specs = W.vortex_box(41)
+    for bad in ({"fc_d": 0}, {"cfl": -1.0}, {"n_f": 0}):
+        with pytest.raises(L.FcsError) as e:
+            _create(specs, **bad)
+        assert e.value.status == L.FCS_EINVAL
