@@ -92,7 +92,7 @@ struct fcs_ctx {
   std::vector<int32_t> iptr, bptr;
   std::vector<double> ival, bval;
   std::vector<BcEntry> bc;
-  bool flux_kernel = false;  // some subpatch is not affine
+  std::vector<int32_t> bcidx;  // entry of each boundary point
   std::vector<double> metric_host[10];  // t1x t1y t2x t2y g11 g12 g22 lap1 lap2 hx
   std::vector<double> basis, wdil;
   std::vector<uint8_t> tau_host;
@@ -383,6 +383,12 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
         e.y = g.y[k];
       }
   }
+  // boundary points are flagged so the stage kernel applies their entry
+  c->bcidx.assign(P, 0);
+  for (size_t q = 0; q < c->bc.size(); ++q) {
+    c->bcidx[c->bc[q].k] = static_cast<int32_t>(q);
+    c->flags[c->bc[q].k] |= kBoundary;
+  }
   // communication tables
   std::vector<InterpRow> rows;
   if (npatch > 1 && !build_fringe_rows(c->grids, rows, err)) {
@@ -427,7 +433,6 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   // contraction tasks
   for (int q = 0; q < npatch; ++q) {
     const Grid& g = c->grids[q];
-    c->flux_kernel = true;
     if (g.affine) {
       // contravariant fluxes a f_x + b f_y with the constant metric terms
       add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_F, 0, A_DF1, 0, 4);
@@ -497,6 +502,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BCOL"] = cv.take(c->bcol.size() * 8);
   o["BVAL"] = cv.take(c->bval.size() * D);
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
+  o["BCIDX"] = cv.take(P * 4);
   o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
   o["BASIS"] = cv.take(256 * D);
   o["WDIL"] = cv.take((p.n_v + 1) * D);
@@ -623,6 +629,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"BCOL", c->bcol.data(), c->bcol.size() * 8},
       {"BVAL", c->bval.data(), c->bval.size() * 8},
       {"BC", c->bc.data(), c->bc.size() * sizeof(BcEntry)},
+      {"BCIDX", c->bcidx.data(), c->bcidx.size() * 4},
       {"SDNN", c->sdnn.data(), c->sdnn.size() * 4},
       {"BASIS", c->basis.data(), c->basis.size() * 8},
       {"WDIL", c->wdil.data(), c->wdil.size() * 8},
@@ -744,8 +751,11 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
   const double* met[10];
   for (int m = 0; m < 10; ++m) met[m] = c->dptr<double>(("MET" + std::to_string(m)).c_str());
-  if (c->flux_kernel)
-    HIPCHK(c, launch_flux(in, c->arr[A_F], flags, met[0], met[1], met[2], met[3], P, p.gamma - 1.0, c->stream));
+  // fluxes of the stage input: computed here at the first stage of a step
+  // (after the filter); later stages receive them from the previous stage's
+  // update and fringe fill
+  FluxOut fo{c->arr[A_F], met[0], met[1], met[2], met[3], p.gamma - 1.0};
+  if (s == 0) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
   fcs_status st;
   c->prof_stage = s;
   if ((st = run_gemm(c, PH_EULER, variant, p.precision, true)) != FCS_OK) return st;
@@ -792,15 +802,22 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   double* scal = c->dptr<double>("SCAL");
   a.dt = scal + 1;
   a.bad_flag = reinterpret_cast<int*>(scal + 3);
-  HIPCHK(c, launch_stage(a, c->stream));
   double frac[5];
   stage_fractions(frac);
-  VortexArgs vx{p.vortex[0], p.vortex[1], p.vortex[2], p.vortex[3], p.vortex[4]};
-  HIPCHK(c, launch_bc(outp, c->dptr<BcEntry>("BC"), static_cast<int>(c->bc.size()), P, p.gamma, scal, scal + 1,
-                      frac[s], vx, c->stream));
-  HIPCHK(c, launch_fringe(outp, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
+  a.bcs.bc = c->dptr<BcEntry>("BC");
+  a.bcs.bcidx = c->dptr<int32_t>("BCIDX");
+  a.bcs.gamma = p.gamma;
+  a.bcs.t = scal;
+  a.bcs.frac = frac[s];
+  a.bcs.vortex = VortexArgs{p.vortex[0], p.vortex[1], p.vortex[2], p.vortex[3], p.vortex[4]};
+  // the last stage's output starts the next step, whose fluxes follow the filter
+  FluxOut next = fo;
+  if (s == 4) next.F = nullptr;
+  a.flux = next;
+  HIPCHK(c, launch_stage(a, c->stream));
+  HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
                           c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
-                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), P, c->stream));
+                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), P, next, c->stream));
   c->cur = outp;
   return FCS_OK;
 }

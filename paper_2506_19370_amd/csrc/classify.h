@@ -1,8 +1,8 @@
 // Device functions of the smoothness classification of a 16-point window
 // of the proxy variable (Sec. 4 and Alg. 3): normalization, the SDNN
 // (16-64-64-3 MLP, bf16 inputs / weights / hidden activations, FP32
-// accumulation, argmax with ties to the higher class) and the modal-decay
-// fallback (energy fraction of the modes of degree >= 8 in the orthonormal
+// accumulation, argmax with ties to the higher class) on the matrix cores,
+// and the modal-decay fallback (energy fraction of the modes of degree >= 8 in the orthonormal
 // discrete polynomial basis; tau = 2 above 10^-1.5, 1 above 10^-3).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -45,51 +45,141 @@ __device__ __forceinline__ int classify_modal(const double* v, const double* bas
   return frac > 0.031622776601683791 ? 2 : (frac > 1e-3 ? 1 : 0);
 }
 
-// W: bf16-rounded weights and FP32 biases in the parameter-blob order.
-__device__ __forceinline__ int classify_sdnn(const double* v, const float* W, float* logits = nullptr) {
-  double xd[16];
-  if (!normalize_window(v, xd)) {
-    if (logits) logits[0] = logits[1] = logits[2] = 0.0f;
-    return 0;
-  }
+// ---------------------------------------------------------------------------
+// SDNN inference on the matrix cores, 16 windows per wave.
+//
+// Lane l of a wave owns window l % 16 and its input features 4 g .. 4 g + 3
+// (g = l / 16).  Layer k computes Z_k^T = W_k H_{k-1}^T (hidden units as MFMA
+// rows, windows as columns), so lane l receives the pre-activations of
+// hidden units 4 g + r (r < 4) of every 16-row tile for window l % 16.  Two
+// such tiles form the B operand of the next 16x16x32 product directly: the
+// sum over hidden units may run in any order, so the k slots of lane group g
+// are taken as hidden units {4 g .. 4 g + 3} of the first tile and
+// {4 g .. 4 g + 3} of the second, and the weight fragments are gathered in
+// that same order.  Weights and biases stay in registers for the whole
+// kernel.  Arithmetic: bf16 inputs, weights and hidden activations, FP32
+// accumulation (the products' summation order differs from a sequential
+// loop only by FP32 rounding).
+typedef short sdnn_s16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 sdnn_bf16x8 __attribute__((ext_vector_type(8)));
+typedef float sdnn_f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+  return static_cast<uint16_t>(__float_as_uint(bf16_round(f)) >> 16);
+}
+
+struct SdnnFrag {
+  sdnn_s16x4 w1[4];       // layer 1, hidden tile ht
+  sdnn_bf16x8 w2[4][2];   // layer 2, [output tile][input block]
+  sdnn_bf16x8 w3[2];      // layer 3 (rows >= 3 zero), [input block]
+  float b1[4][4], b2[4][4], b3[4];
+};
+
+// Hidden unit of k slot j of lane group g in input block kb.
+__device__ __forceinline__ int sdnn_slot(int kb, int g, int j) { return 32 * kb + (j < 4 ? 4 * g + j : 12 + 4 * g + j); }
+
+// W: parameter blob (W1 64x16, b1, W2 64x64, b2, W3 3x64, b3), FP32.
+__device__ __forceinline__ void load_sdnn_frag(const float* __restrict__ W, SdnnFrag& F) {
   const float* W1 = W;
-  const float* b1 = W1 + 64 * 16;
-  const float* W2 = b1 + 64;
-  const float* b2 = W2 + 64 * 64;
-  const float* W3 = b2 + 64;
-  const float* b3 = W3 + 3 * 64;
-  float x[16], h1[64], h2[64], z[3];
-  for (int m = 0; m < 16; ++m) x[m] = bf16_round(static_cast<float>(xd[m]));
-  for (int o = 0; o < 64; ++o) {
-    float s = 0.0f;
-    for (int m = 0; m < 16; ++m) s = fmaf(W1[o * 16 + m], x[m], s);
-    h1[o] = bf16_round(fmaxf(s + b1[o], 0.0f));
+  const float* B1 = W1 + 64 * 16;
+  const float* W2 = B1 + 64;
+  const float* B2 = W2 + 64 * 64;
+  const float* W3 = B2 + 64;
+  const float* B3 = W3 + 3 * 64;
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+#pragma unroll
+  for (int ht = 0; ht < 4; ++ht)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) F.w1[ht][j] = static_cast<short>(bf16_bits(W1[(16 * ht + c) * 16 + 4 * g + j]));
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int h = sdnn_slot(kb, g, j);
+#pragma unroll
+      for (int mt = 0; mt < 4; ++mt)
+        F.w2[mt][kb][j] = __builtin_bit_cast(__bf16, bf16_bits(W2[(16 * mt + c) * 64 + h]));
+      F.w3[kb][j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(c < 3 ? bf16_bits(W3[c * 64 + h]) : 0));
+    }
+#pragma unroll
+  for (int ht = 0; ht < 4; ++ht)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      F.b1[ht][r] = B1[16 * ht + 4 * g + r];
+      F.b2[ht][r] = B2[16 * ht + 4 * g + r];
+    }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) F.b3[r] = (4 * g + r < 3) ? B3[4 * g + r] : 0.0f;
+}
+
+// Two 16-row tiles of pre-activations -> bf16 ReLU activations as one B
+// fragment (k slots in the order of sdnn_slot).
+__device__ __forceinline__ sdnn_bf16x8 sdnn_act(const sdnn_f32x4& za, const float* ba, const sdnn_f32x4& zb,
+                                                const float* bb) {
+  sdnn_bf16x8 h;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    h[j] = __builtin_bit_cast(__bf16, bf16_bits(fmaxf(za[j] + ba[j], 0.0f)));
+    h[4 + j] = __builtin_bit_cast(__bf16, bf16_bits(fmaxf(zb[j] + bb[j], 0.0f)));
   }
-  for (int o = 0; o < 64; ++o) {
-    float s = 0.0f;
-    for (int m = 0; m < 64; ++m) s = fmaf(W2[o * 64 + m], h1[m], s);
-    h2[o] = bf16_round(fmaxf(s + b2[o], 0.0f));
+  return h;
+}
+
+// One wave-wide evaluation of 16 windows.  x: this lane's four features
+// (already bf16-rounded).  On return lanes 0..15 hold the three logits of
+// window lane % 16 in z[0..2].
+__device__ __forceinline__ void sdnn_mfma(const SdnnFrag& F, const float (&x)[4], float (&z)[3]) {
+  sdnn_s16x4 xb;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) xb[j] = static_cast<short>(bf16_bits(x[j]));
+  const sdnn_f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+  sdnn_f32x4 z1[4];
+#pragma unroll
+  for (int ht = 0; ht < 4; ++ht) z1[ht] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(F.w1[ht], xb, zero, 0, 0, 0);
+  sdnn_bf16x8 h1[2];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) h1[kb] = sdnn_act(z1[2 * kb], F.b1[2 * kb], z1[2 * kb + 1], F.b1[2 * kb + 1]);
+  sdnn_f32x4 z2[4];
+#pragma unroll
+  for (int mt = 0; mt < 4; ++mt) {
+    z2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[mt][0], h1[0], zero, 0, 0, 0);
+    z2[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w2[mt][1], h1[1], z2[mt], 0, 0, 0);
   }
-  for (int o = 0; o < 3; ++o) {
-    float s = 0.0f;
-    for (int m = 0; m < 64; ++m) s = fmaf(W3[o * 64 + m], h2[m], s);
-    z[o] = s + b3[o];
-  }
-  if (logits)
-    for (int o = 0; o < 3; ++o) logits[o] = z[o];
+  sdnn_bf16x8 h2[2];
+#pragma unroll
+  for (int kb = 0; kb < 2; ++kb) h2[kb] = sdnn_act(z2[2 * kb], F.b2[2 * kb], z2[2 * kb + 1], F.b2[2 * kb + 1]);
+  sdnn_f32x4 z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[0], h2[0], zero, 0, 0, 0);
+  z3 = __builtin_amdgcn_mfma_f32_16x16x32_bf16(F.w3[1], h2[1], z3, 0, 0, 0);
+#pragma unroll
+  for (int o = 0; o < 3; ++o) z[o] = z3[o] + F.b3[o];
+}
+
+// Class from logits, ties to the higher class.
+__device__ __forceinline__ int sdnn_argmax(const float (&z)[3]) {
   int best = 2;
   if (z[1] > z[best]) best = 1;
   if (z[0] > z[best]) best = 0;
   return best;
 }
 
-// Load the parameter blob into LDS, rounding the weight matrices to bf16.
-__device__ __forceinline__ void load_sdnn_params(const float* src, float* dst, int nparam) {
-  const int w1 = 64 * 16, b1 = w1 + 64, w2 = b1 + 64 * 64, b2 = w2 + 64, w3 = b2 + 3 * 64;
-  for (int q = threadIdx.x; q < nparam; q += blockDim.x) {
-    bool weight = q < w1 || (q >= b1 && q < w2) || (q >= b2 && q < w3);
-    dst[q] = weight ? bf16_round(src[q]) : src[q];
-  }
+// Lane-distributed window normalisation: v holds this lane's 4 of the 16
+// window values (lanes l, l ^ 16, l ^ 32, l ^ 48 share a window).  Returns
+// false (flat window, class 0) when max - min < 1e-3 max(max |v|, 1).
+__device__ __forceinline__ bool sdnn_features(const double (&v)[4], float (&x)[4]) {
+  double lo = fmin(fmin(v[0], v[1]), fmin(v[2], v[3]));
+  double hi = fmax(fmax(v[0], v[1]), fmax(v[2], v[3]));
+  double am = fmax(fmax(fabs(v[0]), fabs(v[1])), fmax(fabs(v[2]), fabs(v[3])));
+  lo = fmin(lo, __shfl_xor(lo, 16));
+  hi = fmax(hi, __shfl_xor(hi, 16));
+  am = fmax(am, __shfl_xor(am, 16));
+  lo = fmin(lo, __shfl_xor(lo, 32));
+  hi = fmax(hi, __shfl_xor(hi, 32));
+  am = fmax(am, __shfl_xor(am, 32));
+  const double range = hi - lo;
+  const bool live = !(range < 1e-3 * fmax(am, 1.0));
+#pragma unroll
+  for (int j = 0; j < 4; ++j) x[j] = live ? bf16_round(static_cast<float>((v[j] - lo) / range)) : 0.0f;
+  return live;
 }
 
 }  // namespace fcs

@@ -49,7 +49,7 @@ struct PatchDev {
 };
 
 // Per-point flags.
-enum : uint8_t { kActive = 1, kFringe = 2, kXFringe = 4, kAffine = 8 };
+enum : uint8_t { kActive = 1, kFringe = 2, kXFringe = 4, kAffine = 8, kBoundary = 16 };
 
 // Boundary conditions of one point (Sec. 5 item 4): slip (zero normal
 // momentum, pressure kept; both momentum components zero at a corner of two

@@ -10,6 +10,24 @@ struct VortexArgs {
   double beta, x0, y0, u0, v0;
 };
 
+// Where a kernel that produces a state also stores the Euler fluxes of that
+// state as the next stage's contraction operands (F == nullptr: not at all).
+struct FluxOut {
+  double* F;
+  const double *t1x, *t1y, *t2x, *t2y;
+  double gm1;
+};
+
+// Boundary data applied by the stage kernel to the points flagged kBoundary.
+struct BcArgs {
+  const BcEntry* bc;
+  const int32_t* bcidx;  // entry of each point (points without one: unused)
+  double gamma;
+  const double* t;       // device time of the step start
+  double frac;           // stage time fraction of the step
+  VortexArgs vortex;
+};
+
 struct StageArgs {
   int64_t P;
   int stage;
@@ -25,6 +43,8 @@ struct StageArgs {
   const double *W1, *W2, *W11, *W22, *W12;
   const double* dt;
   int* bad_flag;
+  BcArgs bcs;
+  FluxOut flux;
 };
 
 struct ClassifyArgs {
@@ -66,13 +86,15 @@ struct ViscArgs {
   const double* bval;
 };
 
-hipError_t launch_flux(const double* U, double* F, const uint8_t* flags, const double* t1x, const double* t1y,
-                       const double* t2x, const double* t2y, int64_t P, double gm1, hipStream_t s);
+hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo, int64_t P, hipStream_t s);
+// Stage update, boundary conditions and (if a.flux.F) the fluxes of the new
+// state at every active point.
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
-hipError_t launch_bc(double* U, const BcEntry* bc, int nbc, int64_t P, double gamma, const double* t,
-                     const double* dt, double frac, const VortexArgs& v, hipStream_t s);
-hipError_t launch_fringe(double* U, const int64_t* copy_pairs, int ncopy, const int64_t* idst, const int32_t* iptr,
-                         const int64_t* icol, const double* ival, int ninterp, int64_t P, hipStream_t s);
+// Fringe fill (copy pairs and interpolation rows) and, if fo.F, the fluxes
+// of the filled points.
+hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
+                         const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
+                         const FluxOut& fo, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);

@@ -23,21 +23,19 @@ __device__ __forceinline__ double pressure(double r, double mx, double my, doubl
   return gm1 * (E - 0.5 * (mx * mx + my * my) / r);
 }
 
-__global__ void k_flux(const double* __restrict__ U, double* __restrict__ F, const uint8_t* __restrict__ flags,
-                       const double* __restrict__ t1x, const double* __restrict__ t1y,
-                       const double* __restrict__ t2x, const double* __restrict__ t2y, int64_t P, double gm1) {
-  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= P) return;
-  uint8_t f = flags[k];
+// Euler fluxes of one state as the 8 operand components of the stage
+// contraction: contravariant q^k_x f_x + q^k_y f_y on affine subpatches,
+// f_x and f_y otherwise; zero at inactive points.
+__device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t k, uint8_t f, double r, double mx,
+                                           double my, double E) {
   double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   if (f & kActive) {
-    double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
-    double p = pressure(r, mx, my, E, gm1);
-    double u = mx / r, w = my / r;
-    double fx[4] = {mx, mx * u + p, mx * w, u * (E + p)};
-    double fy[4] = {my, my * u, my * w + p, w * (E + p)};
+    const double p = pressure(r, mx, my, E, fo.gm1);
+    const double u = mx / r, w = my / r;
+    const double fx[4] = {mx, mx * u + p, mx * w, u * (E + p)};
+    const double fy[4] = {my, my * u, my * w + p, w * (E + p)};
     if (f & kAffine) {
-      double a = t1x[k], b = t1y[k], c = t2x[k], d = t2y[k];
+      const double a = fo.t1x[k], b = fo.t1y[k], c = fo.t2x[k], d = fo.t2y[k];
       for (int q = 0; q < 4; ++q) {
         v[q] = a * fx[q] + b * fy[q];
         v[4 + q] = c * fx[q] + d * fy[q];
@@ -49,7 +47,53 @@ __global__ void k_flux(const double* __restrict__ U, double* __restrict__ F, con
       }
     }
   }
-  for (int q = 0; q < 8; ++q) F[q * P + k] = v[q];
+  for (int q = 0; q < 8; ++q) fo.F[q * P + k] = v[q];
+}
+
+__global__ void k_flux(const double* __restrict__ U, const uint8_t* __restrict__ flags, FluxOut fo, int64_t P) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  store_flux(fo, P, k, flags[k], U[k], U[P + k], U[2 * P + k], U[3 * P + k]);
+}
+
+// Boundary conditions of one point (Sec. 5 item 4): slip (normal momentum
+// removed, pressure kept; zero momentum at a corner of two slip sides), then
+// Dirichlet data (fixed state, or the isentropic vortex at t).
+__device__ __forceinline__ void apply_bc(const BcEntry& b, double gamma, double t, const VortexArgs& v, double& r,
+                                         double& mx, double& my, double& E) {
+  const double gm1 = gamma - 1.0;
+  if (b.slip) {
+    const double p = gm1 * (E - 0.5 * (mx * mx + my * my) / r);
+    if (b.slip == 2) {
+      mx = 0.0;
+      my = 0.0;
+    } else {
+      const double mn = mx * b.nx + my * b.ny;
+      mx = mx - mn * b.nx;
+      my = my - mn * b.ny;
+    }
+    E = p / gm1 + 0.5 * (mx * mx + my * my) / r;
+  }
+  if (b.dirichlet == 1) {
+    r = b.e[0];
+    mx = b.e[1];
+    my = b.e[2];
+    E = b.e[3];
+  } else if (b.dirichlet == 2) {
+    const double pi = 3.141592653589793;
+    const double dx = b.x - v.x0 - v.u0 * t, dy = b.y - v.y0 - v.v0 * t;
+    const double r2 = dx * dx + dy * dy;
+    const double g = exp(0.5 * (1.0 - r2));
+    const double du = -v.beta / (2 * pi) * g * dy, dv = v.beta / (2 * pi) * g * dx;
+    const double T = 1.0 - (gamma - 1.0) * v.beta * v.beta / (8 * gamma * pi * pi) * exp(1.0 - r2);
+    const double rho = pow(T, 1.0 / (gamma - 1.0));
+    const double p = pow(rho, gamma);
+    const double u = v.u0 + du, w = v.v0 + dv;
+    r = rho;
+    mx = rho * u;
+    my = rho * w;
+    E = p / (gamma - 1.0) + 0.5 * rho * (u * u + w * w);
+  }
 }
 
 __global__ void k_stage(StageArgs a) {
@@ -59,6 +103,7 @@ __global__ void k_stage(StageArgs a) {
   const uint8_t f = a.flags[k];
   if (!(f & kActive)) {
     for (int q = 0; q < 4; ++q) a.out[q * P + k] = 0.0;
+    if (a.flux.F) store_flux(a.flux, P, k, f, 0.0, 0.0, 0.0, 0.0);
     return;
   }
   const double dt = *a.dt;
@@ -82,107 +127,74 @@ __global__ void k_stage(StageArgs a) {
       L[q] = L[q] + mu * lap + grad;
     }
   }
-  bool bad = false;
+  double o[4];
   for (int q = 0; q < 4; ++q) {
     const double in = a.in[q * P + k], u0 = a.U0[q * P + k];
-    double o;
     switch (a.stage) {
       case 0:
-        o = u0 + a.c[0] * dt * L[q];
+        o[q] = u0 + a.c[0] * dt * L[q];
         break;
       case 1:
-        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       case 2:
         a.acc[q * P + k] = a.c[4] * in;
-        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       case 3: {
         double acc = a.acc[q * P + k];
         a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
-        o = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       }
       default:
-        o = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
+        o[q] = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
         break;
     }
-    if (!isfinite(o)) bad = true;
-    a.out[q * P + k] = o;
   }
+  bool bad = false;
+  for (int q = 0; q < 4; ++q)
+    if (!isfinite(o[q])) bad = true;
   if (!bad) {
-    double r = a.out[k];
-    double p = pressure(r, a.out[P + k], a.out[2 * P + k], a.out[3 * P + k], a.gm1);
-    bad = !(r > 0.0) || !(p > 0.0);
+    const double p = pressure(o[0], o[1], o[2], o[3], a.gm1);
+    bad = !(o[0] > 0.0) || !(p > 0.0);
   }
   if (bad) *a.bad_flag = 1;
-}
-
-// Boundary conditions of one point: slip (normal momentum removed, pressure
-// kept; zero momentum at a corner of two slip sides), then Dirichlet data
-// (fixed state, or the isentropic vortex at t0 + frac * dt).
-__global__ void k_bc(double* __restrict__ U, const BcEntry* __restrict__ e, int n, int64_t P, double gamma,
-                     const double* __restrict__ tptr, const double* __restrict__ dtptr, double frac, VortexArgs v) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  const BcEntry b = e[q];
-  const int64_t k = b.k;
-  const double gm1 = gamma - 1.0;
-  if (b.slip) {
-    double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
-    double p = gm1 * (E - 0.5 * (mx * mx + my * my) / r);
-    if (b.slip == 2) {
-      mx = 0.0;
-      my = 0.0;
-    } else {
-      double mn = mx * b.nx + my * b.ny;
-      mx = mx - mn * b.nx;
-      my = my - mn * b.ny;
-    }
-    U[P + k] = mx;
-    U[2 * P + k] = my;
-    U[3 * P + k] = p / gm1 + 0.5 * (mx * mx + my * my) / r;
+  if (f & kBoundary) {
+    const double t = *a.bcs.t + a.bcs.frac * dt;
+    apply_bc(a.bcs.bc[a.bcs.bcidx[k]], a.bcs.gamma, t, a.bcs.vortex, o[0], o[1], o[2], o[3]);
   }
-  if (b.dirichlet == 1) {
-    for (int c = 0; c < 4; ++c) U[c * P + k] = b.e[c];
-  } else if (b.dirichlet == 2) {
-    const double t = *tptr + frac * *dtptr;
-    const double pi = 3.141592653589793;
-    double dx = b.x - v.x0 - v.u0 * t, dy = b.y - v.y0 - v.v0 * t;
-    double r2 = dx * dx + dy * dy;
-    double g = exp(0.5 * (1.0 - r2));
-    double du = -v.beta / (2 * pi) * g * dy, dv = v.beta / (2 * pi) * g * dx;
-    double T = 1.0 - (gamma - 1.0) * v.beta * v.beta / (8 * gamma * pi * pi) * exp(1.0 - r2);
-    double rho = pow(T, 1.0 / (gamma - 1.0));
-    double p = pow(rho, gamma);
-    double u = v.u0 + du, w = v.v0 + dv;
-    U[k] = rho;
-    U[P + k] = rho * u;
-    U[2 * P + k] = rho * w;
-    U[3 * P + k] = p / (gamma - 1.0) + 0.5 * rho * (u * u + w * w);
-  }
+  for (int q = 0; q < 4; ++q) a.out[q * P + k] = o[q];
+  if (a.flux.F) store_flux(a.flux, P, k, f, o[0], o[1], o[2], o[3]);
 }
 
-__global__ void k_copy_rows(double* __restrict__ U, const int64_t* __restrict__ pairs, int n, int64_t P,
-                            int ncomp) {
+// Fringe fill (Sec. 3.3): rows 0 .. ncopy-1 copy one donor value (common
+// lattice), the rest evaluate an interpolation row; donors are never
+// recipients, so all rows are independent.  The fluxes of each filled point
+// follow when fo.F is set.
+__global__ void k_fringe(double* __restrict__ U, const uint8_t* __restrict__ flags, const int64_t* __restrict__ pairs,
+                         int ncopy, const int64_t* __restrict__ dst, const int32_t* __restrict__ ptr,
+                         const int64_t* __restrict__ col, const double* __restrict__ val, int ninterp, int64_t P,
+                         FluxOut fo) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
-  int64_t dst = pairs[2 * q], src = pairs[2 * q + 1];
-  for (int c = 0; c < ncomp; ++c) U[c * P + dst] = U[c * P + src];
-}
-
-__global__ void k_interp_rows(double* __restrict__ U, const int64_t* __restrict__ dst,
-                              const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
-                              const double* __restrict__ val, int n, int64_t P, int ncomp) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
+  if (q >= ncopy + ninterp) return;
   double s[4] = {0, 0, 0, 0};
-  for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
-    const double w = val[e];
-    const int64_t c = col[e];
-    for (int m = 0; m < ncomp; ++m) s[m] += w * U[m * P + c];
+  int64_t k;
+  if (q < ncopy) {
+    k = pairs[2 * q];
+    const int64_t src = pairs[2 * q + 1];
+    for (int m = 0; m < 4; ++m) s[m] = U[m * P + src];
+  } else {
+    q -= ncopy;
+    k = dst[q];
+    for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
+      const double w = val[e];
+      const int64_t c = col[e];
+      for (int m = 0; m < 4; ++m) s[m] += w * U[m * P + c];
+    }
   }
-  for (int m = 0; m < ncomp; ++m) U[m * P + dst[q]] = s[m];
+  for (int m = 0; m < 4; ++m) U[m * P + k] = s[m];
+  if (fo.F) store_flux(fo, P, k, flags[k], s[0], s[1], s[2], s[3]);
 }
 
 // Proxy (Mach number) and |u| + a at every point.
@@ -202,50 +214,99 @@ __global__ void k_proxy(const double* __restrict__ U, const uint8_t* __restrict_
   spd[k] = speed + sqrt(gamma * p / r);
 }
 
+// Window geometry of point k along direction dir: start index of the
+// 16-point window (shifted to stay inside the run) as element base and
+// stride; false when the point is inactive or its run is shorter than 16.
+__device__ __forceinline__ bool window_at(const ClassifyArgs& a, int64_t k, uint8_t f, int dir, int64_t& base,
+                                          int64_t& stride) {
+  if (!(f & kActive)) return false;
+  const PatchDev pd = a.patches[a.pid[k]];
+  const int64_t loc = k - pd.offset;
+  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
+  const int2 run = dir == 0 ? a.rowrun[pd.row_run + j] : a.colrun[pd.col_run + i];
+  if (run.y < 16) return false;
+  const int pos = dir == 0 ? i : j;
+  const int ws = min(max(pos - 8, run.x), run.x + run.y - 16);
+  base = dir == 0 ? (pd.offset + static_cast<int64_t>(j) * pd.n1 + ws) : (pd.offset + static_cast<int64_t>(ws) * pd.n1 + i);
+  stride = dir == 0 ? 1 : pd.n1;
+  return true;
+}
+
+__device__ __forceinline__ double muhat_of(const ClassifyArgs& a, int64_t k, uint8_t f, int t0, int t1, double smax) {
+  const double alpha[3] = {0.0, 0.5, 1.0};
+  const double al = fmax(alpha[t0], alpha[t1]);
+  const bool keep = (f & kActive) && !(f & (kFringe | kXFringe));
+  return keep ? a.c_mu * a.hx[k] * smax * al : 0.0;
+}
+
+// Alg. 3 with the modal fallback (mode 1) or frozen classes (mode 3): one
+// point per thread.
 __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
-  __shared__ float W[FCS_SDNN_NPARAM_DEV];
-  if (a.mode == 2) {
-    load_sdnn_params(a.weights, W, FCS_SDNN_NPARAM_DEV);
-    __syncthreads();
-  }
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= a.P) return;
   const uint8_t f = a.flags[k];
-  const int pid = a.pid[k];
-  const PatchDev pd = a.patches[pid];
-  const int64_t loc = k - pd.offset;
-  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
   int tau[2] = {0, 0};
   double smax = 0.0;
-  const int2 rr = a.rowrun[pd.row_run + j];
-  const int2 cr = a.colrun[pd.col_run + i];
   double v[16];
-  if (f & kActive) {
-    for (int dir = 0; dir < 2; ++dir) {
-      int2 run = dir == 0 ? rr : cr;
-      if (run.y < 16) continue;
-      int pos = dir == 0 ? i : j;
-      int ws = min(max(pos - 8, run.x), run.x + run.y - 16);
-      int64_t base = dir == 0 ? (pd.offset + static_cast<int64_t>(j) * pd.n1 + ws)
-                              : (pd.offset + static_cast<int64_t>(ws) * pd.n1 + i);
-      int64_t stride = dir == 0 ? 1 : pd.n1;
-      for (int m = 0; m < 16; ++m) smax = fmax(smax, a.spd[base + m * stride]);
-      if (a.mode == 3) {
-        tau[dir] = a.tau[dir * a.P + k];
-      } else {
-        for (int m = 0; m < 16; ++m) v[m] = a.phi[base + m * stride];
-        tau[dir] = a.mode == 2 ? classify_sdnn(v, W) : classify_modal(v, a.basis);
-      }
+  for (int dir = 0; dir < 2; ++dir) {
+    int64_t base, stride;
+    if (!window_at(a, k, f, dir, base, stride)) continue;
+    for (int m = 0; m < 16; ++m) smax = fmax(smax, a.spd[base + m * stride]);
+    if (a.mode == 3) {
+      tau[dir] = a.tau[dir * a.P + k];
+    } else {
+      for (int m = 0; m < 16; ++m) v[m] = a.phi[base + m * stride];
+      tau[dir] = classify_modal(v, a.basis);
     }
   }
   if (a.mode != 3) {
     a.tau[k] = static_cast<uint8_t>(tau[0]);
     a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
   }
-  const double alpha[3] = {0.0, 0.5, 1.0};
-  double al = fmax(alpha[tau[0]], alpha[tau[1]]);
-  bool keep = (f & kActive) && !(f & (kFringe | kXFringe));
-  a.muhat[k] = keep ? a.c_mu * a.hx[k] * smax * al : 0.0;
+  a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
+}
+
+// Alg. 3 with the SDNN: each wave classifies the two windows of 64 points
+// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma); lanes
+// 0..15 write the classes and the preliminary viscosity of their points.
+__global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
+  SdnnFrag F;
+  load_sdnn_frag(a.weights, F);
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int64_t kw = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
+#pragma unroll 1
+  for (int pg = 0; pg < 4; ++pg) {
+    const int64_t k = kw + 16 * pg + c;
+    const uint8_t f = k < a.P ? a.flags[k] : 0;
+    int tau[2] = {0, 0};
+    double smax = 0.0;
+#pragma unroll
+    for (int dir = 0; dir < 2; ++dir) {
+      int64_t base = 0, stride = 0;
+      const bool valid = k < a.P && window_at(a, k, f, dir, base, stride);
+      double v[4], sp = 0.0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int64_t e = base + (4 * g + j) * stride;
+        v[j] = valid ? a.phi[e] : 0.0;
+        sp = fmax(sp, valid ? a.spd[e] : 0.0);
+      }
+      sp = fmax(sp, __shfl_xor(sp, 16));
+      sp = fmax(sp, __shfl_xor(sp, 32));
+      float x[4], z[3];
+      const bool live = sdnn_features(v, x);
+      sdnn_mfma(F, x, z);  // all 64 lanes take part
+      if (valid) {
+        smax = fmax(smax, sp);
+        tau[dir] = live ? sdnn_argmax(z) : 0;
+      }
+    }
+    if (g == 0 && k < a.P) {
+      a.tau[k] = static_cast<uint8_t>(tau[0]);
+      a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
+      a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
+    }
+  }
 }
 
 // One pass of the windowed max: out(k) = max_off in(k + off * stride) w(|off|)
@@ -253,7 +314,7 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
 // inactive points.
 __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ pid,
                          const PatchDev* __restrict__ patches, const uint8_t* __restrict__ flags, int64_t P, int dir,
-                         int nv, const double* __restrict__ w, int final_pass) {
+                         int nv, const double* __restrict__ w, double* __restrict__ mu) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const PatchDev pd = patches[pid[k]];
@@ -268,15 +329,15 @@ __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out
     double val = in[k + off * stride] * w[off < 0 ? -off : off];
     if (val > best) best = val;
   }
-  if (final_pass && !(flags[k] & kActive)) best = 0.0;
+  if (mu) {
+    // final pass: inactive points carry no viscosity; the blend rows then
+    // overwrite the points covered by several subpatches
+    if (!(flags[k] & kActive)) best = 0.0;
+    mu[k] = fmax(best, 0.0);
+  }
   out[k] = best;
 }
 
-__global__ void k_blend(const double* __restrict__ mut, double* __restrict__ mu, int64_t P) {
-  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (k >= P) return;
-  mu[k] = fmax(mut[k], 0.0);
-}
 
 __global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu, const int64_t* __restrict__ dst,
                              const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
@@ -377,9 +438,8 @@ inline dim3 grid_for(int64_t n, int b = 256) { return dim3(static_cast<unsigned>
 
 }  // namespace
 
-hipError_t launch_flux(const double* U, double* F, const uint8_t* flags, const double* t1x, const double* t1y,
-                       const double* t2x, const double* t2y, int64_t P, double gm1, hipStream_t s) {
-  hipLaunchKernelGGL(k_flux, grid_for(P), dim3(256), 0, s, U, F, flags, t1x, t1y, t2x, t2y, P, gm1);
+hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_flux, grid_for(P), dim3(256), 0, s, U, flags, fo, P);
   return hipGetLastError();
 }
 
@@ -388,17 +448,12 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_bc(double* U, const BcEntry* bc, int nbc, int64_t P, double gamma, const double* t,
-                     const double* dt, double frac, const VortexArgs& v, hipStream_t s) {
-  if (nbc) hipLaunchKernelGGL(k_bc, grid_for(nbc), dim3(256), 0, s, U, bc, nbc, P, gamma, t, dt, frac, v);
-  return hipGetLastError();
-}
-
-hipError_t launch_fringe(double* U, const int64_t* copy_pairs, int ncopy, const int64_t* idst, const int32_t* iptr,
-                         const int64_t* icol, const double* ival, int ninterp, int64_t P, hipStream_t s) {
-  if (ncopy) hipLaunchKernelGGL(k_copy_rows, grid_for(ncopy), dim3(256), 0, s, U, copy_pairs, ncopy, P, 4);
-  if (ninterp)
-    hipLaunchKernelGGL(k_interp_rows, grid_for(ninterp), dim3(256), 0, s, U, idst, iptr, icol, ival, ninterp, P, 4);
+hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
+                         const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
+                         const FluxOut& fo, hipStream_t s) {
+  if (ncopy + ninterp)
+    hipLaunchKernelGGL(k_fringe, grid_for(ncopy + ninterp), dim3(256), 0, s, U, flags, copy_pairs, ncopy, idst, iptr,
+                       icol, ival, ninterp, P, fo);
   return hipGetLastError();
 }
 
@@ -420,12 +475,14 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   c.weights = v.weights;
   c.basis = v.basis;
   c.c_mu = v.c_mu;
-  hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
+  if (c.mode == 2)
+    hipLaunchKernelGGL(k_classify_sdnn, grid_for(v.P), dim3(256), 0, s, c);
+  else
+    hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.patches, v.flags, v.P, 0,
-                     v.nv, v.wdil, 0);
+                     v.nv, v.wdil, nullptr);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.patches, v.flags, v.P, 1,
-                     v.nv, v.wdil, 1);
-  hipLaunchKernelGGL(k_blend, grid_for(v.P), dim3(256), 0, s, v.mut, v.mu, v.P);
+                     v.nv, v.wdil, v.mu);
   if (v.nblend)
     hipLaunchKernelGGL(k_blend_rows, grid_for(v.nblend), dim3(256), 0, s, v.mut, v.mu, v.bdst, v.bptr, v.bcol,
                        v.bval, v.nblend);
