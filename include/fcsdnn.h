@@ -175,11 +175,16 @@ fcs_status fcs_stats(fcs_ctx* ctx, fcs_stats_t* out);
 
 /* Average duration (ms) of the dominant derivative-contraction launch over
  * the advance calls since the last reset, measured with HIP events on the
- * bound stream, and the algorithmic flops of one such launch.  Timing is
- * recorded only after fcs_profile_enable(ctx, 1). */
+ * bound stream, and the algorithmic flops and bytes of one such launch.
+ * Timing is recorded only after fcs_profile_enable(ctx, 1).  Whole steps
+ * then replay a separate graph that carries event-record nodes around each
+ * stage contraction and one empty pair of event nodes; *event_latency_ms
+ * (nullable) is the average interval of that empty pair, the latency an
+ * event pair adds to each measured interval.  Without a stream or graphs
+ * the events are recorded eagerly and *event_latency_ms is 0. */
 fcs_status fcs_profile_enable(fcs_ctx* ctx, int32_t on);
 fcs_status fcs_profile_read(fcs_ctx* ctx, double* avg_ms, double* flops_per_launch,
-                            double* bytes_per_launch, int64_t* launches);
+                            double* bytes_per_launch, int64_t* launches, double* event_latency_ms);
 
 const char* fcs_last_error(const fcs_ctx* ctx);
 void fcs_destroy(fcs_ctx* ctx);
@@ -217,9 +222,15 @@ fcs_status fcs_sweep_profile(fcs_sweep* s, int32_t on, double* avg_ms, double* f
 fcs_status fcs_sweep_points(const fcs_sweep* s, int64_t* npoints);
 /* Autotuner: runs every candidate tile shape of the contraction kernel on
  * the given device arrays (results overwritten), keeps the fastest, and
- * writes the per-candidate ms (up to 8 doubles, host) to ms if non-NULL.
- * Synchronizes. */
+ * writes the per-candidate ms (fcs_gemm_variant_count(precision) doubles,
+ * host) to ms if non-NULL.  Synchronizes. */
 fcs_status fcs_sweep_autotune(fcs_sweep* s, const double* in, double* d1, double* d2, double* ms);
+/* Candidate tile variants of the grouped contraction for a precision
+ * (FCS_PREC_*; 0 for an unknown precision), and the explicit choice of one
+ * of them (0 <= index < count) for a sweep, in the autotuner's order.
+ * FCS_EINVAL for an index out of range. */
+int32_t fcs_gemm_variant_count(int32_t precision);
+fcs_status fcs_sweep_set_variant(fcs_sweep* s, int32_t index);
 void fcs_sweep_destroy(fcs_sweep* s);
 
 /* ---------------------------------------------------------------------

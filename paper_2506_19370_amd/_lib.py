@@ -90,7 +90,7 @@ fcs_get_field = _sig("fcs_get_field", _i, [vp, _i, _i, vp, _i])
 fcs_stats = _sig("fcs_stats", _i, [vp, ctypes.POINTER(Stats)])
 fcs_profile_enable = _sig("fcs_profile_enable", _i, [vp, _i])
 fcs_profile_read = _sig("fcs_profile_read", _i, [vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
-                                                 ctypes.POINTER(_i64)])
+                                                 ctypes.POINTER(_i64), ctypes.POINTER(_d)])
 fcs_last_error = _sig("fcs_last_error", ctypes.c_char_p, [vp])
 fcs_destroy = _sig("fcs_destroy", None, [vp])
 fcs_fc_continuation = _sig("fcs_fc_continuation", _i, [_i, _i, vp, vp])
@@ -102,6 +102,8 @@ fcs_sweep_run = _sig("fcs_sweep_run", _i, [vp, vp, vp, vp])
 fcs_sweep_profile = _sig("fcs_sweep_profile", _i, [vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_d),
                                                    ctypes.POINTER(_d), ctypes.POINTER(_i64)])
 fcs_sweep_points = _sig("fcs_sweep_points", _i, [vp, ctypes.POINTER(_i64)])
+fcs_gemm_variant_count = _sig("fcs_gemm_variant_count", _i, [_i])
+fcs_sweep_set_variant = _sig("fcs_sweep_set_variant", _i, [vp, _i])
 fcs_sweep_destroy = _sig("fcs_sweep_destroy", None, [vp])
 fcs_sweep_autotune = _sig("fcs_sweep_autotune", _i, [vp, vp, vp, vp, vp])
 fcs_sdnn_infer = _sig("fcs_sdnn_infer", _i, [vp, vp, _i64, vp, vp, vp])
@@ -118,7 +120,7 @@ EXPORTED = [
     "fcs_last_error", "fcs_destroy", "fcs_fc_continuation", "fcs_fc_operator", "fcs_sweep_create",
     "fcs_sweep_workspace_size", "fcs_sweep_bind", "fcs_sweep_run", "fcs_sweep_profile", "fcs_sweep_points",
     "fcs_sweep_destroy", "fcs_sweep_autotune", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",
-    "fcs_lines_workspace", "fcs_lines_apply",
+    "fcs_lines_workspace", "fcs_lines_apply", "fcs_gemm_variant_count", "fcs_sweep_set_variant",
 ]
 
 

@@ -148,10 +148,11 @@ class Solver:
         L.check(L.fcs_profile_enable(self.h, int(on)), self.h)
 
     def profile_read(self):
-        ms, fl, by, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        L.check(L.fcs_profile_read(self.h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by), ctypes.byref(n)),
-                self.h)
-        return {"avg_ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": n.value}
+        ms, fl, by, n, lat = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+        L.check(L.fcs_profile_read(self.h, ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by), ctypes.byref(n),
+                                   ctypes.byref(lat)), self.h)
+        return {"avg_ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": n.value,
+                "event_latency_ms": lat.value}
 
 
 class DerivSweep:
@@ -188,8 +189,15 @@ class DerivSweep:
         L.check(L.fcs_sweep_run(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d1.data_ptr()),
                                 ctypes.c_void_p(d2.data_ptr())))
 
+    def set_variant(self, index: int):
+        L.check(L.fcs_sweep_set_variant(self.h, int(index)))
+
+    @staticmethod
+    def variant_count(precision: str) -> int:
+        return int(L.fcs_gemm_variant_count(L.PREC[precision]))
+
     def autotune(self, x: torch.Tensor, d1: torch.Tensor, d2: torch.Tensor):
-        ms = np.zeros(8)
+        ms = np.zeros(16)
         L.check(L.fcs_sweep_autotune(self.h, ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(d1.data_ptr()),
                                      ctypes.c_void_p(d2.data_ptr()), ms.ctypes.data))
         return ms

@@ -101,6 +101,9 @@ struct fcs_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   hipStream_t stream = nullptr;
+  // second stream of the per-step fork: the filter runs beside the viscosity
+  hipStream_t stream2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   bool bound = false;
   std::map<std::string, size_t> off;
   double* arr[A_NARR] = {};
@@ -111,7 +114,7 @@ struct fcs_ctx {
   GemmVariant var[PH_N];
   size_t tile_cap[PH_N] = {};
   bool tuned = false;
-  float tune_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  float tune_ms[16] = {};
 
   // time stepping
   int stage_in_step = 0;
@@ -123,14 +126,14 @@ struct fcs_ctx {
   bool prof = false;
   std::vector<hipEvent_t> ev;
   size_t ev_used = 0;
-  double prof_ms = 0.0;
-  int64_t prof_n = 0;
+  double prof_ms = 0.0, prof_ovh_ms = 0.0;
+  int64_t prof_n = 0, prof_ovh_n = 0;
 
   // graphs: [0] step without filter, [1] with; the profiled copies carry
   // external event-record nodes around each stage contraction
   hipGraphExec_t gexec[2] = {nullptr, nullptr};
   hipGraphExec_t pgexec[2] = {nullptr, nullptr};
-  hipEvent_t pev[2][10] = {};
+  hipEvent_t pev[2][12] = {};  // 5 stage pairs, then an empty pair (event-node latency)
   bool capturing_prof = false;
   int prof_wf = 0, prof_stage = 0;
 
@@ -503,6 +506,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BVAL"] = cv.take(c->bval.size() * D);
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
   o["BCIDX"] = cv.take(P * 4);
+  o["GCTR"] = cv.take(2 * PH_N * 4);  // tile counters of the persistent contractions
   o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
   o["BASIS"] = cv.take(256 * D);
   o["WDIL"] = cv.take((p.n_v + 1) * D);
@@ -644,6 +648,12 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
   double scal0[5] = {c->t_host, 0.0, 0.0, 0.0, c->t_host};
   HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), scal0, sizeof(scal0), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->stream && !c->stream2) {
+    // default priority, like the caller's stream
+    HIPCHK(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+  }
   return FCS_OK;
 }
 
@@ -664,7 +674,8 @@ fcs_status record_in_capture(fcs_ctx* c, hipEvent_t ev) {
   return FCS_OK;
 }
 
-fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed) {
+fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed, hipStream_t s = nullptr) {
+  if (!s) s = c->stream;
   if (c->phase_tiles[ph].empty()) return FCS_OK;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (timed && c->capturing_prof) {
@@ -678,8 +689,13 @@ fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed) 
     e1 = c->ev[c->ev_used++];
     HIPCHK(c, hipEventRecord(e0, c->stream));
   }
-  HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
-                        static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->stream));
+  if (ph == PH_EULER || ph == PH_CROSS)
+    HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
+                          static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->dptr<int>("GCTR") + 2 * ph,
+                          c->stream));
+  else
+    HIPCHK(c, launch_gemm_step(c->d_tasks[ph][variant], c->d_tiles[ph], static_cast<int>(c->phase_tiles[ph].size()),
+                               c->optab, s));
   if (e1) {
     if (c->capturing_prof) {
       fcs_status st = record_in_capture(c, e1);
@@ -697,8 +713,8 @@ fcs_status per_step(fcs_ctx* c) {
   double* U0 = c->arr[A_U0];
   double* scal = c->dptr<double>("SCAL");
   fcs_status st;
+  ViscArgs v{};
   if (c->visc) {
-    ViscArgs v{};
     v.P = P;
     v.U = U0;
     v.flags = c->dptr<uint8_t>("FLAGS");
@@ -726,15 +742,31 @@ fcs_status per_step(fcs_ctx* c) {
     v.bptr = c->dptr<int32_t>("BPTR");
     v.bcol = c->dptr<int64_t>("BCOL");
     v.bval = c->dptr<double>("BVAL");
+    HIPCHK(c, launch_proxy(v, c->stream));
+  }
+  // Alg. 4 (filter) reads and rewrites the state, which after the proxy
+  // kernel no part of Alg. 3 reads: with a second stream the two run side by
+  // side and join before the step size is taken.
+  const bool filt = p.filter && c->steps > 0;
+  const bool fork = filt && c->visc && c->stream2 != nullptr;
+  if (filt) {
+    hipStream_t fs = c->stream;
+    if (fork) {
+      HIPCHK(c, hipEventRecord(c->ev_fork, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork, 0));
+      fs = c->stream2;
+    }
+    HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], c->dptr<uint8_t>("FLAGS"), P, p.gamma, fs));
+    if ((st = run_gemm(c, PH_FILT1, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
+    if ((st = run_gemm(c, PH_FILT2, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
+    HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, fs));
+    if (fork) HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
+  }
+  if (c->visc) {
     HIPCHK(c, launch_viscosity(v, c->stream));
     if ((st = run_gemm(c, PH_MUGRAD, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
   }
-  if (p.filter && c->steps > 0) {
-    HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], c->dptr<uint8_t>("FLAGS"), P, p.gamma, c->stream));
-    if ((st = run_gemm(c, PH_FILT1, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
-    if ((st = run_gemm(c, PH_FILT2, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
-    HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, c->stream));
-  }
+  if (fork) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   HIPCHK(c, launch_dt(U0, c->dptr<uint8_t>("FLAGS"), c->dptr<double>("MET9"), c->visc ? c->arr[A_MU] : nullptr,
                       c->dptr<double>("DTPART"), c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, scal, c->stream));
   return FCS_OK;
@@ -924,7 +956,10 @@ fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
   c->capturing_prof = profiled;
   c->prof_wf = with_filter;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-  fcs_status st = full_step_eager(c);
+  fcs_status st = FCS_OK;
+  if (profiled && (st = record_in_capture(c, c->pev[with_filter][10])) == FCS_OK)
+    st = record_in_capture(c, c->pev[with_filter][11]);
+  if (st == FCS_OK) st = full_step_eager(c);
   hipError_t e = hipStreamEndCapture(c->stream, &graph);
   c->steps = saved;
   c->prof = saved_prof;
@@ -1014,6 +1049,10 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
             c->prof_ms += ms;
             c->prof_n++;
           }
+          float ms = 0;
+          HIPCHK(c, hipEventElapsedTime(&ms, c->pev[wf][10], c->pev[wf][11]));
+          c->prof_ovh_ms += ms;
+          c->prof_ovh_n++;
         }
       } else {
         if ((st = full_step_eager(c)) != FCS_OK) return st;
@@ -1121,10 +1160,13 @@ extern "C" fcs_status fcs_profile_enable(fcs_ctx* c, int32_t on) {
   c->ev_used = 0;
   c->prof_ms = 0;
   c->prof_n = 0;
+  c->prof_ovh_ms = 0;
+  c->prof_ovh_n = 0;
   return FCS_OK;
 }
 
-extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops, double* bytes, int64_t* launches) {
+extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops, double* bytes, int64_t* launches,
+                                       double* event_latency_ms) {
   if (!c) return FCS_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (size_t q = 0; q + 1 < c->ev_used; q += 2) {
@@ -1143,6 +1185,7 @@ extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops
     *bytes = b;
   }
   if (launches) *launches = c->prof_n;
+  if (event_latency_ms) *event_latency_ms = c->prof_ovh_n ? c->prof_ovh_ms / c->prof_ovh_n : 0.0;
   return FCS_OK;
 }
 
@@ -1156,5 +1199,8 @@ extern "C" void fcs_destroy(fcs_ctx* c) {
     for (auto& e : row)
       if (e) hipEventDestroy(e);
   for (auto& e : c->ev) hipEventDestroy(e);
+  if (c->ev_fork) hipEventDestroy(c->ev_fork);
+  if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->stream2) hipStreamDestroy(c->stream2);
   delete c;
 }

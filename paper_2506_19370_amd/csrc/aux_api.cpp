@@ -49,7 +49,7 @@ struct fcs_sweep {
   std::vector<GemmTile> tiles;
   char* ws = nullptr;
   size_t need = 0;
-  size_t o_off = 0, o_roff = 0, o_ld = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
+  size_t o_ctr = 0, o_off = 0, o_roff = 0, o_ld = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
   hipStream_t stream = nullptr;
   const double* last_in = nullptr;
   double *last_d1 = nullptr, *last_d2 = nullptr;
@@ -127,6 +127,7 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     u = align_up(u + std::max<size_t>(b, 1));
     return o;
   };
+  s->o_ctr = take(8);
   s->o_off = take(s->ops.off.size() * 8);
   s->o_roff = take(s->ops.roff.size() * 8);
   s->o_ld = take(s->ops.ld.size() * 4);
@@ -163,6 +164,8 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   std::vector<float> f32;
   std::vector<uint16_t> bhi, blo;
   hipStream_t st = s->stream;
+  // tile counters of the persistent variants start at zero
+  if (hipMemsetAsync(s->ws + s->o_ctr, 0, 8, st)) return FCS_EHIP;
   if (hipMemcpyAsync(s->ws + s->o_off, s->ops.off.data(), s->ops.off.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_roff, s->ops.roff.data(), s->ops.roff.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_ld, s->ops.ld.data(), s->ops.ld.size() * 4, hipMemcpyHostToDevice, st) ||
@@ -219,9 +222,36 @@ extern "C" fcs_status fcs_sweep_run(fcs_sweep* s, const double* in, double* d1, 
   }
   if (launch_gemm(s->precision, s->var, reinterpret_cast<const GemmTask*>(s->ws + s->o_task),
                   reinterpret_cast<const GemmTile*>(s->ws + s->o_tile), static_cast<int>(s->tiles.size()), s->tab,
-                  s->stream) != hipSuccess)
+                  reinterpret_cast<int*>(s->ws + s->o_ctr), s->stream) != hipSuccess)
     return FCS_EHIP;
   if (e1 && hipEventRecord(e1, s->stream)) return FCS_EHIP;
+  return FCS_OK;
+}
+
+extern "C" int32_t fcs_gemm_variant_count(int32_t precision) {
+  if (precision < 0 || precision > 2) return 0;
+  int nv = 0;
+  gemm_variants(precision, &nv);
+  return nv;
+}
+
+extern "C" fcs_status fcs_sweep_set_variant(fcs_sweep* s, int32_t index) {
+  if (!s || !s->ws) return FCS_EINVAL;
+  int nv = 0;
+  const GemmVariant* cand = gemm_variants(s->precision, &nv);
+  if (index < 0 || index >= nv) return FCS_EINVAL;
+  const GemmVariant saved = s->var;
+  s->var = cand[index];
+  sweep_tiles(s);
+  if (s->tiles.size() > s->tile_cap) {
+    s->var = saved;
+    sweep_tiles(s);
+    return FCS_EINVAL;
+  }
+  if (hipMemcpyAsync(s->ws + s->o_tile, s->tiles.data(), s->tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice,
+                     s->stream) ||
+      hipStreamSynchronize(s->stream))
+    return FCS_EHIP;
   return FCS_OK;
 }
 
@@ -411,7 +441,7 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
   tab.ld = reinterpret_cast<const int32_t*>(ws + o_small + 16);
   tab.f64 = reinterpret_cast<const double*>(ws + o_op);
   if (launch_gemm(0, v, reinterpret_cast<const GemmTask*>(ws + o_task), reinterpret_cast<const GemmTile*>(ws + o_tile),
-                  static_cast<int>(tiles.size()), tab, st) != hipSuccess)
+                  static_cast<int>(tiles.size()), tab, nullptr, st) != hipSuccess)
     return FCS_EHIP;
   // the host staging vectors must outlive the copies
   return hipStreamSynchronize(st) == hipSuccess ? FCS_OK : FCS_EHIP;

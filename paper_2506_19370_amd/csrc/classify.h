@@ -78,8 +78,16 @@ struct SdnnFrag {
 // Hidden unit of k slot j of lane group g in input block kb.
 __device__ __forceinline__ int sdnn_slot(int kb, int g, int j) { return 32 * kb + (j < 4 ? 4 * g + j : 12 + 4 * g + j); }
 
-// W: parameter blob (W1 64x16, b1, W2 64x64, b2, W3 3x64, b3), FP32.
-__device__ __forceinline__ void load_sdnn_frag(const float* __restrict__ W, SdnnFrag& F) {
+constexpr int kSdnnParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
+
+// Copies the parameter blob into LDS with coalesced reads (whole block).
+__device__ __forceinline__ void stage_sdnn_params(const float* __restrict__ src, float* dst) {
+  for (int q = threadIdx.x; q < kSdnnParams; q += blockDim.x) dst[q] = src[q];
+  __syncthreads();
+}
+
+// W: parameter blob (W1 64x16, b1, W2 64x64, b2, W3 3x64, b3), FP32 (in LDS).
+__device__ __forceinline__ void load_sdnn_frag(const float* W, SdnnFrag& F) {
   const float* W1 = W;
   const float* B1 = W1 + 64 * 16;
   const float* W2 = B1 + 64;

@@ -11,8 +11,8 @@ namespace fcs {
 // Operator tables are stored zero-padded: operator k occupies
 // op_rows(n) x op_ld(n) elements (row-major, leading dimension op_ld), so a
 // contraction tile never tests operator bounds.  The padding is sized for the
-// largest tile (128 outputs) and the deepest chunk (32 columns).
-constexpr int kOpRowPad = 128;
+// largest tile (256 outputs) and the deepest chunk (32 columns).
+constexpr int kOpRowPad = 256;
 constexpr int kOpColPad = 32;
 inline int op_ld(int n) { return (n + kOpColPad - 1) / kOpColPad * kOpColPad; }
 inline int op_rows(int n) { return (n + kOpRowPad - 1) / kOpRowPad * kOpRowPad; }
@@ -33,12 +33,23 @@ void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::ve
 // Tile shape of a contraction launch: a workgroup covers 64 lines and 64 tb
 // outputs (tb = 1 or 2) and walks the operator depth in chunks of kc
 // (16 or 32; the split-BF16 kernel always uses 32).
+// persist: one workgroup per resident slot taking tiles from a device
+// counter pair (two ints, zero before the first launch; each launch leaves
+// them zero), tiles sorted longest first.
+// xs: operand lines staged in LDS, operator rows loaded straight into MFMA
+// registers (tb 2 or 4; FP64 and FP32).
 struct GemmVariant {
   int tb = 1;
   int kc = 16;
+  bool persist = false;
+  bool xs = false;
 };
 hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
-                       int ntiles, const OpTables& ops, hipStream_t stream);
+                       int ntiles, const OpTables& ops, int* counters, hipStream_t stream);
+// FP64 contraction with the default tile (64 lines x 64 outputs), launched
+// under its own kernel name for the once-per-step phases.
+hipError_t launch_gemm_step(const GemmTask* tasks, const GemmTile* tiles, int ntiles, const OpTables& ops,
+                            hipStream_t stream);
 int gemm_lines_per_tile();
 int gemm_outputs_per_tile(const GemmVariant& v);
 // Tiles of one task set (operator sizes n, lines nrow * ncomp per task).

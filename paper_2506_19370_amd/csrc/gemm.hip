@@ -12,7 +12,7 @@
 // Staging is branch-free and double-buffered in LDS: the global loads of
 // chunk k + 1 are in flight while the matrix cores work on chunk k, and one
 // barrier per chunk separates the buffers.  Operators are zero-padded (rows
-// to 128, columns to 32), so operator reads need no bounds tests; operand
+// to 256, columns to 32), so operator reads need no bounds tests; operand
 // positions past the line end are clamped to the last point (their operator
 // column is zero) and lines past the task end are clamped to its last line
 // (their results are not stored).
@@ -28,6 +28,8 @@
 // the two are added in FP64 with the exact offset term x0 * rowsum(Op).
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 
 #include "fc_builder.h"
 #include "gemm.h"
@@ -41,13 +43,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 namespace {
 
 constexpr int kLB = 64;  // lines per workgroup
-
-__device__ __forceinline__ uint16_t f2bf(float f) {
-  uint32_t u = __float_as_uint(f);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
-}
-__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
 
 // Element offset of position 0 of a line (row fastest numbering).
 __device__ __forceinline__ int64_t line_base(const GemmTask& T, int line) {
@@ -122,8 +117,8 @@ __device__ __forceinline__ void store_tile(const GemmTask& T, const int64_t* dst
 
 // FP64 or FP32 operands on the 16x16x4 MFMA of that type.
 template <typename Elem, int KC, int TB>
-__global__ __launch_bounds__(256) void k_gemm_fp(const GemmTask* __restrict__ tasks,
-                                                 const GemmTile* __restrict__ tiles, OpTables ops) {
+__device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, const GemmTile tile,
+                                        const OpTables& ops) {
   constexpr bool kF64 = sizeof(Elem) == 8;
   constexpr int kTT = 64 * TB;
   constexpr int kDV = 16 / sizeof(Elem);        // operator elements per 16-byte load
@@ -133,7 +128,6 @@ __global__ __launch_bounds__(256) void k_gemm_fp(const GemmTask* __restrict__ ta
   __shared__ Elem Xs[2][kLB][KC + 1];
   __shared__ Elem Ds[2][kTT][KC + 1];
   __shared__ int64_t dst[kLB];
-  const GemmTile tile = tiles[blockIdx.x];
   const GemmTask T = tasks[tile.task];
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
   const int nl = min(kLB, nlines - tile.line0);
@@ -215,11 +209,183 @@ __global__ __launch_bounds__(256) void k_gemm_fp(const GemmTask* __restrict__ ta
                        nullptr);
 }
 
+// Operator in registers: only the operand lines (shared by the four waves)
+// are staged in LDS; each wave loads the operator rows of its own output
+// blocks straight from L2 into MFMA operand registers.  Within a chunk of 16
+// columns the reduction runs in the order k = 4 g + j (lane group g = lane /
+// 16, step j), so a lane's operator values for the chunk are 4 consecutive
+// columns of one row (16-byte loads) and its operand values 4 consecutive
+// columns of one line (16-byte LDS reads).  The operator loads of chunk c+1
+// are issued before the products of chunk c.  TB (2 or 4) 16-output blocks
+// per wave: a workgroup covers 64 lines x 64 TB outputs.
+template <typename Elem, int KC, int TB>
+__device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, const GemmTile tile, const OpTables& ops) {
+  constexpr bool kF64 = sizeof(Elem) == 8;
+  constexpr int kTT = 64 * TB;
+  constexpr int PITCH = KC + 16 / sizeof(Elem);   // 16-byte aligned rows
+  constexpr int NX = kLB * KC / 256;              // operand values per thread and chunk
+  constexpr int NS = KC / 16;                     // 16-column sub-chunks
+  constexpr int DQ = 4 * sizeof(Elem) / 16;       // 16-byte loads per 4 operator values
+  typedef Elem vec4 __attribute__((ext_vector_type(4)));
+  __shared__ __attribute__((aligned(16))) Elem Xs[2][kLB][PITCH];
+  __shared__ int64_t dst[kLB];
+  const GemmTask T = tasks[tile.task];
+  const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
+  const int nl = min(kLB, nlines - tile.line0);
+  const int ld = ops.ld[T.op];
+  const Elem* __restrict__ D;
+  if constexpr (kF64)
+    D = ops.f64 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
+  else
+    D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  const bool q1 = T.s_stride == 1;
+  if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
+  // operand staging: one line and NX consecutive columns per thread
+  const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
+  const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
+  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  double xr[NX];
+  auto load_x = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xr[j] = xbase[static_cast<int64_t>(min(k0 + xs_col + j, n - 1)) * T.s_stride];
+  };
+  auto stage = [&](int b) {
+#pragma unroll
+    for (int j = 0; j < NX; ++j) Xs[b][xs_line][xs_col + j] = static_cast<Elem>(xr[j]);
+  };
+  // operator fragments: block i of this wave, sub-chunk s, 4 values
+  uint4 dr[TB][NS][DQ];
+  auto load_d = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i) {
+      const Elem* row = D + static_cast<int64_t>(16 * (wave + 4 * i) + rr) * ld + k0 + 4 * g;
+#pragma unroll
+      for (int sc = 0; sc < NS; ++sc)
+#pragma unroll
+        for (int q = 0; q < DQ; ++q)
+          dr[i][sc][q] = 16 * (wave + 4 * i) < nt ? *reinterpret_cast<const uint4*>(row + 16 * sc + q * (16 / sizeof(Elem)))
+                                                  : uint4{0, 0, 0, 0};
+    }
+  };
+  vec4 acc[TB][4];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[i][b] = vec4{0, 0, 0, 0};
+  const int nk = (n + KC - 1) / KC;
+  load_x(0);
+  load_d(0);
+  stage(0);
+  __syncthreads();
+  for (int c = 0; c < nk; ++c) {
+    const int b = c & 1;
+    uint4 dn[TB][NS][DQ];
+#pragma unroll
+    for (int i = 0; i < TB; ++i)
+#pragma unroll
+      for (int sc = 0; sc < NS; ++sc)
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) dn[i][sc][q] = dr[i][sc][q];
+    if (c + 1 < nk) {
+      load_x((c + 1) * KC);
+      load_d((c + 1) * KC);
+    }
+#pragma unroll
+    for (int sc = 0; sc < NS; ++sc) {
+      Elem xv[4][4];  // [line block][step]
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        const Elem* xp = &Xs[b][16 * lb + rr][16 * sc + 4 * g];
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const uint4 v = *reinterpret_cast<const uint4*>(xp + q * (16 / sizeof(Elem)));
+          const Elem* e = reinterpret_cast<const Elem*>(&v);
+#pragma unroll
+          for (int j = 0; j < 16 / static_cast<int>(sizeof(Elem)); ++j) xv[lb][q * (16 / sizeof(Elem)) + j] = e[j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        if (16 * (wave + 4 * i) >= nt) continue;
+        const Elem* dv = reinterpret_cast<const Elem*>(&dn[i][sc][0]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int lb = 0; lb < 4; ++lb) {
+            if constexpr (kF64)
+              acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(xv[lb][j], dv[j], acc[i][lb], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f64_16x16x4f64(dv[j], xv[lb][j], acc[i][lb], 0, 0, 0);
+            else
+              acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f32_16x16x4f32(xv[lb][j], dv[j], acc[i][lb], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f32_16x16x4f32(dv[j], xv[lb][j], acc[i][lb], 0, 0, 0);
+          }
+      }
+    }
+    if (c + 1 < nk) stage(b ^ 1);
+    __syncthreads();
+  }
+  store_tile<kF64, TB>(T, dst, nl, t0, nt, q1, wave, lane, acc, static_cast<const vec4(*)[4]>(nullptr), nullptr,
+                       nullptr);
+}
+
+template <typename Elem, int KC, int TB>
+__global__ __launch_bounds__(256) void k_gemm_xs(const GemmTask* __restrict__ tasks,
+                                                 const GemmTile* __restrict__ tiles, OpTables ops) {
+  gemm_xs<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
+}
+
+// Persistent form: the grid holds one workgroup per resident slot and each
+// workgroup takes tiles from a device counter until the list is exhausted
+// (tiles sorted longest first).  ctr[0] hands out tiles, ctr[1] counts
+// finished workgroups; the last one to finish resets both, so the next
+// launch (graph replays included) starts from zero without a memset.
+template <typename Body>
+__device__ __forceinline__ void persistent_tiles(int ntiles, int* ctr, Body body) {
+  __shared__ int tile_id;
+  for (;;) {
+    if (threadIdx.x == 0) tile_id = atomicAdd(&ctr[0], 1);
+    __syncthreads();
+    const int t = tile_id;
+    __syncthreads();
+    if (t < 0 || t >= ntiles) break;
+    body(t);
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    if (atomicAdd(&ctr[1], 1) == static_cast<int>(gridDim.x) - 1) {
+      atomicExch(&ctr[0], 0);
+      atomicExch(&ctr[1], 0);
+    }
+  }
+}
+
+// Stage contractions (every SSPRK stage) ...
+template <typename Elem, int KC, int TB>
+__global__ __launch_bounds__(256) void k_gemm_fp(const GemmTask* __restrict__ tasks,
+                                                 const GemmTile* __restrict__ tiles, OpTables ops) {
+  gemm_fp<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
+}
+
+template <typename Elem, int KC, int TB>
+__global__ __launch_bounds__(256) void k_gemm_fp_persist(const GemmTask* __restrict__ tasks,
+                                                         const GemmTile* __restrict__ tiles, int ntiles,
+                                                         OpTables ops, int* ctr) {
+  persistent_tiles(ntiles, ctr, [&](int t) { gemm_fp<Elem, KC, TB>(tasks, tiles[t], ops); });
+}
+
+// ... and the once-per-step FP64 contractions (viscosity gradient, filter),
+// under their own name so that profiles tell the two apart.
+__global__ __launch_bounds__(256) void k_gemm_step(const GemmTask* __restrict__ tasks,
+                                                   const GemmTile* __restrict__ tiles, OpTables ops) {
+  gemm_fp<double, 16, 1>(tasks, tiles[blockIdx.x], ops);
+}
+
 // Split BF16: chunks of 32 columns (one MFMA depth); LDS rows padded to 40
 // halves so each lane's 8-element operand is one aligned 16-byte read.
 template <int TB>
-__global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict__ tasks,
-                                                     const GemmTile* __restrict__ tiles, OpTables ops) {
+__device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, const GemmTile tile,
+                                            const OpTables& ops) {
   constexpr int KC = 32, PITCH = 40, kTT = 64 * TB;
   constexpr int ND = kTT * KC / (256 * 8);  // 16-byte loads per thread and table
   __shared__ __attribute__((aligned(16))) uint16_t Xh[2][kLB][PITCH];
@@ -228,7 +394,6 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
   __shared__ __attribute__((aligned(16))) uint16_t Dl[2][kTT][PITCH];
   __shared__ double x0s[kLB];
   __shared__ int64_t dst[kLB];
-  const GemmTile tile = tiles[blockIdx.x];
   const GemmTask T = tasks[tile.task];
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
   const int nl = min(kLB, nlines - tile.line0);
@@ -238,17 +403,22 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
   const uint16_t* __restrict__ Bl = ops.blo + dbase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const bool q1 = T.s_stride == 1;
-  XLoad<KC> xl;
-  xl.init(T, tile.line0, nlines, q1);
-  // line offsets x0 (first point of each line) of this thread's elements
-  double x0r[XLoad<KC>::NX];
-#pragma unroll
-  for (int p = 0; p < XLoad<KC>::NX; ++p) x0r[p] = xl.base[p][0];
+  // Operand staging: each thread owns 8 consecutive columns of one line of
+  // the chunk (along q^1 four threads share a line, along q^2 neighbouring
+  // threads hold neighbouring lines), splits them with packed conversions and
+  // stores 16 bytes per table.
+  const int xl_line = q1 ? tid >> 2 : tid & 63, xl_col = 8 * (q1 ? tid & 3 : tid >> 6);
+  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xl_line, nlines - 1));
+  const double x0 = xbase[0];  // line offset (first point of the line)
   if (tid < kLB) {
     dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
     x0s[tid] = T.src[dst[tid]];
   }
-  double xr[XLoad<KC>::NX];
+  double xr[8];
+  auto load_x = [&](int k0) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) xr[j] = xbase[static_cast<int64_t>(min(k0 + xl_col + j, n - 1)) * T.s_stride];
+  };
   uint4 hr[ND], lr[ND];
   auto load_d = [&](int k0) {
 #pragma unroll
@@ -260,15 +430,15 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
     }
   };
   auto stage = [&](int b) {
+    bf16x8 h, l;
 #pragma unroll
-    for (int p = 0; p < XLoad<KC>::NX; ++p) {
-      int l, kk;
-      chunk_pos<KC>(q1, tid + 256 * p, l, kk);
-      const float f = static_cast<float>(xr[p] - x0r[p]);
-      const uint16_t h = f2bf(f);
-      Xh[b][l][kk] = h;
-      Xl[b][l][kk] = f2bf(f - bf2f(h));
+    for (int j = 0; j < 8; ++j) {
+      const float f = static_cast<float>(xr[j] - x0);
+      h[j] = static_cast<__bf16>(f);  // round to nearest even (v_cvt_pk_bf16_f32)
+      l[j] = static_cast<__bf16>(f - static_cast<float>(h[j]));
     }
+    *reinterpret_cast<bf16x8*>(&Xh[b][xl_line][xl_col]) = h;
+    *reinterpret_cast<bf16x8*>(&Xl[b][xl_line][xl_col]) = l;
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * 8, t = e / KC, kk = e % KC;
@@ -282,7 +452,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
 #pragma unroll
     for (int b = 0; b < 4; ++b) am[i][b] = ac[i][b] = f32x4{0, 0, 0, 0};
   const int nk = (n + KC - 1) / KC;
-  xl.load(xr, q1, 0, n, T.s_stride);
+  load_x(0);
   load_d(0);
   stage(0);
   __syncthreads();
@@ -290,7 +460,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
   for (int c = 0; c < nk; ++c) {
     const int b = c & 1;
     if (c + 1 < nk) {
-      xl.load(xr, q1, (c + 1) * KC, n, T.s_stride);
+      load_x((c + 1) * KC);
       load_d((c + 1) * KC);
     }
     bf16x8 xh[4], xlo[4];
@@ -322,6 +492,48 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict_
   }
   // the two FP32 accumulations are added in FP64 at the store
   store_tile<false, TB>(T, dst, nl, t0, nt, q1, wave, lane, am, ac, x0s, ops.rowsum + ops.roff[T.op]);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict__ tasks,
+                                                     const GemmTile* __restrict__ tiles, OpTables ops) {
+  gemm_bf16x3<TB>(tasks, tiles[blockIdx.x], ops);
+}
+
+template <int TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16x3_persist(const GemmTask* __restrict__ tasks,
+                                                             const GemmTile* __restrict__ tiles, int ntiles,
+                                                             OpTables ops, int* ctr) {
+  persistent_tiles(ntiles, ctr, [&](int t) { gemm_bf16x3<TB>(tasks, tiles[t], ops); });
+}
+
+// Resident workgroups of a kernel on the current device (cached per kernel
+// and device).
+template <typename K>
+int device_slots(K kernel) {
+  static std::mutex mu;
+  static std::map<std::pair<const void*, int>, int> cache;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), dev);
+  std::lock_guard<std::mutex> lock(mu);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, 0) != hipSuccess)
+    return 0;
+  const int slots = std::max(1, cus * per_cu);
+  cache[key] = slots;
+  return slots;
+}
+
+template <typename K, typename... Args>
+hipError_t launch_persist(K kernel, int ntiles, hipStream_t stream, Args... args) {
+  const int slots = device_slots(kernel);
+  if (slots <= 0) return hipErrorInvalidDevice;
+  hipLaunchKernelGGL(kernel, dim3(std::min(ntiles, slots)), dim3(256), 0, stream, args...);
+  return hipGetLastError();
 }
 
 uint16_t host_bf16(float f) {
@@ -382,10 +594,56 @@ void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::ve
   }
 }
 
-hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
-                       int ntiles, const OpTables& ops, hipStream_t stream) {
+hipError_t launch_gemm_step(const GemmTask* tasks, const GemmTile* tiles, int ntiles, const OpTables& ops,
+                            hipStream_t stream) {
   if (ntiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_gemm_step, dim3(ntiles), dim3(256), 0, stream, tasks, tiles, ops);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
+                       int ntiles, const OpTables& ops, int* counters, hipStream_t stream) {
+  if (ntiles <= 0) return hipSuccess;
+  if (v.persist) {
+    if (!counters) return hipErrorInvalidValue;
+#define FCS_PFP(E, KC, TB) \
+  return launch_persist(k_gemm_fp_persist<E, KC, TB>, ntiles, stream, tasks, tiles, ntiles, ops, counters)
+    if (precision == 0) {
+      if (v.tb == 2) FCS_PFP(double, 16, 2);
+      FCS_PFP(double, 16, 1);
+    }
+    if (precision == 1) {
+      if (v.kc == 32) {
+        if (v.tb == 2) FCS_PFP(float, 32, 2);
+        FCS_PFP(float, 32, 1);
+      }
+      if (v.tb == 2) FCS_PFP(float, 16, 2);
+      FCS_PFP(float, 16, 1);
+    }
+#undef FCS_PFP
+    if (v.tb == 2) return launch_persist(k_gemm_bf16x3_persist<2>, ntiles, stream, tasks, tiles, ntiles, ops, counters);
+    return launch_persist(k_gemm_bf16x3_persist<1>, ntiles, stream, tasks, tiles, ntiles, ops, counters);
+  }
   dim3 grid(ntiles), block(256);
+  if (v.xs) {
+#define FCS_XS(E, KC, TB) hipLaunchKernelGGL((k_gemm_xs<E, KC, TB>), grid, block, 0, stream, tasks, tiles, ops)
+    if (precision == 0) {
+      if (v.tb == 4) FCS_XS(double, 16, 4);
+      else FCS_XS(double, 16, 2);
+    } else if (precision == 1) {
+      if (v.kc == 32) {
+        if (v.tb == 4) FCS_XS(float, 32, 4);
+        else FCS_XS(float, 32, 2);
+      } else {
+        if (v.tb == 4) FCS_XS(float, 16, 4);
+        else FCS_XS(float, 16, 2);
+      }
+    } else {
+      return hipErrorInvalidValue;
+    }
+#undef FCS_XS
+    return hipGetLastError();
+  }
 #define FCS_FP(E, KC, TB) hipLaunchKernelGGL((k_gemm_fp<E, KC, TB>), grid, block, 0, stream, tasks, tiles, ops)
   if (precision == 0) {
     // FP64 keeps 16-column chunks: 32 would exceed 64 KiB of static LDS
@@ -409,13 +667,17 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
 }
 
 int gemm_lines_per_tile() { return kLB; }
-int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 2 ? 2 : 1); }
+int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 4 ? 4 : (v.tb == 2 ? 2 : 1)); }
 
 const GemmVariant* gemm_variants(int precision, int* count) {
-  static const GemmVariant f64[] = {{1, 16}, {2, 16}};
-  static const GemmVariant f32[] = {{1, 16}, {2, 16}, {1, 32}, {2, 32}};
-  static const GemmVariant bf[] = {{1, 32}, {2, 32}};
-  *count = precision == 1 ? 4 : 2;
+  // {tb, kc, persist, xs}
+  static const GemmVariant f64[] = {{1, 16, false, false}, {2, 16, false, false}, {1, 16, true, false},
+                                    {2, 16, false, true},  {4, 16, false, true}};
+  static const GemmVariant f32[] = {{1, 16, false, false}, {2, 16, false, false}, {1, 32, false, false},
+                                    {2, 16, false, true},  {4, 16, false, true},  {2, 32, false, true},
+                                    {4, 32, false, true}};
+  static const GemmVariant bf[] = {{1, 32, false, false}, {2, 32, false, false}, {1, 32, true, false}};
+  *count = precision == 0 ? 5 : (precision == 1 ? 7 : 3);
   return precision == 0 ? f64 : (precision == 1 ? f32 : bf);
 }
 
@@ -423,9 +685,23 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
                       std::vector<GemmTile>& tiles) {
   tiles.clear();
   const int step = gemm_outputs_per_tile(v);
-  for (size_t q = 0; q < ntasks; ++q)
-    for (int t0 = 0; t0 < n[q]; t0 += step)
-      for (int l0 = 0; l0 < nlines[q]; l0 += kLB) tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
+  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+  // L2.  The output tiles of one 64-line block are placed 8 tiles apart
+  // (groups of 8 line blocks, outputs outer), so they run on the same XCD at
+  // nearly the same time and re-read the block's operand lines from its L2.
+  constexpr int kXcd = 8;
+  for (size_t q = 0; q < ntasks; ++q) {
+    const int nblk = (nlines[q] + kLB - 1) / kLB;
+    for (int g0 = 0; g0 < nblk; g0 += kXcd)
+      for (int t0 = 0; t0 < n[q]; t0 += step)
+        for (int b = g0; b < std::min(nblk, g0 + kXcd); ++b)
+          tiles.push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
+  }
+  if (v.persist) {
+    // longest first (cost ~ operator depth x outputs of the tile)
+    auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
+    std::stable_sort(tiles.begin(), tiles.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
+  }
 }
 
 }  // namespace fcs

@@ -4,7 +4,6 @@
 
 namespace fcs {
 
-constexpr int FCS_SDNN_NPARAM_DEV = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
 
 struct VortexArgs {
   double beta, x0, y0, u0, v0;
@@ -95,6 +94,10 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
                          const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
                          const FluxOut& fo, hipStream_t s);
+// Alg. 3 in two parts: the proxy variable and wave speeds (the only part
+// that reads the state), then classification, preliminary viscosity,
+// dilation and blend.
+hipError_t launch_proxy(const ViscArgs& v, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);

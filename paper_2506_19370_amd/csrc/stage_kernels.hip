@@ -267,23 +267,32 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
 }
 
 // Alg. 3 with the SDNN: each wave classifies the two windows of 64 points
-// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma); lanes
-// 0..15 write the classes and the preliminary viscosity of their points.
+// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  The window
+// geometry is found once per lane (one point each) and handed to the rounds
+// by lane shuffles; lanes 0..15 write the classes and the preliminary
+// viscosity of the points of their rounds.
 __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
+  __shared__ float Wl[kSdnnParams];
+  stage_sdnn_params(a.weights, Wl);
   SdnnFrag F;
-  load_sdnn_frag(a.weights, F);
+  load_sdnn_frag(Wl, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t kw = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
-#pragma unroll 1
+  // geometry of this lane's point kw + lane
+  const int64_t kl = kw + lane;
+  const uint8_t fl = kl < a.P ? a.flags[kl] : 0;
+  int64_t gb[2] = {0, 0}, gs[2] = {0, 0};
+  bool gv[2];
+  for (int dir = 0; dir < 2; ++dir) gv[dir] = kl < a.P && window_at(a, kl, fl, dir, gb[dir], gs[dir]);
+#pragma unroll 2
   for (int pg = 0; pg < 4; ++pg) {
-    const int64_t k = kw + 16 * pg + c;
-    const uint8_t f = k < a.P ? a.flags[k] : 0;
+    const int src = 16 * pg + c;  // lane that owns this round's point
     int tau[2] = {0, 0};
     double smax = 0.0;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-      int64_t base = 0, stride = 0;
-      const bool valid = k < a.P && window_at(a, k, f, dir, base, stride);
+      const int64_t base = __shfl(gb[dir], src), stride = __shfl(gs[dir], src);
+      const bool valid = __shfl(static_cast<int>(gv[dir]), src) != 0;
       double v[4], sp = 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -301,6 +310,8 @@ __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
         tau[dir] = live ? sdnn_argmax(z) : 0;
       }
     }
+    const int64_t k = kw + src;
+    const uint8_t f = __shfl(static_cast<int>(fl), src);
     if (g == 0 && k < a.P) {
       a.tau[k] = static_cast<uint8_t>(tau[0]);
       a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
@@ -457,8 +468,12 @@ hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pa
   return hipGetLastError();
 }
 
-hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
+hipError_t launch_proxy(const ViscArgs& v, hipStream_t s) {
   hipLaunchKernelGGL(k_proxy, grid_for(v.P), dim3(256), 0, s, v.U, v.flags, v.phi, v.spd, v.P, v.gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   ClassifyArgs c;
   c.P = v.P;
   c.flags = v.flags;

@@ -26,8 +26,10 @@ __global__ __launch_bounds__(256) void k_classify_modal(ModalBasis basis, const 
 __global__ __launch_bounds__(256) void k_classify_sdnn_windows(const float* __restrict__ params,
                                                                const double* __restrict__ windows, int64_t nwin,
                                                                uint8_t* __restrict__ tau, float* __restrict__ logits) {
+  __shared__ float Wl[kSdnnParams];
+  stage_sdnn_params(params, Wl);
   SdnnFrag F;
-  load_sdnn_frag(params, F);
+  load_sdnn_frag(Wl, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t w0 = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
 #pragma unroll 1

@@ -30,17 +30,24 @@ def _sweep_ref(fields):
     return out1, out2
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", 2e-12), ("fp32", 2e-6), ("bf16x3", 1e-4)])
-def test_sweep_parity(prec, tol):
+def _variants():
+    from paper_2506_19370_amd import _lib as L
+    return [(p, tol, v) for p, tol in (("fp64", 2e-12), ("fp32", 2e-6), ("bf16x3", 1e-4))
+            for v in range(L.fcs_gemm_variant_count(L.PREC[p]))]
+
+
+@pytest.mark.parametrize("prec,tol,variant", _variants())
+def test_sweep_parity(prec, tol, variant):
     """Grouped contraction over uneven patches (several 64 x 64 tiles and
     ragged tails) vs the oracle's FFT derivative; error relative to the
     largest field value of the component (the operator error multiplies the
     data, not its derivative).  FP32: unit roundoff 6e-8 times the operator's
     row sums of |entries| (<= 18) and the accumulation length; split BF16:
     two 8-bit halves leave ~2^-16 per product on the offset-free data."""
-    sizes, fields = W.deriv_sweep(npatch=12, nmin=20, nmax=200, seed_salt=1)
+    sizes, fields = W.deriv_sweep(npatch=12, nmin=20, nmax=300, seed_salt=1)
     flat = np.concatenate([f.ravel() for f in fields])
     sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
+    sw.set_variant(variant)  # every tile shape the autotuner may choose
     x = torch.tensor(flat, device="cuda")
     d1 = torch.zeros_like(x)
     d2 = torch.zeros_like(x)
@@ -55,7 +62,7 @@ def test_sweep_parity(prec, tol):
             scale = np.abs(f[c]).max()
             e1 = np.abs(g1[off:off + n].reshape(f.shape)[c] - a[c]).max() / scale
             e2 = np.abs(g2[off:off + n].reshape(f.shape)[c] - b[c]).max() / scale
-            assert e1 < tol and e2 < tol, (prec, f.shape, c, e1, e2)
+            assert e1 < tol and e2 < tol, (prec, variant, f.shape, c, e1, e2)
         off += n
 
 
