@@ -505,6 +505,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BCOL"] = cv.take(c->bcol.size() * 8);
   o["BVAL"] = cv.take(c->bval.size() * D);
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
+  o["SDNNF"] = cv.take(64 * 84 * 4);  // classifier fragment table
   o["BCIDX"] = cv.take(P * 4);
   o["GCTR"] = cv.take(2 * PH_N * 4);  // tile counters of the persistent contractions
   o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
@@ -640,6 +641,8 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
   };
   for (auto& u : ups)
     if ((st = upload(c, u.n, u.p, u.b)) != FCS_OK) return st;
+  if (c->visc && c->prm.av_mode == FCS_AV_SDNN)
+    HIPCHK(c, launch_sdnn_pack(c->dptr<float>("SDNN"), c->dptr<uint32_t>("SDNNF"), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (auto& v : staging_tasks)
     for (auto& w : v) std::vector<GemmTask>().swap(w);
@@ -732,6 +735,7 @@ fcs_status per_step(fcs_ctx* c) {
     v.mu = c->arr[A_MU];
     v.mode = p.av_mode;
     v.weights = c->dptr<float>("SDNN");
+    v.sdnn_table = c->dptr<uint32_t>("SDNNF");
     v.basis = c->dptr<double>("BASIS");
     v.c_mu = p.c_mu;
     v.gamma = p.gamma;

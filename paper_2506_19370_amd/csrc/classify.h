@@ -64,10 +64,6 @@ typedef short sdnn_s16x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 sdnn_bf16x8 __attribute__((ext_vector_type(8)));
 typedef float sdnn_f32x4 __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
-  return static_cast<uint16_t>(__float_as_uint(bf16_round(f)) >> 16);
-}
-
 struct SdnnFrag {
   sdnn_s16x4 w1[4];       // layer 1, hidden tile ht
   sdnn_bf16x8 w2[4][2];   // layer 2, [output tile][input block]
@@ -80,44 +76,94 @@ __device__ __forceinline__ int sdnn_slot(int kb, int g, int j) { return 32 * kb 
 
 constexpr int kSdnnParams = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3;
 
-// Copies the parameter blob into LDS with coalesced reads (whole block).
-__device__ __forceinline__ void stage_sdnn_params(const float* __restrict__ src, float* dst) {
-  for (int q = threadIdx.x; q < kSdnnParams; q += blockDim.x) dst[q] = src[q];
-  __syncthreads();
-}
+// Fragment table: the weights and biases each lane needs, lane-major, 84
+// 32-bit words per lane (21 x 16 bytes):
+//   0..7    layer-1 weights, tile ht: words 2 ht, 2 ht + 1 (4 bf16)
+//   8..39   layer-2 weights, [output tile mt][input block kb]: 4 words each
+//   40..47  layer-3 weights, [input block kb]: 4 words each
+//   48..63  layer-1 biases of the lane's rows [ht][r] (FP32)
+//   64..79  layer-2 biases [ht][r]
+//   80..83  layer-3 biases of rows 4 g + r (zero beyond the 3 classes)
+constexpr int kSdnnFragWords = 84;
 
-// W: parameter blob (W1 64x16, b1, W2 64x64, b2, W3 3x64, b3), FP32 (in LDS).
-__device__ __forceinline__ void load_sdnn_frag(const float* W, SdnnFrag& F) {
+// bf16 bit pattern of f, round to nearest even (the rounding the oracle
+// applies).
+__device__ __forceinline__ uint32_t bf16_bits(float f) { return __float_as_uint(bf16_round(f)) >> 16; }
+
+__device__ __forceinline__ uint32_t bf16_pair(float a, float b) { return bf16_bits(a) | (bf16_bits(b) << 16); }
+
+// Word w of lane `lane`'s fragment table, from the FP32 parameter blob.
+__device__ __forceinline__ uint32_t sdnn_frag_word(const float* __restrict__ W, int lane, int w) {
   const float* W1 = W;
   const float* B1 = W1 + 64 * 16;
   const float* W2 = B1 + 64;
   const float* B2 = W2 + 64 * 64;
   const float* W3 = B2 + 64;
   const float* B3 = W3 + 3 * 64;
-  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int g = lane >> 4, c = lane & 15;
+  if (w < 8) {
+    const int ht = w >> 1, j = 2 * (w & 1);
+    const float* r = W1 + (16 * ht + c) * 16 + 4 * g + j;
+    return bf16_pair(r[0], r[1]);
+  }
+  if (w < 40) {
+    const int i = w - 8, mt = i >> 3, kb = (i >> 2) & 1, j = 2 * (i & 3);
+    const float* r = W2 + (16 * mt + c) * 64;
+    return bf16_pair(r[sdnn_slot(kb, g, j)], r[sdnn_slot(kb, g, j + 1)]);
+  }
+  if (w < 48) {
+    const int i = w - 40, kb = i >> 2, j = 2 * (i & 3);
+    if (c >= 3) return 0u;
+    const float* r = W3 + c * 64;
+    return bf16_pair(r[sdnn_slot(kb, g, j)], r[sdnn_slot(kb, g, j + 1)]);
+  }
+  float v;
+  if (w < 64) {
+    v = B1[16 * ((w - 48) >> 2) + 4 * g + ((w - 48) & 3)];
+  } else if (w < 80) {
+    v = B2[16 * ((w - 64) >> 2) + 4 * g + ((w - 64) & 3)];
+  } else {
+    const int row = 4 * g + (w - 80);
+    v = row < 3 ? B3[row] : 0.0f;
+  }
+  return __float_as_uint(v);
+}
+
+// Unpacks this lane's fragments from a table (global memory or LDS).
+__device__ __forceinline__ void load_sdnn_frag(const uint32_t* table, SdnnFrag& F) {
+  const uint4* t = reinterpret_cast<const uint4*>(table + (threadIdx.x & 63) * kSdnnFragWords);
+  uint4 q[21];
 #pragma unroll
-  for (int ht = 0; ht < 4; ++ht)
+  for (int i = 0; i < 21; ++i) q[i] = t[i];
+  const uint32_t* u = reinterpret_cast<const uint32_t*>(q);
 #pragma unroll
-    for (int j = 0; j < 4; ++j) F.w1[ht][j] = static_cast<short>(bf16_bits(W1[(16 * ht + c) * 16 + 4 * g + j]));
+  for (int ht = 0; ht < 4; ++ht) {
+    const uint32_t lo = u[2 * ht], hi = u[2 * ht + 1];
+    F.w1[ht] = sdnn_s16x4{static_cast<short>(lo & 0xFFFF), static_cast<short>(lo >> 16),
+                          static_cast<short>(hi & 0xFFFF), static_cast<short>(hi >> 16)};
+  }
 #pragma unroll
-  for (int kb = 0; kb < 2; ++kb)
+  for (int mt = 0; mt < 4; ++mt)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int h = sdnn_slot(kb, g, j);
+    for (int kb = 0; kb < 2; ++kb) F.w2[mt][kb] = __builtin_bit_cast(sdnn_bf16x8, q[2 + 2 * mt + kb]);
 #pragma unroll
-      for (int mt = 0; mt < 4; ++mt)
-        F.w2[mt][kb][j] = __builtin_bit_cast(__bf16, bf16_bits(W2[(16 * mt + c) * 64 + h]));
-      F.w3[kb][j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(c < 3 ? bf16_bits(W3[c * 64 + h]) : 0));
-    }
+  for (int kb = 0; kb < 2; ++kb) F.w3[kb] = __builtin_bit_cast(sdnn_bf16x8, q[10 + kb]);
 #pragma unroll
   for (int ht = 0; ht < 4; ++ht)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      F.b1[ht][r] = B1[16 * ht + 4 * g + r];
-      F.b2[ht][r] = B2[16 * ht + 4 * g + r];
+      F.b1[ht][r] = __uint_as_float(u[48 + 4 * ht + r]);
+      F.b2[ht][r] = __uint_as_float(u[64 + 4 * ht + r]);
     }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) F.b3[r] = (4 * g + r < 3) ? B3[4 * g + r] : 0.0f;
+  for (int r = 0; r < 4; ++r) F.b3[r] = __uint_as_float(u[80 + r]);
+}
+
+// Builds the fragment table of a parameter blob in LDS (whole block).
+__device__ __forceinline__ void build_sdnn_table(const float* __restrict__ W, uint32_t* table) {
+  for (int q = threadIdx.x; q < 64 * kSdnnFragWords; q += blockDim.x)
+    table[q] = sdnn_frag_word(W, q / kSdnnFragWords, q % kSdnnFragWords);
+  __syncthreads();
 }
 
 // Two 16-row tiles of pre-activations -> bf16 ReLU activations as one B
@@ -127,8 +173,8 @@ __device__ __forceinline__ sdnn_bf16x8 sdnn_act(const sdnn_f32x4& za, const floa
   sdnn_bf16x8 h;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    h[j] = __builtin_bit_cast(__bf16, bf16_bits(fmaxf(za[j] + ba[j], 0.0f)));
-    h[4 + j] = __builtin_bit_cast(__bf16, bf16_bits(fmaxf(zb[j] + bb[j], 0.0f)));
+    h[j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(bf16_bits(fmaxf(za[j] + ba[j], 0.0f))));
+    h[4 + j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(bf16_bits(fmaxf(zb[j] + bb[j], 0.0f))));
   }
   return h;
 }
@@ -139,7 +185,7 @@ __device__ __forceinline__ sdnn_bf16x8 sdnn_act(const sdnn_f32x4& za, const floa
 __device__ __forceinline__ void sdnn_mfma(const SdnnFrag& F, const float (&x)[4], float (&z)[3]) {
   sdnn_s16x4 xb;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) xb[j] = static_cast<short>(bf16_bits(x[j]));
+  for (int j = 0; j < 4; ++j) xb[j] = static_cast<short>(__float_as_uint(x[j]) >> 16);  // x is bf16-exact
   const sdnn_f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
   sdnn_f32x4 z1[4];
 #pragma unroll

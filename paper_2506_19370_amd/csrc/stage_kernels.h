@@ -57,6 +57,7 @@ struct ClassifyArgs {
   double* muhat;
   int mode;  // 1 modal, 2 sdnn, 3 frozen
   const float* weights;
+  const uint32_t* sdnn_table;  // fragment table of the weights (mode 2)
   const double* basis;
   double c_mu;
 };
@@ -74,6 +75,7 @@ struct ViscArgs {
   double *muhat, *tmp, *mut, *mu;
   int mode;
   const float* weights;
+  const uint32_t* sdnn_table;
   const double* basis;
   double c_mu, gamma;
   int nv;
@@ -98,6 +100,8 @@ hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pa
 // that reads the state), then classification, preliminary viscosity,
 // dilation and blend.
 hipError_t launch_proxy(const ViscArgs& v, hipStream_t s);
+// Fragment table (64 x 84 words) of a classifier parameter blob.
+hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);

@@ -272,10 +272,8 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
 // by lane shuffles; lanes 0..15 write the classes and the preliminary
 // viscosity of the points of their rounds.
 __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
-  __shared__ float Wl[kSdnnParams];
-  stage_sdnn_params(a.weights, Wl);
   SdnnFrag F;
-  load_sdnn_frag(Wl, F);
+  load_sdnn_frag(a.sdnn_table, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t kw = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
   // geometry of this lane's point kw + lane
@@ -318,6 +316,13 @@ __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
       a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
     }
   }
+}
+
+// Fragment table of the classifier (see classify.h), built once per
+// context by one workgroup.
+__global__ __launch_bounds__(256) void k_sdnn_pack(const float* __restrict__ W, uint32_t* __restrict__ table) {
+  for (int q = threadIdx.x; q < 64 * kSdnnFragWords; q += blockDim.x)
+    table[q] = sdnn_frag_word(W, q / kSdnnFragWords, q % kSdnnFragWords);
 }
 
 // One pass of the windowed max: out(k) = max_off in(k + off * stride) w(|off|)
@@ -468,6 +473,11 @@ hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pa
   return hipGetLastError();
 }
 
+hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s) {
+  hipLaunchKernelGGL(k_sdnn_pack, dim3(1), dim3(256), 0, s, weights, table);
+  return hipGetLastError();
+}
+
 hipError_t launch_proxy(const ViscArgs& v, hipStream_t s) {
   hipLaunchKernelGGL(k_proxy, grid_for(v.P), dim3(256), 0, s, v.U, v.flags, v.phi, v.spd, v.P, v.gamma);
   return hipGetLastError();
@@ -488,6 +498,7 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   c.muhat = v.muhat;
   c.mode = v.mode;
   c.weights = v.weights;
+  c.sdnn_table = v.sdnn_table;
   c.basis = v.basis;
   c.c_mu = v.c_mu;
   if (c.mode == 2)

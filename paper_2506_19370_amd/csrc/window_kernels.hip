@@ -26,10 +26,10 @@ __global__ __launch_bounds__(256) void k_classify_modal(ModalBasis basis, const 
 __global__ __launch_bounds__(256) void k_classify_sdnn_windows(const float* __restrict__ params,
                                                                const double* __restrict__ windows, int64_t nwin,
                                                                uint8_t* __restrict__ tau, float* __restrict__ logits) {
-  __shared__ float Wl[kSdnnParams];
-  stage_sdnn_params(params, Wl);
+  __shared__ __attribute__((aligned(16))) uint32_t table[64 * kSdnnFragWords];
+  build_sdnn_table(params, table);
   SdnnFrag F;
-  load_sdnn_frag(Wl, F);
+  load_sdnn_frag(table, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t w0 = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
 #pragma unroll 1
