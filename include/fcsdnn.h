@@ -173,9 +173,11 @@ fcs_status fcs_get_field(fcs_ctx* ctx, int32_t patch, int32_t field,
 /* Counters, time, last step and integrals (synchronizes). */
 fcs_status fcs_stats(fcs_ctx* ctx, fcs_stats_t* out);
 
-/* Average duration (ms) of the dominant derivative-contraction launch over
- * the advance calls since the last reset, measured with HIP events on the
- * bound stream, and the algorithmic flops and bytes of one such launch.
+/* Average duration (ms) of the dominant derivative-contraction launch (the
+ * stage contraction of stages 2 to 5 of each step; the first stage's launch
+ * also carries the viscosity gradient) over the advance calls since the last
+ * reset, measured with HIP events on the bound stream, and the algorithmic
+ * flops and bytes of one such launch.
  * Timing is recorded only after fcs_profile_enable(ctx, 1).  Whole steps
  * then replay a separate graph that carries event-record nodes around each
  * stage contraction and one empty pair of event nodes; *event_latency_ms

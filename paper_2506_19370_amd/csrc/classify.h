@@ -173,8 +173,9 @@ __device__ __forceinline__ sdnn_bf16x8 sdnn_act(const sdnn_f32x4& za, const floa
   sdnn_bf16x8 h;
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
-    h[j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(bf16_bits(fmaxf(za[j] + ba[j], 0.0f))));
-    h[4 + j] = __builtin_bit_cast(__bf16, static_cast<uint16_t>(bf16_bits(fmaxf(zb[j] + bb[j], 0.0f))));
+    // v_cvt_pk_bf16_f32 rounds to nearest even, as bf16_round does
+    h[j] = static_cast<__bf16>(fmaxf(za[j] + ba[j], 0.0f));
+    h[4 + j] = static_cast<__bf16>(fmaxf(zb[j] + bb[j], 0.0f));
   }
   return h;
 }
@@ -222,17 +223,18 @@ __device__ __forceinline__ int sdnn_argmax(const float (&z)[3]) {
 __device__ __forceinline__ bool sdnn_features(const double (&v)[4], float (&x)[4]) {
   double lo = fmin(fmin(v[0], v[1]), fmin(v[2], v[3]));
   double hi = fmax(fmax(v[0], v[1]), fmax(v[2], v[3]));
-  double am = fmax(fmax(fabs(v[0]), fabs(v[1])), fmax(fabs(v[2]), fabs(v[3])));
   lo = fmin(lo, __shfl_xor(lo, 16));
   hi = fmax(hi, __shfl_xor(hi, 16));
-  am = fmax(am, __shfl_xor(am, 16));
   lo = fmin(lo, __shfl_xor(lo, 32));
   hi = fmax(hi, __shfl_xor(hi, 32));
-  am = fmax(am, __shfl_xor(am, 32));
+  const double am = fmax(fabs(lo), fabs(hi));  // max |v| over the window
   const double range = hi - lo;
   const bool live = !(range < 1e-3 * fmax(am, 1.0));
+  // one reciprocal per window; (v - lo) * (1 / range) and (v - lo) / range
+  // differ by at most one FP64 ulp, far below the bf16 rounding that follows
+  const double inv = live ? 1.0 / range : 0.0;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) x[j] = live ? bf16_round(static_cast<float>((v[j] - lo) / range)) : 0.0f;
+  for (int j = 0; j < 4; ++j) x[j] = live ? bf16_round(static_cast<float>((v[j] - lo) * inv)) : 0.0f;
   return live;
 }
 

@@ -117,18 +117,24 @@ __device__ __forceinline__ void store_tile(const GemmTask& T, const int64_t* dst
 
 // FP64 or FP32 operands on the 16x16x4 MFMA of that type.
 template <typename Elem, int KC, int TB>
-__device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, const GemmTile tile,
-                                        const OpTables& ops) {
+struct SmemFp {
+  Elem Xs[2][kLB][KC + 1];
+  Elem Ds[2][64 * TB][KC + 1];
+  int64_t dst[kLB];
+};
+
+template <typename Elem, int KC, int TB, bool Q1>
+__device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                            SmemFp<Elem, KC, TB>& sm) {
   constexpr bool kF64 = sizeof(Elem) == 8;
   constexpr int kTT = 64 * TB;
   constexpr int kDV = 16 / sizeof(Elem);        // operator elements per 16-byte load
   constexpr int ND = kTT * KC / (256 * kDV);    // 16-byte operator loads per thread
   static_assert(ND >= 1, "tile too small for the operator loader");
   typedef Elem vec4 __attribute__((ext_vector_type(4)));
-  __shared__ Elem Xs[2][kLB][KC + 1];
-  __shared__ Elem Ds[2][kTT][KC + 1];
-  __shared__ int64_t dst[kLB];
-  const GemmTask T = tasks[tile.task];
+  auto& Xs = sm.Xs;
+  auto& Ds = sm.Ds;
+  int64_t* dst = sm.dst;
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
   const int nl = min(kLB, nlines - tile.line0);
   const int ld = ops.ld[T.op];
@@ -138,7 +144,7 @@ __device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, cons
   else
     D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool q1 = T.s_stride == 1;
+  constexpr bool q1 = Q1;
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   XLoad<KC> xl;
   xl.init(T, tile.line0, nlines, q1);
@@ -209,6 +215,19 @@ __device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, cons
                        nullptr);
 }
 
+// The direction decides the operand roles of every MFMA; it is resolved
+// once per tile so that the inner loop holds no branch.
+template <typename Elem, int KC, int TB>
+__device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, const GemmTile tile,
+                                        const OpTables& ops) {
+  __shared__ SmemFp<Elem, KC, TB> sm;
+  const GemmTask T = tasks[tile.task];
+  if (T.s_stride == 1)
+    gemm_fp_dir<Elem, KC, TB, true>(T, tile, ops, sm);
+  else
+    gemm_fp_dir<Elem, KC, TB, false>(T, tile, ops, sm);
+}
+
 // Operator in registers: only the operand lines (shared by the four waves)
 // are staged in LDS; each wave loads the operator rows of its own output
 // blocks straight from L2 into MFMA operand registers.  Within a chunk of 16
@@ -218,8 +237,15 @@ __device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, cons
 // columns of one line (16-byte LDS reads).  The operator loads of chunk c+1
 // are issued before the products of chunk c.  TB (2 or 4) 16-output blocks
 // per wave: a workgroup covers 64 lines x 64 TB outputs.
-template <typename Elem, int KC, int TB>
-__device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, const GemmTile tile, const OpTables& ops) {
+template <typename Elem, int KC>
+struct SmemXs {
+  alignas(16) Elem Xs[2][kLB][KC + 16 / sizeof(Elem)];
+  int64_t dst[kLB];
+};
+
+template <typename Elem, int KC, int TB, bool Q1>
+__device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                            SmemXs<Elem, KC>& sm) {
   constexpr bool kF64 = sizeof(Elem) == 8;
   constexpr int kTT = 64 * TB;
   constexpr int PITCH = KC + 16 / sizeof(Elem);   // 16-byte aligned rows
@@ -227,9 +253,8 @@ __device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, cons
   constexpr int NS = KC / 16;                     // 16-column sub-chunks
   constexpr int DQ = 4 * sizeof(Elem) / 16;       // 16-byte loads per 4 operator values
   typedef Elem vec4 __attribute__((ext_vector_type(4)));
-  __shared__ __attribute__((aligned(16))) Elem Xs[2][kLB][PITCH];
-  __shared__ int64_t dst[kLB];
-  const GemmTask T = tasks[tile.task];
+  auto& Xs = sm.Xs;
+  int64_t* dst = sm.dst;
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
   const int nl = min(kLB, nlines - tile.line0);
   const int ld = ops.ld[T.op];
@@ -239,7 +264,7 @@ __device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, cons
   else
     D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
-  const bool q1 = T.s_stride == 1;
+  constexpr bool q1 = Q1;
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   // operand staging: one line and NX consecutive columns per thread
   const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
@@ -330,6 +355,16 @@ __device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, cons
 }
 
 template <typename Elem, int KC, int TB>
+__device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, const GemmTile tile, const OpTables& ops) {
+  __shared__ SmemXs<Elem, KC> sm;
+  const GemmTask T = tasks[tile.task];
+  if (T.s_stride == 1)
+    gemm_xs_dir<Elem, KC, TB, true>(T, tile, ops, sm);
+  else
+    gemm_xs_dir<Elem, KC, TB, false>(T, tile, ops, sm);
+}
+
+template <typename Elem, int KC, int TB>
 __global__ __launch_bounds__(256) void k_gemm_xs(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
   gemm_xs<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
@@ -384,17 +419,26 @@ __global__ __launch_bounds__(256) void k_gemm_step(const GemmTask* __restrict__ 
 // Split BF16: chunks of 32 columns (one MFMA depth); LDS rows padded to 40
 // halves so each lane's 8-element operand is one aligned 16-byte read.
 template <int TB>
-__device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, const GemmTile tile,
-                                            const OpTables& ops) {
+struct SmemBf {
+  alignas(16) uint16_t Xh[2][kLB][40];
+  alignas(16) uint16_t Xl[2][kLB][40];
+  alignas(16) uint16_t Dh[2][64 * TB][40];
+  alignas(16) uint16_t Dl[2][64 * TB][40];
+  double x0s[kLB];
+  int64_t dst[kLB];
+};
+
+template <int TB, bool Q1>
+__device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                                SmemBf<TB>& sm) {
   constexpr int KC = 32, PITCH = 40, kTT = 64 * TB;
   constexpr int ND = kTT * KC / (256 * 8);  // 16-byte loads per thread and table
-  __shared__ __attribute__((aligned(16))) uint16_t Xh[2][kLB][PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Xl[2][kLB][PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Dh[2][kTT][PITCH];
-  __shared__ __attribute__((aligned(16))) uint16_t Dl[2][kTT][PITCH];
-  __shared__ double x0s[kLB];
-  __shared__ int64_t dst[kLB];
-  const GemmTask T = tasks[tile.task];
+  auto& Xh = sm.Xh;
+  auto& Xl = sm.Xl;
+  auto& Dh = sm.Dh;
+  auto& Dl = sm.Dl;
+  double* x0s = sm.x0s;
+  int64_t* dst = sm.dst;
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
   const int nl = min(kLB, nlines - tile.line0);
   const int ld = ops.ld[T.op];
@@ -402,7 +446,7 @@ __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, 
   const uint16_t* __restrict__ Bh = ops.bhi + dbase;
   const uint16_t* __restrict__ Bl = ops.blo + dbase;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const bool q1 = T.s_stride == 1;
+  constexpr bool q1 = Q1;
   // Operand staging: each thread owns 8 consecutive columns of one line of
   // the chunk (along q^1 four threads share a line, along q^2 neighbouring
   // threads hold neighbouring lines), splits them with packed conversions and
@@ -492,6 +536,17 @@ __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, 
   }
   // the two FP32 accumulations are added in FP64 at the store
   store_tile<false, TB>(T, dst, nl, t0, nt, q1, wave, lane, am, ac, x0s, ops.rowsum + ops.roff[T.op]);
+}
+
+template <int TB>
+__device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, const GemmTile tile,
+                                            const OpTables& ops) {
+  __shared__ SmemBf<TB> sm;
+  const GemmTask T = tasks[tile.task];
+  if (T.s_stride == 1)
+    gemm_bf16x3_dir<TB, true>(T, tile, ops, sm);
+  else
+    gemm_bf16x3_dir<TB, false>(T, tile, ops, sm);
 }
 
 template <int TB>

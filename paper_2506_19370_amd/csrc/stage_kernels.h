@@ -52,7 +52,9 @@ struct ClassifyArgs {
   const int32_t* pid;
   const PatchDev* patches;
   const int2 *rowrun, *colrun;
-  const double *phi, *spd, *hx;
+  const double2* ps;     // proxy and wave speed |u| + a of every point
+  const int32_t* ij;     // (j << 16) | i of every point
+  const double* hx;
   uint8_t* tau;
   double* muhat;
   int mode;  // 1 modal, 2 sdnn, 3 frozen
@@ -69,7 +71,8 @@ struct ViscArgs {
   const int32_t* pid;
   const PatchDev* patches;
   const int2 *rowrun, *colrun;
-  double *phi, *spd;
+  double2* ps;
+  const int32_t* ij;
   const double* hx;
   uint8_t* tau;
   double *muhat, *tmp, *mut, *mu;

@@ -198,20 +198,18 @@ __global__ void k_fringe(double* __restrict__ U, const uint8_t* __restrict__ fla
 }
 
 // Proxy (Mach number) and |u| + a at every point.
-__global__ void k_proxy(const double* __restrict__ U, const uint8_t* __restrict__ flags, double* __restrict__ phi,
-                        double* __restrict__ spd, int64_t P, double gamma) {
+__global__ void k_proxy(const double* __restrict__ U, const uint8_t* __restrict__ flags, double2* __restrict__ ps,
+                        int64_t P, double gamma) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
   if (!(flags[k] & kActive)) {
-    phi[k] = 0.0;
-    spd[k] = 0.0;
+    ps[k] = double2{0.0, 0.0};
     return;
   }
   double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
   double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
   double speed = sqrt(mx * mx + my * my) / r;
-  phi[k] = speed * sqrt(r / (gamma * p));
-  spd[k] = speed + sqrt(gamma * p / r);
+  ps[k] = double2{speed * sqrt(r / (gamma * p)), speed + sqrt(gamma * p / r)};
 }
 
 // Window geometry of point k along direction dir: start index of the
@@ -221,8 +219,8 @@ __device__ __forceinline__ bool window_at(const ClassifyArgs& a, int64_t k, uint
                                           int64_t& stride) {
   if (!(f & kActive)) return false;
   const PatchDev pd = a.patches[a.pid[k]];
-  const int64_t loc = k - pd.offset;
-  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
+  const int32_t ij = a.ij[k];
+  const int j = ij >> 16, i = ij & 0xFFFF;
   const int2 run = dir == 0 ? a.rowrun[pd.row_run + j] : a.colrun[pd.col_run + i];
   if (run.y < 16) return false;
   const int pos = dir == 0 ? i : j;
@@ -251,11 +249,11 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
   for (int dir = 0; dir < 2; ++dir) {
     int64_t base, stride;
     if (!window_at(a, k, f, dir, base, stride)) continue;
-    for (int m = 0; m < 16; ++m) smax = fmax(smax, a.spd[base + m * stride]);
+    for (int m = 0; m < 16; ++m) smax = fmax(smax, a.ps[base + m * stride].y);
     if (a.mode == 3) {
       tau[dir] = a.tau[dir * a.P + k];
     } else {
-      for (int m = 0; m < 16; ++m) v[m] = a.phi[base + m * stride];
+      for (int m = 0; m < 16; ++m) v[m] = a.ps[base + m * stride].x;
       tau[dir] = classify_modal(v, a.basis);
     }
   }
@@ -295,8 +293,9 @@ __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int64_t e = base + (4 * g + j) * stride;
-        v[j] = valid ? a.phi[e] : 0.0;
-        sp = fmax(sp, valid ? a.spd[e] : 0.0);
+        const double2 q = valid ? a.ps[e] : double2{0.0, 0.0};
+        v[j] = q.x;
+        sp = fmax(sp, q.y);
       }
       sp = fmax(sp, __shfl_xor(sp, 16));
       sp = fmax(sp, __shfl_xor(sp, 32));
@@ -329,13 +328,14 @@ __global__ __launch_bounds__(256) void k_sdnn_pack(const float* __restrict__ W, 
 // over the index box (dir 0 along q^1, 1 along q^2); the final pass zeroes
 // inactive points.
 __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ pid,
-                         const PatchDev* __restrict__ patches, const uint8_t* __restrict__ flags, int64_t P, int dir,
-                         int nv, const double* __restrict__ w, double* __restrict__ mu) {
+                         const int32_t* __restrict__ ijs, const PatchDev* __restrict__ patches,
+                         const uint8_t* __restrict__ flags, int64_t P, int dir, int nv, const double* __restrict__ w,
+                         double* __restrict__ mu) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const PatchDev pd = patches[pid[k]];
-  const int64_t loc = k - pd.offset;
-  const int j = static_cast<int>(loc / pd.n1), i = static_cast<int>(loc - static_cast<int64_t>(j) * pd.n1);
+  const int32_t ij = ijs[k];
+  const int j = ij >> 16, i = ij & 0xFFFF;
   const int pos = dir == 0 ? i : j, len = dir == 0 ? pd.n1 : pd.n2;
   const int64_t stride = dir == 0 ? 1 : pd.n1;
   double best = 0.0;
@@ -479,7 +479,7 @@ hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s
 }
 
 hipError_t launch_proxy(const ViscArgs& v, hipStream_t s) {
-  hipLaunchKernelGGL(k_proxy, grid_for(v.P), dim3(256), 0, s, v.U, v.flags, v.phi, v.spd, v.P, v.gamma);
+  hipLaunchKernelGGL(k_proxy, grid_for(v.P), dim3(256), 0, s, v.U, v.flags, v.ps, v.P, v.gamma);
   return hipGetLastError();
 }
 
@@ -491,8 +491,8 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   c.patches = v.patches;
   c.rowrun = v.rowrun;
   c.colrun = v.colrun;
-  c.phi = v.phi;
-  c.spd = v.spd;
+  c.ps = v.ps;
+  c.ij = v.ij;
   c.hx = v.hx;
   c.tau = v.tau;
   c.muhat = v.muhat;
@@ -505,10 +505,10 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
     hipLaunchKernelGGL(k_classify_sdnn, grid_for(v.P), dim3(256), 0, s, c);
   else
     hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
-  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.patches, v.flags, v.P, 0,
-                     v.nv, v.wdil, nullptr);
-  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.patches, v.flags, v.P, 1,
-                     v.nv, v.wdil, v.mu);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
+                     0, v.nv, v.wdil, nullptr);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.ij, v.patches, v.flags, v.P,
+                     1, v.nv, v.wdil, v.mu);
   if (v.nblend)
     hipLaunchKernelGGL(k_blend_rows, grid_for(v.nblend), dim3(256), 0, s, v.mut, v.mu, v.bdst, v.bptr, v.bcol,
                        v.bval, v.nblend);
