@@ -279,7 +279,8 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
 #pragma unroll
     for (int j = 0; j < NX; ++j) Xs[b][xs_line][xs_col + j] = static_cast<Elem>(xr[j]);
   };
-  // operator fragments: block i of this wave, sub-chunk s, 4 values
+  // operator fragments: block i of this wave, sub-chunk s, 4 values (blocks
+  // past the tile's outputs read zero-padded rows and are not stored)
   uint4 dr[TB][NS][DQ];
   auto load_d = [&](int k0) {
 #pragma unroll
@@ -289,8 +290,7 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
       for (int sc = 0; sc < NS; ++sc)
 #pragma unroll
         for (int q = 0; q < DQ; ++q)
-          dr[i][sc][q] = 16 * (wave + 4 * i) < nt ? *reinterpret_cast<const uint4*>(row + 16 * sc + q * (16 / sizeof(Elem)))
-                                                  : uint4{0, 0, 0, 0};
+          dr[i][sc][q] = *reinterpret_cast<const uint4*>(row + 16 * sc + q * (16 / sizeof(Elem)));
     }
   };
   vec4 acc[TB][4];
@@ -332,7 +332,6 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
       }
 #pragma unroll
       for (int i = 0; i < TB; ++i) {
-        if (16 * (wave + 4 * i) >= nt) continue;
         const Elem* dv = reinterpret_cast<const Elem*>(&dn[i][sc][0]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -365,7 +364,7 @@ __device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, cons
 }
 
 template <typename Elem, int KC, int TB>
-__global__ __launch_bounds__(256) void k_gemm_xs(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, sizeof(Elem) == 8 ? 2 : 1) void k_gemm_xs(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
   gemm_xs<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
 }
@@ -396,14 +395,16 @@ __device__ __forceinline__ void persistent_tiles(int ntiles, int* ctr, Body body
 }
 
 // Stage contractions (every SSPRK stage) ...
+// Launch bounds: the second argument asks for that many waves per SIMD, which
+// bounds the registers per lane (no spills at these shapes).
 template <typename Elem, int KC, int TB>
-__global__ __launch_bounds__(256) void k_gemm_fp(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, 4) void k_gemm_fp(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
   gemm_fp<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
 }
 
 template <typename Elem, int KC, int TB>
-__global__ __launch_bounds__(256) void k_gemm_fp_persist(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, 4) void k_gemm_fp_persist(const GemmTask* __restrict__ tasks,
                                                          const GemmTile* __restrict__ tiles, int ntiles,
                                                          OpTables ops, int* ctr) {
   persistent_tiles(ntiles, ctr, [&](int t) { gemm_fp<Elem, KC, TB>(tasks, tiles[t], ops); });
@@ -411,7 +412,7 @@ __global__ __launch_bounds__(256) void k_gemm_fp_persist(const GemmTask* __restr
 
 // ... and the once-per-step FP64 contractions (viscosity gradient, filter),
 // under their own name so that profiles tell the two apart.
-__global__ __launch_bounds__(256) void k_gemm_step(const GemmTask* __restrict__ tasks,
+__global__ __launch_bounds__(256, 4) void k_gemm_step(const GemmTask* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles, OpTables ops) {
   gemm_fp<double, 16, 1>(tasks, tiles[blockIdx.x], ops);
 }

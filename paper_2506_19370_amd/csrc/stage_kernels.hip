@@ -339,11 +339,23 @@ __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out
   const int pos = dir == 0 ? i : j, len = dir == 0 ? pd.n1 : pd.n2;
   const int64_t stride = dir == 0 ? 1 : pd.n1;
   double best = 0.0;
-  for (int off = -nv; off <= nv; ++off) {
-    int q = pos + off;
-    if (q < 0 || q >= len) continue;
-    double val = in[k + off * stride] * w[off < 0 ? -off : off];
-    if (val > best) best = val;
+  if (nv == 9) {
+    // the default radius: unrolled and branch-free, so all 19 loads are in
+    // flight together (terms outside the line read the point itself with
+    // weight 0, which cannot raise the max of non-negative values)
+#pragma unroll
+    for (int off = -9; off <= 9; ++off) {
+      const bool ok = pos + off >= 0 && pos + off < len;
+      const double val = in[k + (ok ? off : 0) * stride] * (ok ? w[off < 0 ? -off : off] : 0.0);
+      best = fmax(best, val);
+    }
+  } else {
+    for (int off = -nv; off <= nv; ++off) {
+      int q = pos + off;
+      if (q < 0 || q >= len) continue;
+      double val = in[k + off * stride] * w[off < 0 ? -off : off];
+      if (val > best) best = val;
+    }
   }
   if (mu) {
     // final pass: inactive points carry no viscosity; the blend rows then
