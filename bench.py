@@ -41,6 +41,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the derivative-sweep and classifier measurements")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -73,6 +74,59 @@ def train_classifier(F, W, torch, steps=300, batch=4096):
         tr.step(x[sel].contiguous(), y[sel].contiguous(), cw)
     torch.cuda.synchronize()
     return params.cpu().numpy()
+
+
+def sweep_bench(F, W, torch):
+    """Grouped derivative contraction on its own: 2000 patches with sides
+    drawn from 64..256, four fields, d/dq1 and d/dq2 (FC d = 5, C = 27) in one
+    launch, each precision autotuned; rates against each precision's MFMA peak
+    and against the FP32 peak (FP32-equivalent work)."""
+    sizes, fields = W.deriv_sweep(2000)
+    x = torch.tensor(np.concatenate([f.ravel() for f in fields]), device="cuda")
+    d1, d2 = torch.empty_like(x), torch.empty_like(x)
+    out = {"workload": "2000 patches, sides U{64..256}, 4 fields, d/dq1 and d/dq2, FC d=5 C=27, one launch",
+           "points": int(sum(int(a) * int(b) for a, b in sizes))}
+    for prec in ("fp64", "fp32", "bf16x3"):
+        sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
+        sw.autotune(x, d1, d2)
+        sw.profile(1)
+        for _ in range(10):
+            sw.run(x, d1, d2)
+        r = sw.profile(-1)
+        rate = r["flops"] / (r["avg_ms"] * 1e-3)
+        own = PEAK["fp32"] if prec == "bf16x3" else PEAK[prec]
+        out[prec] = {"ms": r["avg_ms"], "tflops": rate / 1e12, "frac_of_fp32_peak": rate / PEAK["fp32"],
+                     "frac_of_own_peak": rate / own if prec != "bf16x3" else None,
+                     "algorithmic_GBps": r["bytes"] / (r["avg_ms"] * 1e-3) / 1e9}
+        del sw
+    return out
+
+
+def classifier_bench(F, W, torch, weights):
+    """Window classification throughput: 10^7 windows of FC-filtered
+    synthetic lines (smooth Fourier sums with 0-2 jumps), trained SDNN on
+    the matrix cores vs the modal-decay fallback."""
+    lines, _, _ = W.classifier_lines(20000, seed_salt=61)
+    filt = F.lines_apply(torch.tensor(lines, device="cuda"), "filter", 2, 27)
+    n = lines.shape[1]
+    start = np.clip(np.arange(n) - 8, 0, n - 16)
+    idx = torch.tensor(start[:, None] + np.arange(16)[None, :], device="cuda")
+    base = filt[:, idx].reshape(-1, 16)
+    nwin = 10_000_000
+    wins = base.repeat((nwin + base.shape[0] - 1) // base.shape[0], 1)[:nwin].contiguous()
+    p = torch.tensor(weights, device="cuda")
+    out = {"windows": nwin}
+    for name, fn in (("sdnn", lambda: F.sdnn_infer(p, wins)), ("modal", lambda: F.modal_infer(wins))):
+        fn()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(3):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 3
+        out[name] = {"ms": ms, "windows_per_s": nwin / (ms * 1e-3)}
+    return out
 
 
 def make_solver(F, W, torch, weights, precision, stream):
@@ -205,6 +259,9 @@ def main():
             del Sm
         best = max(forms, key=lambda k: forms[k]["value"])
         out["mixed"] = {"best": best, **forms}
+    if not a.no_extras:
+        out["derivative_sweep"] = sweep_bench(F, W, torch)
+        out["classifier"] = classifier_bench(F, W, torch, weights)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_steps)
     print(json.dumps(out))

@@ -77,6 +77,9 @@ struct fcs_ctx {
   std::vector<Grid> grids;
   int64_t P = 0, nactive = 0;
   bool visc = false, cross = false;
+  // mixed forms store the stage derivatives as FP32 (not with the cross
+  // phase, which reads W1 as an FP64 operand)
+  bool deriv_f32 = false;
   std::string err;
 
   // operators (zero-padded tables shared by all precisions)
@@ -462,6 +465,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_FILT2, g, 1, FCS_OP_FILTER, A_DF1, 0, A_DF2, 0, 4);
     }
   }
+  c->deriv_f32 = p.precision != FCS_PREC_FP64 && !c->cross;
   if (c->visc) {
     c->phase_tasks[PH_EULER0] = c->phase_tasks[PH_EULER];
     c->phase_tasks[PH_EULER0].insert(c->phase_tasks[PH_EULER0].end(), c->phase_tasks[PH_MUGRAD].begin(),
@@ -600,7 +604,11 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
         GemmTask t{};
         double* sbase = s.src_arr == A_IN ? c->arr[A_U0 + v] : c->arr[s.src_arr];
         t.src = sbase + s.src_off;
-        t.dst = c->arr[s.dst_arr] + s.dst_off;
+        const bool f32 = c->deriv_f32 && (ph == PH_EULER || ph == PH_EULER0) && s.dst_arr != A_MU1 &&
+                         s.dst_arr != A_MU2;
+        // element offsets count in the stored type
+        t.dst = f32 ? static_cast<void*>(reinterpret_cast<float*>(c->arr[s.dst_arr]) + s.dst_off)
+                    : static_cast<void*>(c->arr[s.dst_arr] + s.dst_off);
         t.comp_stride = P;
         t.row_stride = s.row_stride;
         t.s_stride = s.s_stride;
@@ -608,6 +616,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
         t.ncomp = s.ncomp;
         t.n = s.n;
         t.op = s.op;
+        t.out_f32 = f32 ? 1 : 0;
         dt.push_back(t);
       }
       std::string name = "TASK" + std::to_string(ph) + "_" + std::to_string(v);
@@ -849,6 +858,7 @@ fcs_status one_stage(fcs_ctx* c, int s) {
     a.W22 = c->arr[A_W22];
     a.W12 = c->cross ? c->arr[A_W12] : nullptr;
   }
+  a.deriv_f32 = c->deriv_f32;
   double* scal = c->dptr<double>("SCAL");
   a.dt = scal + 1;
   a.bad_flag = reinterpret_cast<int*>(scal + 3);

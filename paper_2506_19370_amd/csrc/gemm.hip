@@ -109,7 +109,11 @@ __device__ __forceinline__ void store_tile(const GemmTask& T, const int64_t* dst
         double v = static_cast<double>(acc[i][lb][r]);
         if (acc2) v += static_cast<double>(acc2[i][lb][r]);
         if (rowsum) v += x0s[lloc] * rowsum[t0 + tloc];
-        T.dst[dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride] = v;
+        const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
+        if (T.out_f32)
+          static_cast<float*>(T.dst)[o] = static_cast<float>(v);
+        else
+          static_cast<double*>(T.dst)[o] = v;
       }
     }
   }

@@ -13,12 +13,14 @@ namespace fcs {
 // (row_stride 1) neighbouring lines are neighbouring doubles.
 struct GemmTask {
   const double* src;
-  double* dst;
+  void* dst;        // double, or float when out_f32
   int64_t comp_stride;
   int32_t row_stride, s_stride;
   int32_t nrow, ncomp;
-  int32_t n;       // line length = operator size
-  int32_t op;      // operator index (into the operator tables)
+  int32_t n;        // line length = operator size
+  int32_t op;       // operator index (into the operator tables)
+  int32_t out_f32;  // results stored as FP32 (mixed-precision stage derivatives)
+  int32_t pad;
 };
 
 struct GemmTile {

@@ -35,11 +35,12 @@ struct StageArgs {
   const uint8_t* flags;
   const double *in, *U0;
   double *out, *acc;
-  const double *DF1, *DF2;
+  const void *DF1, *DF2;  // stage derivatives: double, or float when deriv_f32
   const double *t1x, *t1y, *t2x, *t2y;
   int visc;
   const double *mu, *mu1, *mu2, *g11, *g12, *g22, *lap1, *lap2;
-  const double *W1, *W2, *W11, *W22, *W12;
+  const void *W1, *W2, *W11, *W22, *W12;
+  int deriv_f32;
   const double* dt;
   int* bad_flag;
   BcArgs bcs;

@@ -96,7 +96,12 @@ __device__ __forceinline__ void apply_bc(const BcEntry& b, double gamma, double 
   }
 }
 
+// DT: element type of the stage derivatives (double, or float in the mixed
+// forms, where the contractions themselves are FP32 or split BF16).
+template <typename DT>
 __global__ void k_stage(StageArgs a) {
+  const DT* DF1 = static_cast<const DT*>(a.DF1);
+  const DT* DF2 = static_cast<const DT*>(a.DF2);
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t P = a.P;
   if (k >= P) return;
@@ -109,19 +114,22 @@ __global__ void k_stage(StageArgs a) {
   const double dt = *a.dt;
   double L[4];
   if (f & kAffine) {
-    for (int q = 0; q < 4; ++q) L[q] = -(a.DF1[q * P + k] + a.DF2[(4 + q) * P + k]);
+    for (int q = 0; q < 4; ++q) L[q] = -(static_cast<double>(DF1[q * P + k]) + static_cast<double>(DF2[(4 + q) * P + k]));
   } else {
     double t1x = a.t1x[k], t1y = a.t1y[k], t2x = a.t2x[k], t2y = a.t2y[k];
     for (int q = 0; q < 4; ++q)
-      L[q] = -(t1x * a.DF1[q * P + k] + t1y * a.DF1[(4 + q) * P + k] + t2x * a.DF2[q * P + k] +
-               t2y * a.DF2[(4 + q) * P + k]);
+      L[q] = -(t1x * static_cast<double>(DF1[q * P + k]) + t1y * static_cast<double>(DF1[(4 + q) * P + k]) +
+               t2x * static_cast<double>(DF2[q * P + k]) + t2y * static_cast<double>(DF2[(4 + q) * P + k]));
   }
   if (a.visc) {
     double mu = a.mu[k], mu1 = a.mu1[k], mu2 = a.mu2[k];
     double g11 = a.g11[k], g12 = a.g12[k], g22 = a.g22[k], l1 = a.lap1[k], l2 = a.lap2[k];
+    const DT *W1 = static_cast<const DT*>(a.W1), *W2 = static_cast<const DT*>(a.W2);
+    const DT *W11 = static_cast<const DT*>(a.W11), *W22 = static_cast<const DT*>(a.W22);
+    const DT* W12 = static_cast<const DT*>(a.W12);
     for (int q = 0; q < 4; ++q) {
-      double w1 = a.W1[q * P + k], w2 = a.W2[q * P + k], w11 = a.W11[q * P + k], w22 = a.W22[q * P + k];
-      double w12 = a.W12 ? a.W12[q * P + k] : 0.0;
+      double w1 = W1[q * P + k], w2 = W2[q * P + k], w11 = W11[q * P + k], w22 = W22[q * P + k];
+      double w12 = W12 ? static_cast<double>(W12[q * P + k]) : 0.0;
       double lap = g11 * w11 + 2.0 * g12 * w12 + g22 * w22 + l1 * w1 + l2 * w2;
       double grad = g11 * mu1 * w1 + g12 * (mu1 * w2 + mu2 * w1) + g22 * mu2 * w2;
       L[q] = L[q] + mu * lap + grad;
@@ -472,7 +480,10 @@ hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo,
 }
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_stage, grid_for(a.P), dim3(256), 0, s, a);
+  if (a.deriv_f32)
+    hipLaunchKernelGGL(k_stage<float>, grid_for(a.P), dim3(256), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_stage<double>, grid_for(a.P), dim3(256), 0, s, a);
   return hipGetLastError();
 }
 

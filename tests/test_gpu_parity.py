@@ -238,6 +238,42 @@ def test_curvilinear_viscous_parity_frozen_classes():
     assert _rel(S, O, specs) < 1e-12
 
 
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16x3", 1e-4)])
+def test_step_channel_mixed_precision_frozen_classes(prec, tol):
+    """Mixed forms (FP32 or split-BF16 stage contractions, FP32 stage
+    derivatives, FP64 state) against the FP64 oracle on the step channel with
+    a viscous band of prescribed classes in every subpatch.  Error model: the
+    contraction's bound (the sweep tolerance, relative to max|f|, index
+    units) reaches the state as dt/h (0.025 here) x 2 directions x 2 steps x
+    max|F| / max|U| (about 1.5), i.e. about 0.15 x the bound; the tolerance
+    is the bound itself."""
+    specs = W.step_channel()
+    w = W.uniform_state(specs, W.STEP_INFLOW)
+    for p, s in enumerate(specs):
+        bump = np.exp(-((s.x - 1.0) ** 2 + (s.y - 0.6) ** 2) / 0.02)
+        w[p][0] = w[p][0] * (1.0 + 0.1 * bump)
+        w[p][3] = w[p][3] * (1.0 + 0.1 * bump)
+    taus = []
+    for s in specs:
+        t = np.zeros((2,) + s.shape, dtype=np.uint8)
+        t[0][(s.x > 0.9) & (s.x < 1.1)] = 2
+        t[1][(s.y > 0.5) & (s.y < 0.7)] = 1
+        taus.append(t)
+    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, av="frozen", dt_fixed=1e-4, precision=prec))
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+        S.set_tau(p, taus[p])
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=2, fc_C=27, av="modal", dt_fixed=1e-4))
+    O.set_prim(w)
+    O.tau_override = [t.astype(np.int64) for t in taus]
+    for _ in range(2):
+        S.advance(5, sync=True)
+        O.step()
+    assert np.abs(O.mu[0]).max() > 0  # mu (global array) is non-zero in the band
+    err = _rel(S, O, specs)
+    assert err < tol, (prec, err)
+
+
 def test_graph_replay_equals_eager():
     specs = W.step_channel()
     w = W.uniform_state(specs, W.STEP_INFLOW)
