@@ -31,6 +31,17 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
+# HBM bytes per stage-contraction launch on the step channel (FP64), from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
+# 256 MiB copy in the same runs); profiles/stage_contraction_fp64_traffic.md.
+# Valid for the kernels as they were when the counters were taken.
+STAGE_TRAFFIC_FP64 = {
+    "k_gemm_fp<double, 16, 1>": 142.75e6,
+    "k_gemm_fp<double, 16, 2>": 107.51e6,
+    "k_gemm_fp_persist<double, 16, 1>": 126.60e6,
+    "k_gemm_xs<double, 16, 2>": 110.22e6,
+    "k_gemm_xs<double, 16, 4>": 132.57e6,
+}
 HBM_PEAK = 8.0e12
 
 
@@ -42,6 +53,10 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="skip the derivative-sweep and classifier measurements")
+    ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying step graphs "
+                                                           "(for per-dispatch counter runs)")
+    ap.add_argument("--calibration-copy", action="store_true",
+                    help="finish with three plain 256 MiB device copies (byte-counter calibration)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -129,9 +144,9 @@ def classifier_bench(F, W, torch, weights):
     return out
 
 
-def make_solver(F, W, torch, weights, precision, stream):
+def make_solver(F, W, torch, weights, precision, stream, use_graph=True):
     specs = W.step_channel()
-    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=True,
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=use_graph,
                          precision=precision, sdnn_weights=weights, autotune=True)
     with torch.cuda.stream(stream):
         S = F.Solver(specs, prm, stream=stream)
@@ -208,7 +223,7 @@ def main():
 
     weights = train_classifier(F, W, torch)
     stream = torch.cuda.Stream()
-    S, specs = make_solver(F, W, torch, weights, "fp64", stream)
+    S, specs = make_solver(F, W, torch, weights, "fp64", stream, use_graph=not a.eager)
     npts = int(sum(s.npoints() for s in specs))
     el = timed_run(S, torch, stream, a.steps, a.warmup)
     value = npts * 5 * a.steps / el
@@ -217,6 +232,9 @@ def main():
     # latency of the event nodes themselves, reported separately)
     kernel_ms = prof["avg_ms"]
     achieved = prof["flops"] / (kernel_ms * 1e-3)
+    from paper_2506_19370_amd import _lib as L
+    kernel = L.gemm_variant_name("fp64", S.stats()["stage_variant"])
+    traffic = STAGE_TRAFFIC_FP64.get(kernel)
     out = {
         "metric": "point-stage updates/s, plain FP64 vs mixed-precision batched form at stated error",
         "value": value, "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -226,9 +244,9 @@ def main():
                                "(C1 L-shaped + C2 corner patches), %d points, SDNN viscosity (GPU-trained), "
                                "filter, CFL 0.5, FC-Gram d=2 C=27" % npts,
                    "points": npts, "stages_per_step": 5},
-        "roofline": {"bound": "mfma", "kernel": "k_gemm_fp<double, 16, tb> (grouped FC stage contraction, autotuned tile)",
+        "roofline": {"bound": "mfma", "kernel": kernel + " (grouped FC stage contraction, autotuned tile)",
                      "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64"], "traffic": None,
+                     "frac": achieved / PEAK["fp64"], "traffic": traffic, "traffic_unit": "bytes per launch",
                      "avg_launch_ms": kernel_ms, "event_pair_latency_ms": prof["event_latency_ms"],
                      "flops_per_launch": prof["flops"],
                      "algorithmic_bytes_per_launch": prof["bytes"], "launches_timed": prof["launches"]},
@@ -264,6 +282,12 @@ def main():
         out["classifier"] = classifier_bench(F, W, torch, weights)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_steps)
+    if a.calibration_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
     print(json.dumps(out))
 
 

@@ -126,6 +126,9 @@ typedef struct {
   double mass, energy;     /* sums of rho and E over active points (no
                               overlap weighting)                             */
   int64_t npoints;         /* active points, all subpatches                  */
+  int32_t stage_variant;   /* contraction tile variant of the stage launches
+                              (index for fcs_gemm_variant_name)             */
+  int32_t reserved;
 } fcs_stats_t;
 
 typedef struct fcs_ctx fcs_ctx;
@@ -232,6 +235,9 @@ fcs_status fcs_sweep_autotune(fcs_sweep* s, const double* in, double* d1, double
  * of them (0 <= index < count) for a sweep, in the autotuner's order.
  * FCS_EINVAL for an index out of range. */
 int32_t fcs_gemm_variant_count(int32_t precision);
+/* Kernel name of a variant (as profilers list it, without namespaces), NUL
+ * terminated in buf (len bytes, host); FCS_EINVAL for an unknown variant. */
+fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, char* buf, int32_t len);
 fcs_status fcs_sweep_set_variant(fcs_sweep* s, int32_t index);
 void fcs_sweep_destroy(fcs_sweep* s);
 

@@ -64,7 +64,7 @@ class PatchDesc(ctypes.Structure):
 class Stats(ctypes.Structure):
     _fields_ = [("steps", ctypes.c_int64), ("stages", ctypes.c_int64), ("t", ctypes.c_double),
                 ("dt", ctypes.c_double), ("mass", ctypes.c_double), ("energy", ctypes.c_double),
-                ("npoints", ctypes.c_int64)]
+                ("npoints", ctypes.c_int64), ("stage_variant", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def _sig(name, res, args):
@@ -103,6 +103,7 @@ fcs_sweep_profile = _sig("fcs_sweep_profile", _i, [vp, _i, ctypes.POINTER(_d), c
                                                    ctypes.POINTER(_d), ctypes.POINTER(_i64)])
 fcs_sweep_points = _sig("fcs_sweep_points", _i, [vp, ctypes.POINTER(_i64)])
 fcs_gemm_variant_count = _sig("fcs_gemm_variant_count", _i, [_i])
+fcs_gemm_variant_name = _sig("fcs_gemm_variant_name", _i, [_i, _i, ctypes.c_char_p, _i])
 fcs_sweep_set_variant = _sig("fcs_sweep_set_variant", _i, [vp, _i])
 fcs_sweep_destroy = _sig("fcs_sweep_destroy", None, [vp])
 fcs_sweep_autotune = _sig("fcs_sweep_autotune", _i, [vp, vp, vp, vp, vp])
@@ -121,6 +122,7 @@ EXPORTED = [
     "fcs_sweep_workspace_size", "fcs_sweep_bind", "fcs_sweep_run", "fcs_sweep_profile", "fcs_sweep_points",
     "fcs_sweep_destroy", "fcs_sweep_autotune", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",
     "fcs_lines_workspace", "fcs_lines_apply", "fcs_gemm_variant_count", "fcs_sweep_set_variant",
+    "fcs_gemm_variant_name",
 ]
 
 
@@ -134,6 +136,12 @@ def fc_operator(n: int, d: int, C: int, kind: str = "d1") -> np.ndarray:
     out = np.zeros((n, n))
     check(fcs_fc_operator(n, d, C, OP[kind], out.ctypes.data))
     return out
+
+
+def gemm_variant_name(precision: str, index: int) -> str:
+    buf = ctypes.create_string_buffer(96)
+    check(fcs_gemm_variant_name(PREC[precision], int(index), buf, 96))
+    return buf.value.decode()
 
 
 def fc_continuation(d: int, C: int):

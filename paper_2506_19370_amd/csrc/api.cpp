@@ -121,6 +121,7 @@ struct fcs_ctx {
   size_t tile_cap[PH_N] = {};
   bool tuned = false;
   float tune_ms[16] = {};
+  int stage_variant = 0;  // index of var[PH_EULER] among the candidates
 
   // time stepping
   int stage_in_step = 0;
@@ -1036,6 +1037,7 @@ fcs_status autotune(fcs_ctx* c) {
     if (ms < best) {
       best = ms;
       bestv = cand[q];
+      c->stage_variant = q;
     }
   }
   hipEventDestroy(e0);
@@ -1175,6 +1177,8 @@ extern "C" fcs_status fcs_stats(fcs_ctx* c, fcs_stats_t* out) {
       out->energy += e[3 * c->P + k];
     }
   out->npoints = c->nactive;
+  out->stage_variant = c->stage_variant;
+  out->reserved = 0;
   return check_bad(c);
 }
 

@@ -235,6 +235,25 @@ extern "C" int32_t fcs_gemm_variant_count(int32_t precision) {
   return nv;
 }
 
+extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, char* buf, int32_t len) {
+  if (!buf || len <= 0 || precision < 0 || precision > 2) return FCS_EINVAL;
+  int nv = 0;
+  const GemmVariant* cand = gemm_variants(precision, &nv);
+  if (index < 0 || index >= nv) return FCS_EINVAL;
+  const GemmVariant& v = cand[index];
+  std::string name;
+  if (precision == 2) {
+    name = std::string(v.persist ? "k_gemm_bf16x3_persist<" : "k_gemm_bf16x3<") + std::to_string(v.tb) + ">";
+  } else {
+    const char* kind = v.xs ? "k_gemm_xs<" : (v.persist ? "k_gemm_fp_persist<" : "k_gemm_fp<");
+    name = std::string(kind) + (precision == 0 ? "double" : "float") + ", " + std::to_string(v.kc) + ", " +
+           std::to_string(v.tb) + ">";
+  }
+  if (static_cast<int32_t>(name.size()) >= len) return FCS_EINVAL;
+  std::memcpy(buf, name.c_str(), name.size() + 1);
+  return FCS_OK;
+}
+
 extern "C" fcs_status fcs_sweep_set_variant(fcs_sweep* s, int32_t index) {
   if (!s || !s->ws) return FCS_EINVAL;
   int nv = 0;
