@@ -242,8 +242,13 @@ extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, ch
   if (index < 0 || index >= nv) return FCS_EINVAL;
   const GemmVariant& v = cand[index];
   std::string name;
-  if (precision == 2) {
+  if (precision == 2 && v.xw) {
+    name = "k_gemm_xw_bf16x3<128, " + std::to_string(v.tb) + ">";
+  } else if (precision == 2) {
     name = std::string(v.persist ? "k_gemm_bf16x3_persist<" : "k_gemm_bf16x3<") + std::to_string(v.tb) + ">";
+  } else if (v.xw) {
+    name = std::string("k_gemm_xw<") + (precision == 0 ? "double, 64, " : "float, 128, ") + std::to_string(v.tb) +
+           ">";
   } else {
     const char* kind = v.xs ? "k_gemm_xs<" : (v.persist ? "k_gemm_fp_persist<" : "k_gemm_fp<");
     name = std::string(kind) + (precision == 0 ? "double" : "float") + ", " + std::to_string(v.kc) + ", " +

@@ -38,11 +38,14 @@ void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::ve
 // them zero), tiles sorted longest first.
 // xs: operand lines staged in LDS, operator rows loaded straight into MFMA
 // registers (tb 2 or 4; FP64 and FP32).
+// xw: operand lines staged in LDS a wide slab at a time (128 columns, 64 in
+// FP64), operator rows in registers (tb 2 or 4; all precisions).
 struct GemmVariant {
   int tb = 1;
   int kc = 16;
   bool persist = false;
   bool xs = false;
+  bool xw = false;
 };
 hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
                        int ntiles, const OpTables& ops, int* counters, hipStream_t stream);

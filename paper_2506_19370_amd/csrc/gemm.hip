@@ -373,6 +373,246 @@ __global__ __launch_bounds__(256, sizeof(Elem) == 8 ? 2 : 1) void k_gemm_xs(cons
   gemm_xs<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
 }
 
+// Wide staging ("xw"): a tile's operand lines are staged in LDS a slab of
+// SLAB columns at a time, with all of the slab's global loads in flight at
+// once (one memory latency per slab instead of one per 16 columns); the
+// products of the slab then run from LDS, with each wave's operator rows
+// loaded from L2 into registers one 16-column step ahead (reduction order
+// k = 4 g + j within a step, as in the operator-in-registers kernel).  Other
+// workgroups on the CU overlap one tile's slab loads with another's
+// products.
+template <typename Elem, int SLAB>
+struct SmemXw {
+  alignas(16) Elem Xs[kLB][SLAB + 16 / sizeof(Elem)];
+  int64_t dst[kLB];
+};
+
+template <typename Elem, int SLAB, int TB, bool Q1>
+__device__ __forceinline__ void gemm_xw_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                            SmemXw<Elem, SLAB>& sm) {
+  constexpr bool kF64 = sizeof(Elem) == 8;
+  constexpr int kTT = 64 * TB;
+  constexpr int NX = kLB * SLAB / 256;           // operand values per thread and slab
+  constexpr int DQ = 4 * sizeof(Elem) / 16;      // 16-byte loads per 4 operator values
+  constexpr int EV = 16 / sizeof(Elem);          // elements per 16 bytes
+  constexpr bool q1 = Q1;
+  typedef Elem vec4 __attribute__((ext_vector_type(4)));
+  auto& Xs = sm.Xs;
+  int64_t* dst = sm.dst;
+  const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
+  const int nl = min(kLB, nlines - tile.line0);
+  const int ld = ops.ld[T.op];
+  const Elem* __restrict__ D;
+  if constexpr (kF64)
+    D = ops.f64 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
+  else
+    D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
+  const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
+  const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
+  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  // operator rows of this wave's output blocks (zero-padded beyond n)
+  const Elem* drow[TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i) drow[i] = D + static_cast<int64_t>(16 * (wave + 4 * i) + rr) * ld + 4 * g;
+  const int nsteps = (n + 15) / 16;  // 16-column steps over the whole line (operator columns padded to 32)
+  uint4 dcur[TB][DQ], dnext[TB][DQ];
+  auto load_d = [&](uint4 (&d)[TB][DQ], int step) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i)
+#pragma unroll
+      for (int q = 0; q < DQ; ++q) d[i][q] = *reinterpret_cast<const uint4*>(drow[i] + 16 * step + q * EV);
+  };
+  vec4 acc[TB][4];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) acc[i][b] = vec4{0, 0, 0, 0};
+  load_d(dcur, 0);
+  for (int s0 = 0; s0 < n; s0 += SLAB) {
+    // stage the slab: every load of the slab in flight before the first store
+    double xr[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xr[j] = xbase[static_cast<int64_t>(min(s0 + xs_col + j, n - 1)) * T.s_stride];
+    __syncthreads();  // the previous slab's products have read Xs
+#pragma unroll
+    for (int j = 0; j < NX; ++j) Xs[xs_line][xs_col + j] = static_cast<Elem>(xr[j]);
+    __syncthreads();
+    const int step0 = s0 / 16, nsub = min(SLAB / 16, nsteps - step0);
+    for (int sc = 0; sc < nsub; ++sc) {
+      if (step0 + sc + 1 < nsteps) load_d(dnext, step0 + sc + 1);
+      Elem xv[4][4];  // [line block][step j]
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        const Elem* xp = &Xs[16 * lb + rr][16 * sc + 4 * g];
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) {
+          const uint4 v = *reinterpret_cast<const uint4*>(xp + q * EV);
+          const Elem* e = reinterpret_cast<const Elem*>(&v);
+#pragma unroll
+          for (int j = 0; j < EV; ++j) xv[lb][q * EV + j] = e[j];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        const Elem* dv = reinterpret_cast<const Elem*>(&dcur[i][0]);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int lb = 0; lb < 4; ++lb) {
+            if constexpr (kF64)
+              acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(xv[lb][j], dv[j], acc[i][lb], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f64_16x16x4f64(dv[j], xv[lb][j], acc[i][lb], 0, 0, 0);
+            else
+              acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f32_16x16x4f32(xv[lb][j], dv[j], acc[i][lb], 0, 0, 0)
+                              : __builtin_amdgcn_mfma_f32_16x16x4f32(dv[j], xv[lb][j], acc[i][lb], 0, 0, 0);
+          }
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i)
+#pragma unroll
+        for (int q = 0; q < DQ; ++q) dcur[i][q] = dnext[i][q];
+    }
+  }
+  store_tile<kF64, TB>(T, dst, nl, t0, nt, q1, wave, lane, acc, static_cast<const vec4(*)[4]>(nullptr), nullptr,
+                       nullptr);
+}
+
+template <typename Elem, int SLAB, int TB>
+__global__ __launch_bounds__(256) void k_gemm_xw(const GemmTask* __restrict__ tasks, const GemmTile* __restrict__ tiles,
+                                                 OpTables ops) {
+  __shared__ SmemXw<Elem, SLAB> sm;
+  const GemmTile tile = tiles[blockIdx.x];
+  const GemmTask T = tasks[tile.task];
+  if (T.s_stride == 1)
+    gemm_xw_dir<Elem, SLAB, TB, true>(T, tile, ops, sm);
+  else
+    gemm_xw_dir<Elem, SLAB, TB, false>(T, tile, ops, sm);
+}
+
+// Wide staging for split BF16: the slab holds X - x0 as bf16 hi and lo; the
+// 16x16x32 products take 8 consecutive columns per lane on both operands.
+template <int SLAB>
+struct SmemXwBf {
+  alignas(16) uint16_t Xh[kLB][SLAB + 8];
+  alignas(16) uint16_t Xl[kLB][SLAB + 8];
+  double x0s[kLB];
+  int64_t dst[kLB];
+};
+
+template <int SLAB, int TB, bool Q1>
+__device__ __forceinline__ void gemm_xw_bf16x3_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                                   SmemXwBf<SLAB>& sm) {
+  constexpr int kTT = 64 * TB;
+  constexpr int NX = kLB * SLAB / 256;  // operand values per thread and slab
+  constexpr bool q1 = Q1;
+  auto& Xh = sm.Xh;
+  auto& Xl = sm.Xl;
+  double* x0s = sm.x0s;
+  int64_t* dst = sm.dst;
+  const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
+  const int nl = min(kLB, nlines - tile.line0);
+  const int ld = ops.ld[T.op];
+  const int64_t dbase = ops.off[T.op] + static_cast<int64_t>(t0) * ld;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  if (tid < kLB) {
+    dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
+    x0s[tid] = T.src[dst[tid]];
+  }
+  const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
+  const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
+  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  const double x0 = xbase[0];
+  const uint16_t* bh[TB];
+  const uint16_t* bl[TB];
+#pragma unroll
+  for (int i = 0; i < TB; ++i) {
+    const int64_t o = dbase + static_cast<int64_t>(16 * (wave + 4 * i) + rr) * ld + 8 * g;
+    bh[i] = ops.bhi + o;
+    bl[i] = ops.blo + o;
+  }
+  const int nsteps = (n + 31) / 32;  // 32-column steps (operator columns padded to 32)
+  uint4 hcur[TB], lcur[TB], hnext[TB], lnext[TB];
+  auto load_d = [&](uint4 (&h)[TB], uint4 (&l)[TB], int step) {
+#pragma unroll
+    for (int i = 0; i < TB; ++i) {
+      h[i] = *reinterpret_cast<const uint4*>(bh[i] + 32 * step);
+      l[i] = *reinterpret_cast<const uint4*>(bl[i] + 32 * step);
+    }
+  };
+  f32x4 am[TB][4], ac[TB][4];
+#pragma unroll
+  for (int i = 0; i < TB; ++i)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) am[i][b] = ac[i][b] = f32x4{0, 0, 0, 0};
+  load_d(hcur, lcur, 0);
+  for (int s0 = 0; s0 < n; s0 += SLAB) {
+    double xr[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) xr[j] = xbase[static_cast<int64_t>(min(s0 + xs_col + j, n - 1)) * T.s_stride];
+    __syncthreads();
+#pragma unroll
+    for (int j0 = 0; j0 < NX; j0 += 8) {
+      bf16x8 h, l;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        const float f = static_cast<float>(xr[j0 + j] - x0);
+        h[j] = static_cast<__bf16>(f);  // round to nearest even (v_cvt_pk_bf16_f32)
+        l[j] = static_cast<__bf16>(f - static_cast<float>(h[j]));
+      }
+      *reinterpret_cast<bf16x8*>(&Xh[xs_line][xs_col + j0]) = h;
+      *reinterpret_cast<bf16x8*>(&Xl[xs_line][xs_col + j0]) = l;
+    }
+    __syncthreads();
+    const int step0 = s0 / 32, nsub = min(SLAB / 32, nsteps - step0);
+    for (int sc = 0; sc < nsub; ++sc) {
+      if (step0 + sc + 1 < nsteps) load_d(hnext, lnext, step0 + sc + 1);
+      bf16x8 xh[4], xlo[4];
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        xh[lb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[16 * lb + rr][32 * sc + 8 * g]));
+        xlo[lb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[16 * lb + rr][32 * sc + 8 * g]));
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        const bf16x8 dh = __builtin_bit_cast(bf16x8, hcur[i]);
+        const bf16x8 dl = __builtin_bit_cast(bf16x8, lcur[i]);
+#pragma unroll
+        for (int lb = 0; lb < 4; ++lb) {
+          if (q1) {
+            am[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[lb], dh, am[i][lb], 0, 0, 0);
+            ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[lb], dl, ac[i][lb], 0, 0, 0);
+            ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xlo[lb], dh, ac[i][lb], 0, 0, 0);
+          } else {
+            am[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, xh[lb], am[i][lb], 0, 0, 0);
+            ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dh, xlo[lb], ac[i][lb], 0, 0, 0);
+            ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(dl, xh[lb], ac[i][lb], 0, 0, 0);
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < TB; ++i) {
+        hcur[i] = hnext[i];
+        lcur[i] = lnext[i];
+      }
+    }
+  }
+  store_tile<false, TB>(T, dst, nl, t0, nt, q1, wave, lane, am, ac, x0s, ops.rowsum + ops.roff[T.op]);
+}
+
+template <int SLAB, int TB>
+__global__ __launch_bounds__(256) void k_gemm_xw_bf16x3(const GemmTask* __restrict__ tasks,
+                                                        const GemmTile* __restrict__ tiles, OpTables ops) {
+  __shared__ SmemXwBf<SLAB> sm;
+  const GemmTile tile = tiles[blockIdx.x];
+  const GemmTask T = tasks[tile.task];
+  if (T.s_stride == 1)
+    gemm_xw_bf16x3_dir<SLAB, TB, true>(T, tile, ops, sm);
+  else
+    gemm_xw_bf16x3_dir<SLAB, TB, false>(T, tile, ops, sm);
+}
+
 // Persistent form: the grid holds one workgroup per resident slot and each
 // workgroup takes tiles from a device counter until the list is exhausted
 // (tiles sorted longest first).  ctr[0] hands out tiles, ctr[1] counts
@@ -685,6 +925,19 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
     return launch_persist(k_gemm_bf16x3_persist<1>, ntiles, stream, tasks, tiles, ntiles, ops, counters);
   }
   dim3 grid(ntiles), block(256);
+  if (v.xw) {
+    if (precision == 0) {
+      if (v.tb == 4) hipLaunchKernelGGL((k_gemm_xw<double, 64, 4>), grid, block, 0, stream, tasks, tiles, ops);
+      else hipLaunchKernelGGL((k_gemm_xw<double, 64, 2>), grid, block, 0, stream, tasks, tiles, ops);
+    } else if (precision == 1) {
+      if (v.tb == 4) hipLaunchKernelGGL((k_gemm_xw<float, 128, 4>), grid, block, 0, stream, tasks, tiles, ops);
+      else hipLaunchKernelGGL((k_gemm_xw<float, 128, 2>), grid, block, 0, stream, tasks, tiles, ops);
+    } else {
+      if (v.tb == 4) hipLaunchKernelGGL((k_gemm_xw_bf16x3<128, 4>), grid, block, 0, stream, tasks, tiles, ops);
+      else hipLaunchKernelGGL((k_gemm_xw_bf16x3<128, 2>), grid, block, 0, stream, tasks, tiles, ops);
+    }
+    return hipGetLastError();
+  }
   if (v.xs) {
 #define FCS_XS(E, KC, TB) hipLaunchKernelGGL((k_gemm_xs<E, KC, TB>), grid, block, 0, stream, tasks, tiles, ops)
     if (precision == 0) {
@@ -730,14 +983,20 @@ int gemm_lines_per_tile() { return kLB; }
 int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 4 ? 4 : (v.tb == 2 ? 2 : 1)); }
 
 const GemmVariant* gemm_variants(int precision, int* count) {
-  // {tb, kc, persist, xs}
-  static const GemmVariant f64[] = {{1, 16, false, false}, {2, 16, false, false}, {1, 16, true, false},
-                                    {2, 16, false, true},  {4, 16, false, true}};
-  static const GemmVariant f32[] = {{1, 16, false, false}, {2, 16, false, false}, {1, 32, false, false},
-                                    {2, 16, false, true},  {4, 16, false, true},  {2, 32, false, true},
-                                    {4, 32, false, true}};
-  static const GemmVariant bf[] = {{1, 32, false, false}, {2, 32, false, false}, {1, 32, true, false}};
-  *count = precision == 0 ? 5 : (precision == 1 ? 7 : 3);
+  // {tb, kc, persist, xs, xw}
+  static const GemmVariant f64[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
+                                    {1, 16, true, false, false},  {2, 16, false, true, false},
+                                    {4, 16, false, true, false},  {2, 16, false, false, true},
+                                    {4, 16, false, false, true}};
+  static const GemmVariant f32[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
+                                    {1, 32, false, false, false}, {2, 16, false, true, false},
+                                    {4, 16, false, true, false},  {2, 32, false, true, false},
+                                    {4, 32, false, true, false},  {2, 16, false, false, true},
+                                    {4, 16, false, false, true}};
+  static const GemmVariant bf[] = {{1, 32, false, false, false}, {2, 32, false, false, false},
+                                   {1, 32, true, false, false},  {2, 32, false, false, true},
+                                   {4, 32, false, false, true}};
+  *count = precision == 0 ? 7 : (precision == 1 ? 9 : 5);
   return precision == 0 ? f64 : (precision == 1 ? f32 : bf);
 }
 
