@@ -473,8 +473,20 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
                                      c->phase_tasks[PH_MUGRAD].end());
   }
   for (int ph = 0; ph < PH_N; ++ph) {
-    build_tiles(c.get(), ph);  // default variant: the largest tile count
-    c->tile_cap[ph] = c->phase_tiles[ph].size();
+    // room for the tile list of every candidate shape the autotuner may pick
+    size_t cap = 0;
+    if (ph == PH_EULER || ph == PH_CROSS || ph == PH_EULER0) {
+      int nv = 0;
+      const GemmVariant* cand = gemm_variants(p.precision, &nv);
+      for (int q = 0; q < nv; ++q) {
+        c->var[ph] = cand[q];
+        build_tiles(c.get(), ph);
+        cap = std::max(cap, c->phase_tiles[ph].size());
+      }
+      c->var[ph] = GemmVariant{};
+    }
+    build_tiles(c.get(), ph);
+    c->tile_cap[ph] = std::max(cap, c->phase_tiles[ph].size());
   }
   // workspace layout
   Carve cv;

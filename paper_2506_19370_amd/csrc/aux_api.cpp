@@ -119,8 +119,19 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     t.op = s->ops.add(b, FCS_OP_D1);
     s->tasks.push_back(t);
   }
+  // room for the tile list of every candidate shape
+  {
+    int nv = 0;
+    const GemmVariant* cand = gemm_variants(precision, &nv);
+    for (int q = 0; q < nv; ++q) {
+      s->var = cand[q];
+      sweep_tiles(s.get());
+      s->tile_cap = std::max(s->tile_cap, s->tiles.size());
+    }
+    s->var = GemmVariant{};
+  }
   sweep_tiles(s.get());
-  s->tile_cap = s->tiles.size();
+  s->tile_cap = std::max(s->tile_cap, s->tiles.size());
   size_t u = 0;
   auto take = [&](size_t b) {
     size_t o = u;

@@ -370,7 +370,9 @@ __device__ __forceinline__ void gemm_xs(const GemmTask* __restrict__ tasks, cons
 template <typename Elem, int KC, int TB>
 __global__ __launch_bounds__(256, sizeof(Elem) == 8 ? 2 : 1) void k_gemm_xs(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
-  gemm_xs<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  gemm_xs<Elem, KC, TB>(tasks, tile, ops);
 }
 
 // Wide staging ("xw"): a tile's operand lines are staged in LDS a slab of
@@ -484,6 +486,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw(const GemmTask* __restrict__ ta
                                                  OpTables ops) {
   __shared__ SmemXw<Elem, SLAB> sm;
   const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
     gemm_xw_dir<Elem, SLAB, TB, true>(T, tile, ops, sm);
@@ -606,6 +609,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16x3(const GemmTask* __restri
                                                         const GemmTile* __restrict__ tiles, OpTables ops) {
   __shared__ SmemXwBf<SLAB> sm;
   const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
     gemm_xw_bf16x3_dir<SLAB, TB, true>(T, tile, ops, sm);
@@ -644,7 +648,9 @@ __device__ __forceinline__ void persistent_tiles(int ntiles, int* ctr, Body body
 template <typename Elem, int KC, int TB>
 __global__ __launch_bounds__(256, 4) void k_gemm_fp(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
-  gemm_fp<Elem, KC, TB>(tasks, tiles[blockIdx.x], ops);
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  gemm_fp<Elem, KC, TB>(tasks, tile, ops);
 }
 
 template <typename Elem, int KC, int TB>
@@ -658,7 +664,9 @@ __global__ __launch_bounds__(256, 4) void k_gemm_fp_persist(const GemmTask* __re
 // under their own name so that profiles tell the two apart.
 __global__ __launch_bounds__(256, 4) void k_gemm_step(const GemmTask* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles, OpTables ops) {
-  gemm_fp<double, 16, 1>(tasks, tiles[blockIdx.x], ops);
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  gemm_fp<double, 16, 1>(tasks, tile, ops);
 }
 
 // Split BF16: chunks of 32 columns (one MFMA depth); LDS rows padded to 40
@@ -797,7 +805,9 @@ __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, 
 template <int TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict__ tasks,
                                                      const GemmTile* __restrict__ tiles, OpTables ops) {
-  gemm_bf16x3<TB>(tasks, tiles[blockIdx.x], ops);
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  gemm_bf16x3<TB>(tasks, tile, ops);
 }
 
 template <int TB>
@@ -1004,23 +1014,35 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
                       std::vector<GemmTile>& tiles) {
   tiles.clear();
   const int step = gemm_outputs_per_tile(v);
-  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
-  // L2.  The output tiles of one 64-line block are placed 8 tiles apart
-  // (groups of 8 line blocks, outputs outer), so they run on the same XCD at
-  // nearly the same time and re-read the block's operand lines from its L2.
-  constexpr int kXcd = 8;
-  for (size_t q = 0; q < ntasks; ++q) {
-    const int nblk = (nlines[q] + kLB - 1) / kLB;
-    for (int g0 = 0; g0 < nblk; g0 += kXcd)
-      for (int t0 = 0; t0 < n[q]; t0 += step)
-        for (int b = g0; b < std::min(nblk, g0 + kXcd); ++b)
-          tiles.push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
-  }
   if (v.persist) {
+    for (size_t q = 0; q < ntasks; ++q)
+      for (int t0 = 0; t0 < n[q]; t0 += step)
+        for (int l0 = 0; l0 < nlines[q]; l0 += kLB) tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
     // longest first (cost ~ operator depth x outputs of the tile)
     auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
     std::stable_sort(tiles.begin(), tiles.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
+    return;
   }
+  // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
+  // L2.  Every task (one operator) is given to one XCD, balancing the work,
+  // and the per-XCD queues are interleaved so that tile i runs on XCD i mod 8:
+  // a task's operator rows are then fetched into one L2 only, and the output
+  // tiles of each 64-line block follow one another there (its operand lines
+  // are re-read from that L2).  Short queues are padded with empty tiles.
+  constexpr int kXcd = 8;
+  std::vector<std::vector<GemmTile>> queue(kXcd);
+  std::vector<double> load(kXcd, 0.0);
+  for (size_t q = 0; q < ntasks; ++q) {
+    const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    const int nblk = (nlines[q] + kLB - 1) / kLB;
+    for (int b = 0; b < nblk; ++b)
+      for (int t0 = 0; t0 < n[q]; t0 += step) queue[x].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
+    load[x] += static_cast<double>(nblk) * n[q] * n[q];
+  }
+  size_t len = 0;
+  for (const auto& qx : queue) len = std::max(len, qx.size());
+  for (size_t r = 0; r < len; ++r)
+    for (int x = 0; x < kXcd; ++x) tiles.push_back(r < queue[x].size() ? queue[x][r] : GemmTile{-1, 0, 0, 0});
 }
 
 }  // namespace fcs
