@@ -325,6 +325,16 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     pd.row_run = rr;
     pd.col_run = cr;
     pd.affine = g.affine;
+    if (g.affine) {
+      const size_t k0 = first_active(g);
+      pd.t1x = g.t1x[k0];
+      pd.t1y = g.t1y[k0];
+      pd.t2x = g.t2x[k0];
+      pd.t2y = g.t2y[k0];
+      pd.g11 = g.g11[k0];
+      pd.g12 = g.g12[k0];
+      pd.g22 = g.g22[k0];
+    }
     c->pdev.push_back(pd);
     for (const Run& r : g.rows) c->rowrun.push_back(make_int2(r.start, r.len));
     for (const Run& r : g.cols) c->colrun.push_back(make_int2(r.start, r.len));
@@ -797,7 +807,11 @@ fcs_status per_step(fcs_ctx* c) {
     HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], c->dptr<uint8_t>("FLAGS"), P, p.gamma, fs));
     if ((st = run_gemm(c, PH_FILT1, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
     if ((st = run_gemm(c, PH_FILT2, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
-    HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, fs));
+    const double* met[4] = {c->dptr<double>("MET0"), c->dptr<double>("MET1"), c->dptr<double>("MET2"),
+                            c->dptr<double>("MET3")};
+    FluxOut fo{c->arr[A_F], met[0], met[1], met[2], met[3], p.gamma - 1.0, c->dptr<int32_t>("PID"),
+               c->dptr<PatchDev>("PATCH")};
+    HIPCHK(c, launch_filter_post(c->arr[A_DF2], U0, c->dptr<uint8_t>("FLAGS"), P, fo, fs));
     if (fork) HIPCHK(c, hipEventRecord(c->ev_join, c->stream2));
   }
   if (c->visc) {
@@ -823,8 +837,11 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   // fluxes of the stage input: computed here at the first stage of a step
   // (after the filter); later stages receive them from the previous stage's
   // update and fringe fill
-  FluxOut fo{c->arr[A_F], met[0], met[1], met[2], met[3], p.gamma - 1.0};
-  if (s == 0) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
+  FluxOut fo{c->arr[A_F], met[0], met[1], met[2], met[3], p.gamma - 1.0, c->dptr<int32_t>("PID"),
+             c->dptr<PatchDev>("PATCH")};
+  // after the filter (every step but the first) the filter's last kernel has
+  // already stored the fluxes of the stage input
+  if (s == 0 && !(p.filter && c->steps > 0)) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
   fcs_status st;
   c->prof_stage = s;
   // the first stage's launch also differentiates mu (PH_EULER0); the later
@@ -872,6 +889,8 @@ fcs_status one_stage(fcs_ctx* c, int s) {
     a.W12 = c->cross ? c->arr[A_W12] : nullptr;
   }
   a.deriv_f32 = c->deriv_f32;
+  a.pid = c->dptr<int32_t>("PID");
+  a.patches = c->dptr<PatchDev>("PATCH");
   double* scal = c->dptr<double>("SCAL");
   a.dt = scal + 1;
   a.bad_flag = reinterpret_cast<int*>(scal + 3);

@@ -48,6 +48,10 @@ struct PatchDev {
   int32_t col_run;  // index of column 0
   int32_t affine;
   int32_t pad;
+  // affine subpatches: the metric terms, the same at every active point
+  // (q^k_x, q^k_y and g^{kl}; the Laplacian terms of the index coordinates
+  // vanish)
+  double t1x, t1y, t2x, t2y, g11, g12, g22;
 };
 
 // Per-point flags.

@@ -13,8 +13,10 @@ struct VortexArgs {
 // state as the next stage's contraction operands (F == nullptr: not at all).
 struct FluxOut {
   double* F;
-  const double *t1x, *t1y, *t2x, *t2y;
+  const double *t1x, *t1y, *t2x, *t2y;  // per-point metrics (non-affine subpatches)
   double gm1;
+  const int32_t* pid;                   // subpatch of each point
+  const PatchDev* patches;              // constant metrics of affine subpatches
 };
 
 // Boundary data applied by the stage kernel to the points flagged kBoundary.
@@ -45,6 +47,8 @@ struct StageArgs {
   int* bad_flag;
   BcArgs bcs;
   FluxOut flux;
+  const int32_t* pid;
+  const PatchDev* patches;
 };
 
 struct ClassifyArgs {
@@ -109,7 +113,10 @@ hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);
-hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, hipStream_t s);
+// Rebuilds the state from the filtered variables and stores its fluxes (the
+// operands of the step's first stage) through fo.
+hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, const FluxOut& fo,
+                              hipStream_t s);
 // scal: device scalars [t, dt, last dt, bad flag, t + dt]
 hipError_t launch_dt(const double* U, const uint8_t* flags, const double* hx, const double* mu, double* part,
                      int nblocks, int64_t P, double gamma, double cfl, double dt_fixed, double* scal, hipStream_t s);

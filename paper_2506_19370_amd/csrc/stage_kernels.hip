@@ -35,7 +35,8 @@ __device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t
     const double fx[4] = {mx, mx * u + p, mx * w, u * (E + p)};
     const double fy[4] = {my, my * u, my * w + p, w * (E + p)};
     if (f & kAffine) {
-      const double a = fo.t1x[k], b = fo.t1y[k], c = fo.t2x[k], d = fo.t2y[k];
+      const PatchDev& pd = fo.patches[fo.pid[k]];
+      const double a = pd.t1x, b = pd.t1y, c = pd.t2x, d = pd.t2y;
       for (int q = 0; q < 4; ++q) {
         v[q] = a * fx[q] + b * fy[q];
         v[4 + q] = c * fx[q] + d * fy[q];
@@ -123,7 +124,22 @@ __global__ void k_stage(StageArgs a) {
   }
   if (a.visc) {
     double mu = a.mu[k], mu1 = a.mu1[k], mu2 = a.mu2[k];
-    double g11 = a.g11[k], g12 = a.g12[k], g22 = a.g22[k], l1 = a.lap1[k], l2 = a.lap2[k];
+    double g11, g12, g22, l1, l2;
+    if (f & kAffine) {
+      // constant metrics of the subpatch; the index coordinates are harmonic
+      const PatchDev& pd = a.patches[a.pid[k]];
+      g11 = pd.g11;
+      g12 = pd.g12;
+      g22 = pd.g22;
+      l1 = 0.0;
+      l2 = 0.0;
+    } else {
+      g11 = a.g11[k];
+      g12 = a.g12[k];
+      g22 = a.g22[k];
+      l1 = a.lap1[k];
+      l2 = a.lap2[k];
+    }
     const DT *W1 = static_cast<const DT*>(a.W1), *W2 = static_cast<const DT*>(a.W2);
     const DT *W11 = static_cast<const DT*>(a.W11), *W22 = static_cast<const DT*>(a.W22);
     const DT* W12 = static_cast<const DT*>(a.W12);
@@ -402,18 +418,22 @@ __global__ void k_filter_pre(const double* __restrict__ U, double* __restrict__ 
 }
 
 __global__ void k_filter_post(const double* __restrict__ Q, double* __restrict__ U, const uint8_t* __restrict__ flags,
-                              int64_t P) {
+                              int64_t P, FluxOut fo) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
-  if (!(flags[k] & kActive)) {
+  const uint8_t f = flags[k];
+  if (!(f & kActive)) {
     for (int c = 0; c < 4; ++c) U[c * P + k] = 0.0;
+    store_flux(fo, P, k, f, 0.0, 0.0, 0.0, 0.0);
     return;
   }
-  double r = Q[k], mx = Q[P + k], my = Q[2 * P + k], th = Q[3 * P + k];
+  const double r = Q[k], mx = Q[P + k], my = Q[2 * P + k], th = Q[3 * P + k];
+  const double E = r * th + 0.5 * (mx * mx + my * my) / r;
   U[k] = r;
   U[P + k] = mx;
   U[2 * P + k] = my;
-  U[3 * P + k] = r * th + 0.5 * (mx * mx + my * my) / r;
+  U[3 * P + k] = E;
+  store_flux(fo, P, k, f, r, mx, my, E);
 }
 
 __global__ __launch_bounds__(256) void k_dt_partial(const double* __restrict__ U, const uint8_t* __restrict__ flags,
@@ -544,8 +564,9 @@ hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, i
   return hipGetLastError();
 }
 
-hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, hipStream_t s) {
-  hipLaunchKernelGGL(k_filter_post, grid_for(P), dim3(256), 0, s, Q, U, flags, P);
+hipError_t launch_filter_post(const double* Q, double* U, const uint8_t* flags, int64_t P, const FluxOut& fo,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_filter_post, grid_for(P), dim3(256), 0, s, Q, U, flags, P, fo);
   return hipGetLastError();
 }
 
