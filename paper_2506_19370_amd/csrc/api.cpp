@@ -309,6 +309,10 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     }
   }
   c->P = offset;
+  if (offset >= (int64_t{1} << 31)) {  // point indices are stored as int32 in the window table
+    *out = c.release();
+    return (*out)->fail(FCS_EINVAL, "more than 2^31 - 1 points in one context");
+  }
   // per-point tables
   const int64_t P = c->P;
   c->flags.assign(P, 0);
@@ -510,6 +514,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     for (const char* n : {"MU", "MU1", "MU2", "MUHAT", "MUT", "TMP"}) o[n] = cv.take(P * D);
     o["PS"] = cv.take(2 * P * D);  // proxy and wave speed, interleaved
     o["TAU"] = cv.take(2 * P);
+    o["WGEO"] = cv.take(P * 16);  // window geometry of every point (int4)
   }
   for (int m = 0; m < 10; ++m) o["MET" + std::to_string(m)] = cv.take(P * D);
   o["FLAGS"] = cv.take(P);
@@ -562,6 +567,10 @@ extern "C" fcs_status fcs_workspace_size(const fcs_ctx* ctx, size_t* bytes) {
   *bytes = ctx->ws_need;
   return FCS_OK;
 }
+
+namespace {
+ViscArgs visc_args(fcs_ctx* c);
+}  // namespace
 
 extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* stream) {
   if (!c || !workspace) return FCS_EINVAL;
@@ -687,6 +696,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
     if ((st = upload(c, u.n, u.p, u.b)) != FCS_OK) return st;
   if (c->visc && c->prm.av_mode == FCS_AV_SDNN)
     HIPCHK(c, launch_sdnn_pack(c->dptr<float>("SDNN"), c->dptr<uint32_t>("SDNNF"), c->stream));
+  if (c->visc) HIPCHK(c, launch_window_geo(visc_args(c), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (auto& v : staging_tasks)
     for (auto& w : v) std::vector<GemmTask>().swap(w);
@@ -753,6 +763,43 @@ fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed, 
   return FCS_OK;
 }
 
+// Device arguments of the viscosity kernels (Alg. 3 and the blend).
+ViscArgs visc_args(fcs_ctx* c) {
+  const int64_t P = c->P;
+  const fcs_params& p = c->prm;
+  ViscArgs v{};
+  v.P = P;
+  v.U = c->arr[A_U0];
+  v.flags = c->dptr<uint8_t>("FLAGS");
+  v.pid = c->dptr<int32_t>("PID");
+  v.patches = c->dptr<PatchDev>("PATCH");
+  v.rowrun = c->dptr<int2>("ROWRUN");
+  v.colrun = c->dptr<int2>("COLRUN");
+  v.ps = c->dptr<double2>("PS");
+  v.ij = c->dptr<int32_t>("IJ");
+  v.hx = c->dptr<double>("MET9");
+  v.tau = c->dptr<uint8_t>("TAU");
+  v.muhat = c->dptr<double>("MUHAT");
+  v.tmp = c->dptr<double>("TMP");
+  v.mut = c->dptr<double>("MUT");
+  v.mu = c->arr[A_MU];
+  v.mode = p.av_mode;
+  v.weights = c->dptr<float>("SDNN");
+  v.sdnn_table = c->dptr<uint32_t>("SDNNF");
+  v.basis = c->dptr<double>("BASIS");
+  v.c_mu = p.c_mu;
+  v.gamma = p.gamma;
+  v.nv = p.n_v;
+  v.wdil = c->dptr<double>("WDIL");
+  v.nblend = static_cast<int>(c->bdst.size());
+  v.bdst = c->dptr<int64_t>("BDST");
+  v.bptr = c->dptr<int32_t>("BPTR");
+  v.bcol = c->dptr<int64_t>("BCOL");
+  v.bval = c->dptr<double>("BVAL");
+  v.wgeo = c->dptr<int4>("WGEO");
+  return v;
+}
+
 // Alg. 3 + blend + gradient of mu, filter (Alg. 4), adaptive step.
 fcs_status per_step(fcs_ctx* c) {
   const int64_t P = c->P;
@@ -762,34 +809,7 @@ fcs_status per_step(fcs_ctx* c) {
   fcs_status st;
   ViscArgs v{};
   if (c->visc) {
-    v.P = P;
-    v.U = U0;
-    v.flags = c->dptr<uint8_t>("FLAGS");
-    v.pid = c->dptr<int32_t>("PID");
-    v.patches = c->dptr<PatchDev>("PATCH");
-    v.rowrun = c->dptr<int2>("ROWRUN");
-    v.colrun = c->dptr<int2>("COLRUN");
-    v.ps = c->dptr<double2>("PS");
-    v.ij = c->dptr<int32_t>("IJ");
-    v.hx = c->dptr<double>("MET9");
-    v.tau = c->dptr<uint8_t>("TAU");
-    v.muhat = c->dptr<double>("MUHAT");
-    v.tmp = c->dptr<double>("TMP");
-    v.mut = c->dptr<double>("MUT");
-    v.mu = c->arr[A_MU];
-    v.mode = p.av_mode;
-    v.weights = c->dptr<float>("SDNN");
-    v.sdnn_table = c->dptr<uint32_t>("SDNNF");
-    v.basis = c->dptr<double>("BASIS");
-    v.c_mu = p.c_mu;
-    v.gamma = p.gamma;
-    v.nv = p.n_v;
-    v.wdil = c->dptr<double>("WDIL");
-    v.nblend = static_cast<int>(c->bdst.size());
-    v.bdst = c->dptr<int64_t>("BDST");
-    v.bptr = c->dptr<int32_t>("BPTR");
-    v.bcol = c->dptr<int64_t>("BCOL");
-    v.bval = c->dptr<double>("BVAL");
+    v = visc_args(c);
     HIPCHK(c, launch_proxy(v, c->stream));
   }
   // Alg. 4 (filter) reads and rewrites the state, which after the proxy

@@ -6,8 +6,10 @@
 // form one product  Y[line][t] = sum_s Op[t][s] X[line][s].  One launch covers
 // every (subpatch, direction, operand set) through a tile list.  A 256-thread
 // workgroup owns 64 lines and 64 tb outputs (tb = 1 or 2) and walks the
-// operator depth in chunks of kc columns; wave w computes the 16-output
-// blocks w, w + 4 for all 64 lines (4 x tb MFMA tiles).
+// operator depth in chunks of kc columns; wave w computes the 16 lines
+// 16 w .. 16 w + 15 for all 4 tb 16-output blocks of the tile.  The blocks
+// past the line length (the ragged last tile of a line, about a quarter of
+// the products at line lengths near 100) are skipped by every wave alike.
 //
 // Staging is branch-free and double-buffered in LDS: the global loads of
 // chunk k + 1 are in flight while the matrix cores work on chunk k, and one
@@ -30,6 +32,7 @@
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <type_traits>
 
 #include "fc_builder.h"
 #include "gemm.h"
@@ -119,6 +122,43 @@ __device__ __forceinline__ void store_tile(const GemmTask& T, const int64_t* dst
   }
 }
 
+// Stores the accumulators of a wave that owns the 16 lines 16 wave ..
+// 16 wave + 15 and the NB output blocks of the tile (same register layout).
+template <bool kF64, int NB, typename Acc>
+__device__ __forceinline__ void store_lines(const GemmTask& T, const int64_t* dst, int nl, int t0, int nt, bool q1,
+                                            int wave, int lane, const Acc (&acc)[NB]) {
+#pragma unroll
+  for (int ob = 0; ob < NB; ++ob) {
+    if (16 * ob >= nt) continue;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = kF64 ? (lane >> 4) + 4 * r : 4 * (lane >> 4) + r;
+      const int col = lane & 15;
+      const int lloc = 16 * wave + (q1 ? row : col);
+      const int tloc = 16 * ob + (q1 ? col : row);
+      if (tloc >= nt || lloc >= nl) continue;
+      const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
+      if (T.out_f32)
+        static_cast<float*>(T.dst)[o] = static_cast<float>(acc[ob][r]);
+      else
+        static_cast<double*>(T.dst)[o] = static_cast<double>(acc[ob][r]);
+    }
+  }
+}
+
+// Calls f(std::integral_constant<int, min(nb, K)>) for 0 <= nb.
+template <int K, typename F>
+__device__ __forceinline__ void with_live(int nb, F&& f) {
+  if constexpr (K == 0) {
+    f(std::integral_constant<int, 0>{});
+  } else {
+    if (nb >= K)
+      f(std::integral_constant<int, K>{});
+    else
+      with_live<K - 1>(nb, f);
+  }
+}
+
 // FP64 or FP32 operands on the 16x16x4 MFMA of that type.
 template <typename Elem, int KC, int TB>
 struct SmemFp {
@@ -147,7 +187,7 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
     D = ops.f64 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   else
     D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr bool q1 = Q1;
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   XLoad<KC> xl;
@@ -176,47 +216,49 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
       for (int j = 0; j < kDV; ++j) Ds[b][t][kk + j] = v[j];
     }
   };
-  vec4 acc[TB][4];
-#pragma unroll
-  for (int i = 0; i < TB; ++i)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[i][b] = vec4{0, 0, 0, 0};
+  // Output blocks that hold outputs (none if this wave's lines are past the
+  // task's end); the same count on every wave of a full line tile.  The
+  // chunk loop is instantiated per count, so the accumulators keep static
+  // registers; every instantiation takes part in the same loads and barriers.
+  const int nb = 16 * wave < nl ? (nt + 15) >> 4 : 0;
   const int nk = (n + KC - 1) / KC;
   xl.load(xr, q1, 0, n, T.s_stride);
   load_d(0);
   stage(0);
   __syncthreads();
-  for (int c = 0; c < nk; ++c) {
-    const int b = c & 1;
-    if (c + 1 < nk) {
-      xl.load(xr, q1, (c + 1) * KC, n, T.s_stride);
-      load_d((c + 1) * KC);
-    }
+  with_live<4 * TB>(nb, [&](auto live) {
+    constexpr int NL = decltype(live)::value;
+    vec4 acc[NL > 0 ? NL : 1];
 #pragma unroll
-    for (int ks = 0; ks < KC; ks += 4) {
-      const int kr = ks + (lane >> 4), rr = lane & 15;
-      Elem xb[4];
+    for (int ob = 0; ob < NL; ++ob) acc[ob] = vec4{0, 0, 0, 0};
+    for (int c = 0; c < nk; ++c) {
+      const int b = c & 1;
+      if (c + 1 < nk) {
+        xl.load(xr, q1, (c + 1) * KC, n, T.s_stride);
+        load_d((c + 1) * KC);
+      }
+      if constexpr (NL > 0) {
 #pragma unroll
-      for (int lb = 0; lb < 4; ++lb) xb[lb] = Xs[b][16 * lb + rr][kr];
+        for (int ks = 0; ks < KC; ks += 4) {
+          const int kr = ks + (lane >> 4), rr = lane & 15;
+          const Elem xa = Xs[b][16 * wave + rr][kr];
 #pragma unroll
-      for (int i = 0; i < TB; ++i) {
-        const Elem da = Ds[b][16 * (wave + 4 * i) + rr][kr];
-#pragma unroll
-        for (int lb = 0; lb < 4; ++lb) {
-          if constexpr (kF64)
-            acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(xb[lb], da, acc[i][lb], 0, 0, 0)
-                            : __builtin_amdgcn_mfma_f64_16x16x4f64(da, xb[lb], acc[i][lb], 0, 0, 0);
-          else
-            acc[i][lb] = q1 ? __builtin_amdgcn_mfma_f32_16x16x4f32(xb[lb], da, acc[i][lb], 0, 0, 0)
-                            : __builtin_amdgcn_mfma_f32_16x16x4f32(da, xb[lb], acc[i][lb], 0, 0, 0);
+          for (int ob = 0; ob < NL; ++ob) {
+            const Elem da = Ds[b][16 * ob + rr][kr];
+            if constexpr (kF64)
+              acc[ob] = q1 ? __builtin_amdgcn_mfma_f64_16x16x4f64(xa, da, acc[ob], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f64_16x16x4f64(da, xa, acc[ob], 0, 0, 0);
+            else
+              acc[ob] = q1 ? __builtin_amdgcn_mfma_f32_16x16x4f32(xa, da, acc[ob], 0, 0, 0)
+                           : __builtin_amdgcn_mfma_f32_16x16x4f32(da, xa, acc[ob], 0, 0, 0);
+          }
         }
       }
+      if (c + 1 < nk) stage(b ^ 1);
+      __syncthreads();
     }
-    if (c + 1 < nk) stage(b ^ 1);
-    __syncthreads();
-  }
-  store_tile<kF64, TB>(T, dst, nl, t0, nt, q1, wave, lane, acc, static_cast<const vec4(*)[4]>(nullptr), nullptr,
-                       nullptr);
+    if constexpr (NL > 0) store_lines<kF64, NL>(T, dst, nl, t0, nt, q1, wave, lane, acc);
+  });
 }
 
 // The direction decides the operand roles of every MFMA; it is resolved
@@ -240,7 +282,8 @@ __device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, cons
 // columns of one row (16-byte loads) and its operand values 4 consecutive
 // columns of one line (16-byte LDS reads).  The operator loads of chunk c+1
 // are issued before the products of chunk c.  TB (2 or 4) 16-output blocks
-// per wave: a workgroup covers 64 lines x 64 TB outputs.
+// per wave: a workgroup covers 64 lines x 64 TB outputs; a wave skips the
+// loads and products of its blocks past the line end.
 template <typename Elem, int KC>
 struct SmemXs {
   alignas(16) Elem Xs[2][kLB][KC + 16 / sizeof(Elem)];
@@ -267,7 +310,8 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
     D = ops.f64 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   else
     D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4,
+            rr = lane & 15;
   constexpr bool q1 = Q1;
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   // operand staging: one line and NX consecutive columns per thread
@@ -285,10 +329,11 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
   };
   // operator fragments: block i of this wave, sub-chunk s, 4 values (blocks
   // past the tile's outputs read zero-padded rows and are not stored)
-  uint4 dr[TB][NS][DQ];
+  uint4 dr[TB][NS][DQ] = {};  // blocks past the line end stay zero
   auto load_d = [&](int k0) {
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
+      if (16 * (wave + 4 * i) >= nt) continue;  // block past the line end: no products
       const Elem* row = D + static_cast<int64_t>(16 * (wave + 4 * i) + rr) * ld + k0 + 4 * g;
 #pragma unroll
       for (int sc = 0; sc < NS; ++sc)
@@ -336,6 +381,7 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
       }
 #pragma unroll
       for (int i = 0; i < TB; ++i) {
+        if (16 * (wave + 4 * i) >= nt) continue;
         const Elem* dv = reinterpret_cast<const Elem*>(&dn[i][sc][0]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -409,7 +455,8 @@ __device__ __forceinline__ void gemm_xw_dir(const GemmTask& T, const GemmTile ti
     D = ops.f64 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   else
     D = ops.f32 + ops.off[T.op] + static_cast<int64_t>(t0) * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4,
+            rr = lane & 15;
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
   const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
@@ -419,12 +466,14 @@ __device__ __forceinline__ void gemm_xw_dir(const GemmTask& T, const GemmTile ti
 #pragma unroll
   for (int i = 0; i < TB; ++i) drow[i] = D + static_cast<int64_t>(16 * (wave + 4 * i) + rr) * ld + 4 * g;
   const int nsteps = (n + 15) / 16;  // 16-column steps over the whole line (operator columns padded to 32)
-  uint4 dcur[TB][DQ], dnext[TB][DQ];
+  uint4 dcur[TB][DQ] = {}, dnext[TB][DQ] = {};  // blocks past the line end stay zero
   auto load_d = [&](uint4 (&d)[TB][DQ], int step) {
 #pragma unroll
-    for (int i = 0; i < TB; ++i)
+    for (int i = 0; i < TB; ++i) {
+      if (16 * (wave + 4 * i) >= nt) continue;  // block past the line end: no products
 #pragma unroll
       for (int q = 0; q < DQ; ++q) d[i][q] = *reinterpret_cast<const uint4*>(drow[i] + 16 * step + q * EV);
+    }
   };
   vec4 acc[TB][4];
 #pragma unroll
@@ -458,6 +507,7 @@ __device__ __forceinline__ void gemm_xw_dir(const GemmTask& T, const GemmTile ti
       }
 #pragma unroll
       for (int i = 0; i < TB; ++i) {
+        if (16 * (wave + 4 * i) >= nt) continue;
         const Elem* dv = reinterpret_cast<const Elem*>(&dcur[i][0]);
 #pragma unroll
         for (int j = 0; j < 4; ++j)
@@ -518,7 +568,8 @@ __device__ __forceinline__ void gemm_xw_bf16x3_dir(const GemmTask& T, const Gemm
   const int nl = min(kLB, nlines - tile.line0);
   const int ld = ops.ld[T.op];
   const int64_t dbase = ops.off[T.op] + static_cast<int64_t>(t0) * ld;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, rr = lane & 15;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6), g = lane >> 4,
+            rr = lane & 15;
   if (tid < kLB) {
     dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
     x0s[tid] = T.src[dst[tid]];
@@ -536,10 +587,11 @@ __device__ __forceinline__ void gemm_xw_bf16x3_dir(const GemmTask& T, const Gemm
     bl[i] = ops.blo + o;
   }
   const int nsteps = (n + 31) / 32;  // 32-column steps (operator columns padded to 32)
-  uint4 hcur[TB], lcur[TB], hnext[TB], lnext[TB];
+  uint4 hcur[TB] = {}, lcur[TB] = {}, hnext[TB] = {}, lnext[TB] = {};  // blocks past the line end stay zero
   auto load_d = [&](uint4 (&h)[TB], uint4 (&l)[TB], int step) {
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
+      if (16 * (wave + 4 * i) >= nt) continue;  // block past the line end: no products
       h[i] = *reinterpret_cast<const uint4*>(bh[i] + 32 * step);
       l[i] = *reinterpret_cast<const uint4*>(bl[i] + 32 * step);
     }
@@ -579,6 +631,7 @@ __device__ __forceinline__ void gemm_xw_bf16x3_dir(const GemmTask& T, const Gemm
       }
 #pragma unroll
       for (int i = 0; i < TB; ++i) {
+        if (16 * (wave + 4 * i) >= nt) continue;
         const bf16x8 dh = __builtin_bit_cast(bf16x8, hcur[i]);
         const bf16x8 dl = __builtin_bit_cast(bf16x8, lcur[i]);
 #pragma unroll
@@ -698,7 +751,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   const int64_t dbase = ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   const uint16_t* __restrict__ Bh = ops.bhi + dbase;
   const uint16_t* __restrict__ Bl = ops.blo + dbase;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr bool q1 = Q1;
   // Operand staging: each thread owns 8 consecutive columns of one line of
   // the chunk (along q^1 four threads share a line, along q^2 neighbouring
@@ -769,6 +822,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
 #pragma unroll
     for (int i = 0; i < TB; ++i) {
       const int tb = wave + 4 * i;
+      if (16 * tb >= nt) continue;  // block past the line end: no products
       const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * tb + rr][kb]));
       const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * tb + rr][kb]));
 #pragma unroll

@@ -59,6 +59,7 @@ struct ClassifyArgs {
   const int2 *rowrun, *colrun;
   const double2* ps;     // proxy and wave speed |u| + a of every point
   const int32_t* ij;     // (j << 16) | i of every point
+  const int4* wgeo;      // window start and stride of every point along q^1, q^2 (start -1: none)
   const double* hx;
   uint8_t* tau;
   double* muhat;
@@ -78,6 +79,7 @@ struct ViscArgs {
   const int2 *rowrun, *colrun;
   double2* ps;
   const int32_t* ij;
+  int4* wgeo;  // per-point window geometry, filled once by launch_window_geo
   const double* hx;
   uint8_t* tau;
   double *muhat, *tmp, *mut, *mu;
@@ -111,6 +113,9 @@ hipError_t launch_proxy(const ViscArgs& v, hipStream_t s);
 // Fragment table (64 x 84 words) of a classifier parameter blob.
 hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);
+// Window start and stride of every point in both directions (static
+// geometry; run once per bound context).
+hipError_t launch_window_geo(const ViscArgs& v, hipStream_t s);
 hipError_t launch_filter_pre(const double* U, double* Q, const uint8_t* flags, int64_t P, double gamma,
                              hipStream_t s);
 // Rebuilds the state from the filtered variables and stores its fluxes (the

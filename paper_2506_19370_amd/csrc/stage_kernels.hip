@@ -288,48 +288,84 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a) {
   a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
 }
 
+// Window geometry of every point in both directions (window_at), stored
+// as (start, stride) pairs with start -1 where the point has no window.
+__global__ void k_window_geo(ClassifyArgs a, int4* __restrict__ out) {
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= a.P) return;
+  const uint8_t f = a.flags[k];
+  int4 g{-1, 0, -1, 0};
+  int64_t base, stride;
+  if (window_at(a, k, f, 0, base, stride)) {
+    g.x = static_cast<int>(base);
+    g.y = static_cast<int>(stride);
+  }
+  if (window_at(a, k, f, 1, base, stride)) {
+    g.z = static_cast<int>(base);
+    g.w = static_cast<int>(stride);
+  }
+  out[k] = g;
+}
+
 // Alg. 3 with the SDNN: each wave classifies the two windows of 64 points
-// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  The window
-// geometry is found once per lane (one point each) and handed to the rounds
-// by lane shuffles; lanes 0..15 write the classes and the preliminary
-// viscosity of the points of their rounds.
+// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  Round
+// 2 pg + dir covers direction dir of the points 16 pg .. 16 pg + 15 of the
+// wave; the window geometry comes from the per-point table, is handed to the
+// rounds by lane shuffles, and each round's window values are fetched while
+// the previous round is on the matrix cores.  Lanes 0..15 write the classes
+// and the preliminary viscosity of the points of their rounds.
 __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
   SdnnFrag F;
   load_sdnn_frag(a.sdnn_table, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
   const int64_t kw = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
-  // geometry of this lane's point kw + lane
   const int64_t kl = kw + lane;
   const uint8_t fl = kl < a.P ? a.flags[kl] : 0;
-  int64_t gb[2] = {0, 0}, gs[2] = {0, 0};
-  bool gv[2];
-  for (int dir = 0; dir < 2; ++dir) gv[dir] = kl < a.P && window_at(a, kl, fl, dir, gb[dir], gs[dir]);
-#pragma unroll 2
+  const int4 geo = kl < a.P ? a.wgeo[kl] : int4{-1, 0, -1, 0};
+  // values (proxy, wave speed) of this lane's 4 window points in round (pg, dir)
+  auto fetch = [&](int pg, int dir, double2 (&q)[4]) -> bool {
+    const int src = 16 * pg + c;
+    const int base = __shfl(dir == 0 ? geo.x : geo.z, src);
+    const int stride = __shfl(dir == 0 ? geo.y : geo.w, src);
+    const bool valid = base >= 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      q[j] = valid ? a.ps[static_cast<int64_t>(base) + static_cast<int64_t>(4 * g + j) * stride] : double2{0.0, 0.0};
+    return valid;
+  };
+  double2 qc[4];
+  bool vc = fetch(0, 0, qc);
+#pragma unroll 1
   for (int pg = 0; pg < 4; ++pg) {
     const int src = 16 * pg + c;  // lane that owns this round's point
     int tau[2] = {0, 0};
     double smax = 0.0;
 #pragma unroll
     for (int dir = 0; dir < 2; ++dir) {
-      const int64_t base = __shfl(gb[dir], src), stride = __shfl(gs[dir], src);
-      const bool valid = __shfl(static_cast<int>(gv[dir]), src) != 0;
+      double2 qn[4] = {};
+      bool vn = false;
+      if (dir == 0)
+        vn = fetch(pg, 1, qn);
+      else if (pg + 1 < 4)
+        vn = fetch(pg + 1, 0, qn);
       double v[4], sp = 0.0;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const int64_t e = base + (4 * g + j) * stride;
-        const double2 q = valid ? a.ps[e] : double2{0.0, 0.0};
-        v[j] = q.x;
-        sp = fmax(sp, q.y);
+        v[j] = qc[j].x;
+        sp = fmax(sp, qc[j].y);
       }
       sp = fmax(sp, __shfl_xor(sp, 16));
       sp = fmax(sp, __shfl_xor(sp, 32));
       float x[4], z[3];
       const bool live = sdnn_features(v, x);
       sdnn_mfma(F, x, z);  // all 64 lanes take part
-      if (valid) {
+      if (vc) {
         smax = fmax(smax, sp);
         tau[dir] = live ? sdnn_argmax(z) : 0;
       }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) qc[j] = qn[j];
+      vc = vn;
     }
     const int64_t k = kw + src;
     const uint8_t f = __shfl(static_cast<int>(fl), src);
@@ -526,7 +562,8 @@ hipError_t launch_proxy(const ViscArgs& v, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
+// Classifier arguments of a viscosity evaluation.
+static ClassifyArgs classify_args(const ViscArgs& v) {
   ClassifyArgs c;
   c.P = v.P;
   c.flags = v.flags;
@@ -544,6 +581,17 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   c.sdnn_table = v.sdnn_table;
   c.basis = v.basis;
   c.c_mu = v.c_mu;
+  c.wgeo = v.wgeo;
+  return c;
+}
+
+hipError_t launch_window_geo(const ViscArgs& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_window_geo, grid_for(v.P), dim3(256), 0, s, classify_args(v), v.wgeo);
+  return hipGetLastError();
+}
+
+hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
+  const ClassifyArgs c = classify_args(v);
   if (c.mode == 2)
     hipLaunchKernelGGL(k_classify_sdnn, grid_for(v.P), dim3(256), 0, s, c);
   else
