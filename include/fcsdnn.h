@@ -176,6 +176,13 @@ fcs_status fcs_get_field(fcs_ctx* ctx, int32_t patch, int32_t field,
 /* Counters, time, last step and integrals (synchronizes). */
 fcs_status fcs_stats(fcs_ctx* ctx, fcs_stats_t* out);
 
+/* Stage-contraction autotuner results of the context (autotune in
+ * fcs_params; the tuning runs at the first advance): the average launch
+ * time in ms of every candidate variant, in the order of
+ * fcs_gemm_variant_name, written to ms[0 .. n-1] (host; n <= 16; 0 for
+ * candidates not timed).  FCS_EINVAL for n out of range or a NULL ms. */
+fcs_status fcs_autotune_times(const fcs_ctx* ctx, int32_t n, double* ms);
+
 /* Average duration (ms) of the dominant derivative-contraction launch (the
  * stage contraction of stages 2 to 5 of each step; the first stage's launch
  * also carries the viscosity gradient) over the advance calls since the last

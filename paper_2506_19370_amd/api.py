@@ -144,6 +144,13 @@ class Solver:
         L.check(L.fcs_stats(self.h, ctypes.byref(s)), self.h)
         return {k: getattr(s, k) for k, _ in L.Stats._fields_}
 
+    def autotune_times(self):
+        """Average launch ms of every stage-contraction candidate (0: not timed)."""
+        n = L.fcs_gemm_variant_count(L.PREC[self.prm.precision])
+        ms = (ctypes.c_double * n)()
+        L.check(L.fcs_autotune_times(self.h, n, ms), self.h)
+        return list(ms)
+
     def profile(self, on: bool):
         L.check(L.fcs_profile_enable(self.h, int(on)), self.h)
 

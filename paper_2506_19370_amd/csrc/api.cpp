@@ -550,7 +550,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
   o["SDNNF"] = cv.take(64 * 84 * 4);  // classifier fragment table
   o["BCIDX"] = cv.take(P * 4);
-  o["GCTR"] = cv.take(2 * PH_N * 4);  // tile counters of the persistent contractions
+  o["GCTR"] = cv.take(kGemmCounters * PH_N * 4);  // tile counters of the persistent contractions
   o["SDNN"] = cv.take(FCS_SDNN_NPARAM * 4);
   o["BASIS"] = cv.take(256 * D);
   o["WDIL"] = cv.take((p.n_v + 1) * D);
@@ -748,7 +748,7 @@ fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed, 
   }
   if (ph == PH_EULER || ph == PH_CROSS || ph == PH_EULER0)
     HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
-                          static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->dptr<int>("GCTR") + 2 * ph,
+                          static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->dptr<int>("GCTR") + kGemmCounters * ph,
                           c->stream));
   else
     HIPCHK(c, launch_gemm_step(c->d_tasks[ph][variant], c->d_tiles[ph], static_cast<int>(c->phase_tiles[ph].size()),
@@ -1206,6 +1206,12 @@ extern "C" fcs_status fcs_get_field(fcs_ctx* c, int32_t patch, int32_t field, do
   } else {
     std::copy(h.begin(), h.end(), dst);
   }
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_autotune_times(const fcs_ctx* c, int32_t n, double* ms) {
+  if (!c || !ms || n < 0 || n > 16) return FCS_EINVAL;
+  for (int32_t q = 0; q < n; ++q) ms[q] = c->tune_ms[q];
   return FCS_OK;
 }
 

@@ -138,7 +138,7 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
     u = align_up(u + std::max<size_t>(b, 1));
     return o;
   };
-  s->o_ctr = take(8);
+  s->o_ctr = take(kGemmCounters * 4);
   s->o_off = take(s->ops.off.size() * 8);
   s->o_roff = take(s->ops.roff.size() * 8);
   s->o_ld = take(s->ops.ld.size() * 4);
@@ -176,7 +176,7 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   std::vector<uint16_t> bhi, blo;
   hipStream_t st = s->stream;
   // tile counters of the persistent variants start at zero
-  if (hipMemsetAsync(s->ws + s->o_ctr, 0, 8, st)) return FCS_EHIP;
+  if (hipMemsetAsync(s->ws + s->o_ctr, 0, kGemmCounters * 4, st)) return FCS_EHIP;
   if (hipMemcpyAsync(s->ws + s->o_off, s->ops.off.data(), s->ops.off.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_roff, s->ops.roff.data(), s->ops.roff.size() * 8, hipMemcpyHostToDevice, st) ||
       hipMemcpyAsync(s->ws + s->o_ld, s->ops.ld.data(), s->ops.ld.size() * 4, hipMemcpyHostToDevice, st) ||
@@ -263,7 +263,10 @@ extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, ch
   } else {
     const char* kind = v.xs ? "k_gemm_xs<" : (v.persist ? "k_gemm_fp_persist<" : "k_gemm_fp<");
     name = std::string(kind) + (precision == 0 ? "double" : "float") + ", " + std::to_string(v.kc) + ", " +
-           std::to_string(v.tb) + ">";
+           std::to_string(v.tb);
+    // the staged kernel carries its workgroups per CU (launch bound)
+    if (!v.xs && !v.persist) name += precision == 0 && v.kc == 8 ? ", 7" : ", 4";
+    name += ">";
   }
   if (static_cast<int32_t>(name.size()) >= len) return FCS_EINVAL;
   std::memcpy(buf, name.c_str(), name.size() + 1);

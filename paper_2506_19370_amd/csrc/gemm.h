@@ -13,6 +13,8 @@ namespace fcs {
 // contraction tile never tests operator bounds.  The padding is sized for the
 // largest tile (256 outputs) and the deepest chunk (32 columns).
 constexpr int kOpRowPad = 256;
+// Device counters (ints) that one persistent contraction launch uses.
+constexpr int kGemmCounters = 16;
 constexpr int kOpColPad = 32;
 inline int op_ld(int n) { return (n + kOpColPad - 1) / kOpColPad * kOpColPad; }
 inline int op_rows(int n) { return (n + kOpRowPad - 1) / kOpRowPad * kOpRowPad; }
@@ -33,9 +35,10 @@ void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::ve
 // Tile shape of a contraction launch: a workgroup covers 64 lines and 64 tb
 // outputs (tb = 1 or 2) and walks the operator depth in chunks of kc
 // (16 or 32; the split-BF16 kernel always uses 32).
-// persist: one workgroup per resident slot taking tiles from a device
-// counter pair (two ints, zero before the first launch; each launch leaves
-// them zero), tiles sorted longest first.
+// persist: one workgroup per resident slot (a multiple of 8), each taking
+// tiles of its XCD's queue from a device counter (kGemmCounters ints, zero
+// before the first launch; each launch leaves them zero), every queue sorted
+// longest tile first.
 // xs: operand lines staged in LDS, operator rows loaded straight into MFMA
 // registers (tb 2 or 4; FP64 and FP32).
 // xw: operand lines staged in LDS a wide slab at a time (128 columns, 64 in

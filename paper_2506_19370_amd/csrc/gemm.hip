@@ -670,37 +670,44 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16x3(const GemmTask* __restri
     gemm_xw_bf16x3_dir<SLAB, TB, false>(T, tile, ops, sm);
 }
 
-// Persistent form: the grid holds one workgroup per resident slot and each
-// workgroup takes tiles from a device counter until the list is exhausted
-// (tiles sorted longest first).  ctr[0] hands out tiles, ctr[1] counts
-// finished workgroups; the last one to finish resets both, so the next
-// launch (graph replays included) starts from zero without a memset.
+// Persistent form over the XCD queues.  The tile list holds 8 interleaved
+// queues (tile 8 r + x belongs to queue x, each queue longest tile first).
+// The grid is a multiple of 8 workgroups; workgroup b serves queue b mod 8
+// (the XCD it is dispatched to), takes tile r = b / 8 first and later ones
+// from the queue's counter ctr[x], offset by the workgroups per queue.  The
+// next index is requested before the current tile is computed, so the
+// atomic's latency hides behind it.  ctr[8] counts finished workgroups; the
+// last one resets all nine counters, so the next launch (graph replays
+// included) starts from zero without a memset.
 template <typename Body>
-__device__ __forceinline__ void persistent_tiles(int ntiles, int* ctr, Body body) {
-  __shared__ int tile_id;
-  for (;;) {
-    if (threadIdx.x == 0) tile_id = atomicAdd(&ctr[0], 1);
+__device__ __forceinline__ void xcd_queue_tiles(int ntiles, int* ctr, Body body) {
+  __shared__ int next_r;
+  const int x = blockIdx.x & 7, per_q = gridDim.x >> 3, qlen = ntiles >> 3;
+  int r = blockIdx.x >> 3;
+  while (r < qlen) {
+    int nr = 0;
+    if (threadIdx.x == 0) nr = atomicAdd(&ctr[x], 1) + per_q;
+    body(8 * r + x);
+    if (threadIdx.x == 0) next_r = nr;
+    __syncthreads();  // also: every wave is done with the tile's LDS
+    r = next_r;
     __syncthreads();
-    const int t = tile_id;
-    __syncthreads();
-    if (t < 0 || t >= ntiles) break;
-    body(t);
   }
   if (threadIdx.x == 0) {
     __threadfence();
-    if (atomicAdd(&ctr[1], 1) == static_cast<int>(gridDim.x) - 1) {
-      atomicExch(&ctr[0], 0);
-      atomicExch(&ctr[1], 0);
-    }
+    if (atomicAdd(&ctr[8], 1) == static_cast<int>(gridDim.x) - 1)
+      for (int q = 0; q < 9; ++q) atomicExch(&ctr[q], 0);
   }
 }
 
 // Stage contractions (every SSPRK stage) ...
 // Launch bounds: the second argument asks for that many waves per SIMD, which
 // bounds the registers per lane (no spills at these shapes).
-template <typename Elem, int KC, int TB>
-__global__ __launch_bounds__(256, 4) void k_gemm_fp(const GemmTask* __restrict__ tasks,
-                                                 const GemmTile* __restrict__ tiles, OpTables ops) {
+// MINB workgroups per CU: 8-column FP64 chunks (19 KB of LDS) let seven
+// share a CU, enough for the step-channel stage task set in one round.
+template <typename Elem, int KC, int TB, int MINB>
+__global__ __launch_bounds__(256, MINB) void k_gemm_fp(const GemmTask* __restrict__ tasks,
+                                                    const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
   if (tile.task < 0) return;  // padding tile of the XCD-ordered list
   gemm_fp<Elem, KC, TB>(tasks, tile, ops);
@@ -710,7 +717,10 @@ template <typename Elem, int KC, int TB>
 __global__ __launch_bounds__(256, 4) void k_gemm_fp_persist(const GemmTask* __restrict__ tasks,
                                                          const GemmTile* __restrict__ tiles, int ntiles,
                                                          OpTables ops, int* ctr) {
-  persistent_tiles(ntiles, ctr, [&](int t) { gemm_fp<Elem, KC, TB>(tasks, tiles[t], ops); });
+  xcd_queue_tiles(ntiles, ctr, [&](int t) {
+    const GemmTile tile = tiles[t];
+    if (tile.task >= 0) gemm_fp<Elem, KC, TB>(tasks, tile, ops);
+  });
 }
 
 // ... and the once-per-step FP64 contractions (viscosity gradient, filter),
@@ -868,7 +878,10 @@ template <int TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3_persist(const GemmTask* __restrict__ tasks,
                                                              const GemmTile* __restrict__ tiles, int ntiles,
                                                              OpTables ops, int* ctr) {
-  persistent_tiles(ntiles, ctr, [&](int t) { gemm_bf16x3<TB>(tasks, tiles[t], ops); });
+  xcd_queue_tiles(ntiles, ctr, [&](int t) {
+    const GemmTile tile = tiles[t];
+    if (tile.task >= 0) gemm_bf16x3<TB>(tasks, tile, ops);
+  });
 }
 
 // Resident workgroups of a kernel on the current device (cached per kernel
@@ -894,8 +907,10 @@ int device_slots(K kernel) {
 
 template <typename K, typename... Args>
 hipError_t launch_persist(K kernel, int ntiles, hipStream_t stream, Args... args) {
-  const int slots = device_slots(kernel);
-  if (slots <= 0) return hipErrorInvalidDevice;
+  // a multiple of 8 workgroups (one set per XCD queue), at most one per
+  // resident slot and per tile
+  const int slots = device_slots(kernel) / 8 * 8;
+  if (slots <= 0 || ntiles % 8) return hipErrorInvalidValue;
   hipLaunchKernelGGL(kernel, dim3(std::min(ntiles, slots)), dim3(256), 0, stream, args...);
   return hipGetLastError();
 }
@@ -1021,10 +1036,11 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
 #undef FCS_XS
     return hipGetLastError();
   }
-#define FCS_FP(E, KC, TB) hipLaunchKernelGGL((k_gemm_fp<E, KC, TB>), grid, block, 0, stream, tasks, tiles, ops)
+#define FCS_FP(E, KC, TB) hipLaunchKernelGGL((k_gemm_fp<E, KC, TB, 4>), grid, block, 0, stream, tasks, tiles, ops)
   if (precision == 0) {
-    // FP64 keeps 16-column chunks: 32 would exceed 64 KiB of static LDS
-    if (v.tb == 2) FCS_FP(double, 16, 2);
+    // FP64 chunks of 8 or 16 columns: 32 would exceed 64 KiB of static LDS
+    if (v.kc == 8) hipLaunchKernelGGL((k_gemm_fp<double, 8, 1, 7>), grid, block, 0, stream, tasks, tiles, ops);
+    else if (v.tb == 2) FCS_FP(double, 16, 2);
     else FCS_FP(double, 16, 1);
   } else if (precision == 1) {
     if (v.kc == 32) {
@@ -1049,18 +1065,20 @@ int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 4 ? 4 : (
 const GemmVariant* gemm_variants(int precision, int* count) {
   // {tb, kc, persist, xs, xw}
   static const GemmVariant f64[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
-                                    {1, 16, true, false, false},  {2, 16, false, true, false},
-                                    {4, 16, false, true, false},  {2, 16, false, false, true},
-                                    {4, 16, false, false, true}};
+                                    {1, 16, true, false, false},  {2, 16, true, false, false},
+                                    {2, 16, false, true, false},  {4, 16, false, true, false},
+                                    {2, 16, false, false, true},  {4, 16, false, false, true},
+                                    {1, 8, false, false, false}};
   static const GemmVariant f32[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
-                                    {1, 32, false, false, false}, {2, 16, false, true, false},
+                                    {1, 32, false, false, false}, {1, 16, true, false, false},
+                                    {1, 32, true, false, false},  {2, 16, false, true, false},
                                     {4, 16, false, true, false},  {2, 32, false, true, false},
                                     {4, 32, false, true, false},  {2, 16, false, false, true},
                                     {4, 16, false, false, true}};
   static const GemmVariant bf[] = {{1, 32, false, false, false}, {2, 32, false, false, false},
-                                   {1, 32, true, false, false},  {2, 32, false, false, true},
-                                   {4, 32, false, false, true}};
-  *count = precision == 0 ? 7 : (precision == 1 ? 9 : 5);
+                                   {1, 32, true, false, false},  {2, 32, true, false, false},
+                                   {2, 32, false, false, true},  {4, 32, false, false, true}};
+  *count = precision == 0 ? 9 : (precision == 1 ? 11 : 6);
   return precision == 0 ? f64 : (precision == 1 ? f32 : bf);
 }
 
@@ -1068,21 +1086,14 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
                       std::vector<GemmTile>& tiles) {
   tiles.clear();
   const int step = gemm_outputs_per_tile(v);
-  if (v.persist) {
-    for (size_t q = 0; q < ntasks; ++q)
-      for (int t0 = 0; t0 < n[q]; t0 += step)
-        for (int l0 = 0; l0 < nlines[q]; l0 += kLB) tiles.push_back({static_cast<int32_t>(q), l0, t0, 0});
-    // longest first (cost ~ operator depth x outputs of the tile)
-    auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
-    std::stable_sort(tiles.begin(), tiles.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
-    return;
-  }
   // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
   // L2.  Every task (one operator) is given to one XCD, balancing the work,
   // and the per-XCD queues are interleaved so that tile i runs on XCD i mod 8:
   // a task's operator rows are then fetched into one L2 only, and the output
   // tiles of each 64-line block follow one another there (its operand lines
   // are re-read from that L2).  Short queues are padded with empty tiles.
+  // The persistent form takes each queue longest tile first (cost ~ operator
+  // depth x outputs of the tile).
   constexpr int kXcd = 8;
   std::vector<std::vector<GemmTile>> queue(kXcd);
   std::vector<double> load(kXcd, 0.0);
@@ -1092,6 +1103,11 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
     for (int b = 0; b < nblk; ++b)
       for (int t0 = 0; t0 < n[q]; t0 += step) queue[x].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
     load[x] += static_cast<double>(nblk) * n[q] * n[q];
+  }
+  if (v.persist) {
+    auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
+    for (auto& qx : queue)
+      std::stable_sort(qx.begin(), qx.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
   }
   size_t len = 0;
   for (const auto& qx : queue) len = std::max(len, qx.size());

@@ -51,10 +51,17 @@ def test_sweep_parity(prec, tol, variant):
     x = torch.tensor(flat, device="cuda")
     d1 = torch.zeros_like(x)
     d2 = torch.zeros_like(x)
-    sw.run(x, d1, d2)
-    torch.cuda.synchronize()
-    g1, g2 = d1.cpu().numpy(), d2.cpu().numpy()
     r1, r2 = _sweep_ref(fields)
+    # twice: the persistent forms must leave their tile counters at zero
+    for _ in range(2):
+        d1.zero_()
+        d2.zero_()
+        sw.run(x, d1, d2)
+        torch.cuda.synchronize()
+        _check_sweep(d1.cpu().numpy(), d2.cpu().numpy(), fields, r1, r2, tol, (prec, variant))
+
+
+def _check_sweep(g1, g2, fields, r1, r2, tol, tag):
     off = 0
     for f, a, b in zip(fields, r1, r2):
         n = f.size
@@ -62,8 +69,35 @@ def test_sweep_parity(prec, tol, variant):
             scale = np.abs(f[c]).max()
             e1 = np.abs(g1[off:off + n].reshape(f.shape)[c] - a[c]).max() / scale
             e2 = np.abs(g2[off:off + n].reshape(f.shape)[c] - b[c]).max() / scale
-            assert e1 < tol and e2 < tol, (prec, variant, f.shape, c, e1, e2)
+            assert e1 < tol and e2 < tol, (tag, f.shape, c, e1, e2)
         off += n
+
+
+def _persistent_variants():
+    from paper_2506_19370_amd import _lib as L
+    return [(p, tol, v) for p, tol in (("fp64", 2e-12), ("fp32", 2e-6), ("bf16x3", 1e-4))
+            for v in range(L.fcs_gemm_variant_count(L.PREC[p])) if "persist" in L.gemm_variant_name(p, v)]
+
+
+@pytest.mark.parametrize("prec,tol,variant", _persistent_variants())
+def test_sweep_persistent_queues(prec, tol, variant):
+    """Persistent forms on a tile list several times the resident slots, so
+    that every workgroup takes further tiles from its XCD queue's counter;
+    three launches in a row (the counters must return to zero)."""
+    sizes, fields = W.deriv_sweep(npatch=160, nmin=60, nmax=160, seed_salt=2)
+    flat = np.concatenate([f.ravel() for f in fields])
+    sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
+    sw.set_variant(variant)
+    x = torch.tensor(flat, device="cuda")
+    d1 = torch.zeros_like(x)
+    d2 = torch.zeros_like(x)
+    r1, r2 = _sweep_ref(fields)
+    for _ in range(3):
+        d1.zero_()
+        d2.zero_()
+        sw.run(x, d1, d2)
+        torch.cuda.synchronize()
+        _check_sweep(d1.cpu().numpy(), d2.cpu().numpy(), fields, r1, r2, tol, (prec, variant))
 
 
 def test_sweep_full_size_sampled():
