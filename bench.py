@@ -35,15 +35,7 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # 256 MiB copy in the same runs); profiles/stage_contraction_fp64_traffic.md.
 # Valid for the kernels as they were when the counters were taken.
-STAGE_TRAFFIC_FP64 = {
-    "k_gemm_fp<double, 16, 1>": 91.90e6,
-    "k_gemm_fp<double, 16, 2>": 92.32e6,
-    "k_gemm_fp_persist<double, 16, 1>": 129.06e6,
-    "k_gemm_xs<double, 16, 2>": 94.96e6,
-    "k_gemm_xs<double, 16, 4>": 104.15e6,
-    "k_gemm_xw<double, 64, 2>": 93.80e6,
-    "k_gemm_xw<double, 64, 4>": 100.76e6,
-}
+STAGE_TRAFFIC_FP64 = {}
 HBM_PEAK = 8.0e12
 
 

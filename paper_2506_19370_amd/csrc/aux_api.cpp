@@ -265,7 +265,9 @@ extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, ch
     name = std::string(kind) + (precision == 0 ? "double" : "float") + ", " + std::to_string(v.kc) + ", " +
            std::to_string(v.tb);
     // the staged kernel carries its workgroups per CU (launch bound)
-    if (!v.xs && !v.persist) name += precision == 0 && v.kc == 8 ? ", 7" : ", 4";
+    if (!v.xs && !v.persist) {
+      name += ", " + std::to_string(v.minb) + ", " + std::to_string(v.pf);
+    }
     name += ">";
   }
   if (static_cast<int32_t>(name.size()) >= len) return FCS_EINVAL;

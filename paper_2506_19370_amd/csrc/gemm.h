@@ -43,12 +43,15 @@ void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::ve
 // registers (tb 2 or 4; FP64 and FP32).
 // xw: operand lines staged in LDS a wide slab at a time (128 columns, 64 in
 // FP64), operator rows in registers (tb 2 or 4; all precisions).
+// pf: the staged kernel keeps the loads of one or two chunks in flight.
 struct GemmVariant {
   int tb = 1;
   int kc = 16;
   bool persist = false;
   bool xs = false;
   bool xw = false;
+  int pf = 1;    // staged kernel: chunks whose loads are in flight (1 or 2)
+  int minb = 4;  // staged kernel: workgroups per CU of its launch bound
 };
 hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
                        int ntiles, const OpTables& ops, int* counters, hipStream_t stream);

@@ -47,6 +47,17 @@ namespace {
 
 constexpr int kLB = 64;  // lines per workgroup
 
+// Operand and result pointers come from the task table in memory, so the
+// compiler cannot tell their address space and would access them with FLAT
+// instructions.  Those count in the LDS wait counter too: every wait for an
+// LDS read would then also wait for the operand loads of the next chunk.
+// All operands and results are device global memory.
+typedef __attribute__((address_space(1))) double gdouble;
+typedef __attribute__((address_space(1))) float gfloat;
+__device__ __forceinline__ const gdouble* gsrc(const double* p) { return (const gdouble*)p; }
+__device__ __forceinline__ gdouble* gdst64(void* p) { return (gdouble*)p; }
+__device__ __forceinline__ gfloat* gdst32(void* p) { return (gfloat*)p; }
+
 // Element offset of position 0 of a line (row fastest numbering).
 __device__ __forceinline__ int64_t line_base(const GemmTask& T, int line) {
   const int c = line / T.nrow, r = line - c * T.nrow;
@@ -71,13 +82,13 @@ __device__ __forceinline__ void chunk_pos(bool q1, int e, int& l, int& kk) {
 template <int KC>
 struct XLoad {
   static constexpr int NX = kLB * KC / 256;
-  const double* base[NX];
+  const gdouble* base[NX];
   __device__ __forceinline__ void init(const GemmTask& T, int line0, int nlines, bool q1) {
 #pragma unroll
     for (int p = 0; p < NX; ++p) {
       int l, kk;
       chunk_pos<KC>(q1, threadIdx.x + 256 * p, l, kk);
-      base[p] = T.src + line_base(T, min(line0 + l, nlines - 1));
+      base[p] = gsrc(T.src) + line_base(T, min(line0 + l, nlines - 1));
     }
   }
   __device__ __forceinline__ void load(double (&v)[NX], bool q1, int k0, int n, int sstride) const {
@@ -114,9 +125,9 @@ __device__ __forceinline__ void store_tile(const GemmTask& T, const int64_t* dst
         if (rowsum) v += x0s[lloc] * rowsum[t0 + tloc];
         const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
         if (T.out_f32)
-          static_cast<float*>(T.dst)[o] = static_cast<float>(v);
+          gdst32(T.dst)[o] = static_cast<float>(v);
         else
-          static_cast<double*>(T.dst)[o] = v;
+          gdst64(T.dst)[o] = v;
       }
     }
   }
@@ -139,9 +150,9 @@ __device__ __forceinline__ void store_lines(const GemmTask& T, const int64_t* ds
       if (tloc >= nt || lloc >= nl) continue;
       const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
       if (T.out_f32)
-        static_cast<float*>(T.dst)[o] = static_cast<float>(acc[ob][r]);
+        gdst32(T.dst)[o] = static_cast<float>(acc[ob][r]);
       else
-        static_cast<double*>(T.dst)[o] = static_cast<double>(acc[ob][r]);
+        gdst64(T.dst)[o] = static_cast<double>(acc[ob][r]);
     }
   }
 }
@@ -167,14 +178,16 @@ struct SmemFp {
   int64_t dst[kLB];
 };
 
-template <typename Elem, int KC, int TB, bool Q1>
+template <typename Elem, int KC, int TB, bool Q1, int PF>
 __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
                                             SmemFp<Elem, KC, TB>& sm) {
   constexpr bool kF64 = sizeof(Elem) == 8;
   constexpr int kTT = 64 * TB;
   constexpr int kDV = 16 / sizeof(Elem);        // operator elements per 16-byte load
   constexpr int ND = kTT * KC / (256 * kDV);    // 16-byte operator loads per thread
+  constexpr int NX = XLoad<KC>::NX;
   static_assert(ND >= 1, "tile too small for the operator loader");
+  static_assert(PF == 1 || PF == 2, "prefetch depth 1 or 2");
   typedef Elem vec4 __attribute__((ext_vector_type(4)));
   auto& Xs = sm.Xs;
   auto& Ds = sm.Ds;
@@ -192,26 +205,29 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   XLoad<KC> xl;
   xl.init(T, tile.line0, nlines, q1);
-  double xr[XLoad<KC>::NX];
-  uint4 dr[ND];
-  auto load_d = [&](int k0) {
+  // register sets of the chunks in flight: one (PF = 1) or two (PF = 2,
+  // even chunks in set 0, odd chunks in set 1)
+  double xr[PF][NX];
+  uint4 dr[PF][ND];
+  auto load = [&](int set, int c) {
+    xl.load(xr[set], q1, c * KC, n, T.s_stride);
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * kDV, t = e / KC, kk = e % KC;
-      dr[p] = *reinterpret_cast<const uint4*>(D + static_cast<int64_t>(t) * ld + k0 + kk);
+      dr[set][p] = *reinterpret_cast<const uint4*>(D + static_cast<int64_t>(t) * ld + c * KC + kk);
     }
   };
-  auto stage = [&](int b) {
+  auto stage = [&](int b, int set) {
 #pragma unroll
-    for (int p = 0; p < XLoad<KC>::NX; ++p) {
+    for (int p = 0; p < NX; ++p) {
       int l, kk;
       chunk_pos<KC>(q1, tid + 256 * p, l, kk);
-      Xs[b][l][kk] = static_cast<Elem>(xr[p]);
+      Xs[b][l][kk] = static_cast<Elem>(xr[set][p]);
     }
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * kDV, t = e / KC, kk = e % KC;
-      const Elem* v = reinterpret_cast<const Elem*>(&dr[p]);
+      const Elem* v = reinterpret_cast<const Elem*>(&dr[set][p]);
 #pragma unroll
       for (int j = 0; j < kDV; ++j) Ds[b][t][kk + j] = v[j];
     }
@@ -222,21 +238,20 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
   // registers; every instantiation takes part in the same loads and barriers.
   const int nb = 16 * wave < nl ? (nt + 15) >> 4 : 0;
   const int nk = (n + KC - 1) / KC;
-  xl.load(xr, q1, 0, n, T.s_stride);
-  load_d(0);
-  stage(0);
+  // With two chunks in flight every load is issued unconditionally (chunk
+  // indices past the end clamped to the last chunk, inside the padded
+  // operator rows), so that each wait covers only the older set.
+  load(0, 0);
+  if constexpr (PF == 2) load(1, min(1, nk - 1));
+  stage(0, 0);
   __syncthreads();
+  if constexpr (PF == 2) load(0, min(2, nk - 1));
   with_live<4 * TB>(nb, [&](auto live) {
     constexpr int NL = decltype(live)::value;
     vec4 acc[NL > 0 ? NL : 1];
 #pragma unroll
     for (int ob = 0; ob < NL; ++ob) acc[ob] = vec4{0, 0, 0, 0};
-    for (int c = 0; c < nk; ++c) {
-      const int b = c & 1;
-      if (c + 1 < nk) {
-        xl.load(xr, q1, (c + 1) * KC, n, T.s_stride);
-        load_d((c + 1) * KC);
-      }
+    auto products = [&](int b) {
       if constexpr (NL > 0) {
 #pragma unroll
         for (int ks = 0; ks < KC; ks += 4) {
@@ -254,8 +269,30 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
           }
         }
       }
-      if (c + 1 < nk) stage(b ^ 1);
-      __syncthreads();
+    };
+    if constexpr (PF == 1) {
+      for (int c = 0; c < nk; ++c) {
+        const int b = c & 1;
+        if (c + 1 < nk) load(0, c + 1);
+        products(b);
+        if (c + 1 < nk) stage(b ^ 1, 0);
+        __syncthreads();
+      }
+    } else {
+      // chunk c in LDS buffer c & 1, chunks c + 1 and c + 2 in flight in the
+      // register sets (c + 1) & 1 and c & 1; unrolled by two so that the
+      // sets keep fixed registers
+      for (int c = 0; c < nk; c += 2) {
+        products(0);
+        if (c + 1 < nk) stage(1, 1);
+        __syncthreads();
+        load(1, min(c + 3, nk - 1));
+        if (c + 1 >= nk) break;
+        products(1);
+        if (c + 2 < nk) stage(0, 0);
+        __syncthreads();
+        load(0, min(c + 4, nk - 1));
+      }
     }
     if constexpr (NL > 0) store_lines<kF64, NL>(T, dst, nl, t0, nt, q1, wave, lane, acc);
   });
@@ -263,15 +300,15 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
 
 // The direction decides the operand roles of every MFMA; it is resolved
 // once per tile so that the inner loop holds no branch.
-template <typename Elem, int KC, int TB>
+template <typename Elem, int KC, int TB, int PF = 1>
 __device__ __forceinline__ void gemm_fp(const GemmTask* __restrict__ tasks, const GemmTile tile,
                                         const OpTables& ops) {
   __shared__ SmemFp<Elem, KC, TB> sm;
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
-    gemm_fp_dir<Elem, KC, TB, true>(T, tile, ops, sm);
+    gemm_fp_dir<Elem, KC, TB, true, PF>(T, tile, ops, sm);
   else
-    gemm_fp_dir<Elem, KC, TB, false>(T, tile, ops, sm);
+    gemm_fp_dir<Elem, KC, TB, false, PF>(T, tile, ops, sm);
 }
 
 // Operator in registers: only the operand lines (shared by the four waves)
@@ -317,7 +354,7 @@ __device__ __forceinline__ void gemm_xs_dir(const GemmTask& T, const GemmTile ti
   // operand staging: one line and NX consecutive columns per thread
   const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
   const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
-  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  const gdouble* __restrict__ xbase = gsrc(T.src) + line_base(T, min(tile.line0 + xs_line, nlines - 1));
   double xr[NX];
   auto load_x = [&](int k0) {
 #pragma unroll
@@ -460,7 +497,7 @@ __device__ __forceinline__ void gemm_xw_dir(const GemmTask& T, const GemmTile ti
   if (tid < kLB) dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
   const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
   const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
-  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  const gdouble* __restrict__ xbase = gsrc(T.src) + line_base(T, min(tile.line0 + xs_line, nlines - 1));
   // operator rows of this wave's output blocks (zero-padded beyond n)
   const Elem* drow[TB];
 #pragma unroll
@@ -572,11 +609,11 @@ __device__ __forceinline__ void gemm_xw_bf16x3_dir(const GemmTask& T, const Gemm
             rr = lane & 15;
   if (tid < kLB) {
     dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
-    x0s[tid] = T.src[dst[tid]];
+    x0s[tid] = gsrc(T.src)[dst[tid]];
   }
   const int xs_line = q1 ? tid / (256 / kLB) : tid % kLB;
   const int xs_col = NX * (q1 ? tid % (256 / kLB) : tid / kLB);
-  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xs_line, nlines - 1));
+  const gdouble* __restrict__ xbase = gsrc(T.src) + line_base(T, min(tile.line0 + xs_line, nlines - 1));
   const double x0 = xbase[0];
   const uint16_t* bh[TB];
   const uint16_t* bl[TB];
@@ -703,14 +740,17 @@ __device__ __forceinline__ void xcd_queue_tiles(int ntiles, int* ctr, Body body)
 // Stage contractions (every SSPRK stage) ...
 // Launch bounds: the second argument asks for that many waves per SIMD, which
 // bounds the registers per lane (no spills at these shapes).
-// MINB workgroups per CU: 8-column FP64 chunks (19 KB of LDS) let seven
-// share a CU, enough for the step-channel stage task set in one round.
-template <typename Elem, int KC, int TB, int MINB>
+// MINB workgroups per CU (the launch bound caps the registers at 512 /
+// MINB per lane): 8-column FP64 chunks (19 KB of LDS) let seven share a CU,
+// enough for the step-channel stage task set in one round; the two-chunk
+// prefetch of 16-column FP64 chunks needs the registers of three.
+// PF: chunks whose loads are in flight while a chunk is on the matrix cores.
+template <typename Elem, int KC, int TB, int MINB, int PF>
 __global__ __launch_bounds__(256, MINB) void k_gemm_fp(const GemmTask* __restrict__ tasks,
                                                     const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
   if (tile.task < 0) return;  // padding tile of the XCD-ordered list
-  gemm_fp<Elem, KC, TB>(tasks, tile, ops);
+  gemm_fp<Elem, KC, TB, PF>(tasks, tile, ops);
 }
 
 template <typename Elem, int KC, int TB>
@@ -768,11 +808,11 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   // threads hold neighbouring lines), splits them with packed conversions and
   // stores 16 bytes per table.
   const int xl_line = q1 ? tid >> 2 : tid & 63, xl_col = 8 * (q1 ? tid & 3 : tid >> 6);
-  const double* __restrict__ xbase = T.src + line_base(T, min(tile.line0 + xl_line, nlines - 1));
+  const gdouble* __restrict__ xbase = gsrc(T.src) + line_base(T, min(tile.line0 + xl_line, nlines - 1));
   const double x0 = xbase[0];  // line offset (first point of the line)
   if (tid < kLB) {
     dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
-    x0s[tid] = T.src[dst[tid]];
+    x0s[tid] = gsrc(T.src)[dst[tid]];
   }
   double xr[8];
   auto load_x = [&](int k0) {
@@ -1036,21 +1076,31 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
 #undef FCS_XS
     return hipGetLastError();
   }
-#define FCS_FP(E, KC, TB) hipLaunchKernelGGL((k_gemm_fp<E, KC, TB, 4>), grid, block, 0, stream, tasks, tiles, ops)
+  // staged kernel instances (element, chunk, tb, workgroups per CU, prefetch)
+#define FCS_FP(E, KC, TB, MB, PF)                                                               \
+  if (v.kc == KC && v.tb == TB && v.minb == MB && v.pf == PF) {                                \
+    hipLaunchKernelGGL((k_gemm_fp<E, KC, TB, MB, PF>), grid, block, 0, stream, tasks, tiles, ops); \
+    return hipGetLastError();                                                                   \
+  }
   if (precision == 0) {
     // FP64 chunks of 8 or 16 columns: 32 would exceed 64 KiB of static LDS
-    if (v.kc == 8) hipLaunchKernelGGL((k_gemm_fp<double, 8, 1, 7>), grid, block, 0, stream, tasks, tiles, ops);
-    else if (v.tb == 2) FCS_FP(double, 16, 2);
-    else FCS_FP(double, 16, 1);
-  } else if (precision == 1) {
-    if (v.kc == 32) {
-      if (v.tb == 2) FCS_FP(float, 32, 2);
-      else FCS_FP(float, 32, 1);
-    } else {
-      if (v.tb == 2) FCS_FP(float, 16, 2);
-      else FCS_FP(float, 16, 1);
-    }
-  } else if (v.tb == 2) {
+    FCS_FP(double, 16, 1, 4, 1)
+    FCS_FP(double, 16, 2, 4, 1)
+    FCS_FP(double, 8, 1, 7, 1)
+    FCS_FP(double, 16, 1, 3, 2)
+    FCS_FP(double, 8, 1, 4, 2)
+    return hipErrorInvalidValue;
+  }
+  if (precision == 1) {
+    FCS_FP(float, 16, 1, 4, 1)
+    FCS_FP(float, 16, 2, 4, 1)
+    FCS_FP(float, 32, 1, 4, 1)
+    FCS_FP(float, 32, 2, 4, 1)
+    FCS_FP(float, 16, 1, 4, 2)
+    FCS_FP(float, 16, 1, 7, 1)
+    return hipErrorInvalidValue;
+  }
+  if (v.tb == 2) {
     hipLaunchKernelGGL((k_gemm_bf16x3<2>), grid, block, 0, stream, tasks, tiles, ops);
   } else {
     hipLaunchKernelGGL((k_gemm_bf16x3<1>), grid, block, 0, stream, tasks, tiles, ops);
@@ -1063,22 +1113,24 @@ int gemm_lines_per_tile() { return kLB; }
 int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 4 ? 4 : (v.tb == 2 ? 2 : 1)); }
 
 const GemmVariant* gemm_variants(int precision, int* count) {
-  // {tb, kc, persist, xs, xw}
+  // {tb, kc, persist, xs, xw, pf, minb}
   static const GemmVariant f64[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
                                     {1, 16, true, false, false},  {2, 16, true, false, false},
                                     {2, 16, false, true, false},  {4, 16, false, true, false},
                                     {2, 16, false, false, true},  {4, 16, false, false, true},
-                                    {1, 8, false, false, false}};
+                                    {1, 8, false, false, false, 1, 7}, {1, 16, false, false, false, 2, 3},
+                                    {1, 8, false, false, false, 2, 4}};
   static const GemmVariant f32[] = {{1, 16, false, false, false}, {2, 16, false, false, false},
                                     {1, 32, false, false, false}, {1, 16, true, false, false},
                                     {1, 32, true, false, false},  {2, 16, false, true, false},
                                     {4, 16, false, true, false},  {2, 32, false, true, false},
                                     {4, 32, false, true, false},  {2, 16, false, false, true},
-                                    {4, 16, false, false, true}};
+                                    {4, 16, false, false, true},  {1, 16, false, false, false, 2, 4},
+                                    {1, 16, false, false, false, 1, 7}};
   static const GemmVariant bf[] = {{1, 32, false, false, false}, {2, 32, false, false, false},
                                    {1, 32, true, false, false},  {2, 32, true, false, false},
                                    {2, 32, false, false, true},  {4, 32, false, false, true}};
-  *count = precision == 0 ? 9 : (precision == 1 ? 11 : 6);
+  *count = precision == 0 ? 11 : (precision == 1 ? 13 : 6);
   return precision == 0 ? f64 : (precision == 1 ? f32 : bf);
 }
 
@@ -1089,11 +1141,16 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
   // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
   // L2.  Every task (one operator) is given to one XCD, balancing the work,
   // and the per-XCD queues are interleaved so that tile i runs on XCD i mod 8:
-  // a task's operator rows are then fetched into one L2 only, and the output
-  // tiles of each 64-line block follow one another there (its operand lines
-  // are re-read from that L2).  Short queues are padded with empty tiles.
-  // The persistent form takes each queue longest tile first (cost ~ operator
-  // depth x outputs of the tile).
+  // a task's operator rows and operand lines are then fetched into one L2
+  // only (the output tiles of a 64-line block re-read its lines from there).
+  // Short queues are padded with empty tiles.
+  // A queue that fits in about two rounds of the XCD's resident workgroups
+  // (at most 8 per CU on its 32 CUs) runs longest tile first (cost ~
+  // operator depth x outputs of the tile): the dispatcher hands consecutive
+  // workgroups of an XCD to different CUs, so every CU receives a mix of
+  // long and short tiles and the short ones fill the last round.  Longer
+  // queues keep each task's tiles together, which keeps its operator rows
+  // and operand lines in L2 while they run.
   constexpr int kXcd = 8;
   std::vector<std::vector<GemmTile>> queue(kXcd);
   std::vector<double> load(kXcd, 0.0);
@@ -1104,11 +1161,11 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
       for (int t0 = 0; t0 < n[q]; t0 += step) queue[x].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
     load[x] += static_cast<double>(nblk) * n[q] * n[q];
   }
-  if (v.persist) {
-    auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
-    for (auto& qx : queue)
+  constexpr size_t kSortedQueue = 2 * 8 * 32;
+  auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
+  for (auto& qx : queue)
+    if (v.persist || qx.size() <= kSortedQueue)
       std::stable_sort(qx.begin(), qx.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
-  }
   size_t len = 0;
   for (const auto& qx : queue) len = std::max(len, qx.size());
   for (size_t r = 0; r < len; ++r)
