@@ -35,7 +35,19 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
 # 256 MiB copy in the same runs); profiles/stage_contraction_fp64_traffic.md.
 # Valid for the kernels as they were when the counters were taken.
-STAGE_TRAFFIC_FP64 = {}
+STAGE_TRAFFIC_FP64 = {
+    "k_gemm_fp<double, 16, 1, 4, 1>": 108.79e6,
+    "k_gemm_fp<double, 16, 2, 4, 1>": 92.36e6,
+    "k_gemm_fp_persist<double, 16, 1>": 154.02e6,
+    "k_gemm_fp_persist<double, 16, 2>": 91.92e6,
+    "k_gemm_xs<double, 16, 2>": 93.18e6,
+    "k_gemm_xs<double, 16, 4>": 90.80e6,
+    "k_gemm_xw<double, 64, 2>": 93.08e6,
+    "k_gemm_xw<double, 64, 4>": 88.96e6,
+    "k_gemm_fp<double, 8, 1, 7, 1>": 109.08e6,
+    "k_gemm_fp<double, 16, 1, 3, 2>": 121.01e6,
+    "k_gemm_fp<double, 8, 1, 4, 2>": 109.14e6,
+}
 HBM_PEAK = 8.0e12
 
 
