@@ -109,7 +109,8 @@ struct fcs_ctx {
   hipStream_t stream = nullptr;
   // second stream of the per-step fork: the filter runs beside the viscosity
   hipStream_t stream2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;    // filter chain beside Alg. 3
+  hipEvent_t ev_fork2 = nullptr, ev_join2 = nullptr;  // step size beside the first contraction
   bool bound = false;
   std::map<std::string, size_t> off;
   double* arr[A_NARR] = {};
@@ -710,6 +711,8 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
     HIPCHK(c, hipStreamCreateWithFlags(&c->stream2, hipStreamNonBlocking));
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
     HIPCHK(c, hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_fork2, hipEventDisableTiming));
+    HIPCHK(c, hipEventCreateWithFlags(&c->ev_join2, hipEventDisableTiming));
   }
   return FCS_OK;
 }
@@ -800,12 +803,12 @@ ViscArgs visc_args(fcs_ctx* c) {
   return v;
 }
 
-// Alg. 3 + blend + gradient of mu, filter (Alg. 4), adaptive step.
+// Alg. 3 + blend + gradient of mu and the filter (Alg. 4); the adaptive
+// step size follows in the first stage.
 fcs_status per_step(fcs_ctx* c) {
   const int64_t P = c->P;
   const fcs_params& p = c->prm;
   double* U0 = c->arr[A_U0];
-  double* scal = c->dptr<double>("SCAL");
   fcs_status st;
   ViscArgs v{};
   if (c->visc) {
@@ -838,9 +841,7 @@ fcs_status per_step(fcs_ctx* c) {
     HIPCHK(c, launch_viscosity(v, c->stream));
   }
   if (fork) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
-  HIPCHK(c, launch_dt(U0, c->dptr<uint8_t>("FLAGS"), c->dptr<double>("MET9"), c->visc ? c->arr[A_MU] : nullptr,
-                      c->dptr<double>("DTPART"), c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, scal, c->stream));
-  return FCS_OK;
+  return FCS_OK;  // the step size is taken by the first stage (one_stage)
 }
 
 fcs_status one_stage(fcs_ctx* c, int s) {
@@ -862,6 +863,21 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   // after the filter (every step but the first) the filter's last kernel has
   // already stored the fluxes of the stage input
   if (s == 0 && !(p.filter && c->steps > 0)) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
+  // The step size (CFL and viscous limits) reads only the filtered state and
+  // mu: it runs on the second stream beside the first stage's contraction
+  // and joins before the stage update that uses it.
+  const bool dt_side = s == 0 && c->stream2 != nullptr;
+  if (s == 0) {
+    hipStream_t ds = c->stream;
+    if (dt_side) {
+      HIPCHK(c, hipEventRecord(c->ev_fork2, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->stream2, c->ev_fork2, 0));
+      ds = c->stream2;
+    }
+    HIPCHK(c, launch_dt(in, flags, met[9], c->visc ? c->arr[A_MU] : nullptr, c->dptr<double>("DTPART"),
+                        c->dt_blocks, P, p.gamma, p.cfl, p.dt_fixed, c->dptr<double>("SCAL"), ds));
+    if (dt_side) HIPCHK(c, hipEventRecord(c->ev_join2, c->stream2));
+  }
   fcs_status st;
   c->prof_stage = s;
   // the first stage's launch also differentiates mu (PH_EULER0); the later
@@ -870,6 +886,7 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   if ((st = run_gemm(c, eph, variant, p.precision, s > 0)) != FCS_OK) return st;
   if (c->visc && c->cross)
     if ((st = run_gemm(c, PH_CROSS, 0, p.precision, false)) != FCS_OK) return st;
+  if (dt_side) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join2, 0));
   StageArgs a{};
   a.P = P;
   a.stage = s;
@@ -1290,6 +1307,8 @@ extern "C" void fcs_destroy(fcs_ctx* c) {
   for (auto& e : c->ev) hipEventDestroy(e);
   if (c->ev_fork) hipEventDestroy(c->ev_fork);
   if (c->ev_join) hipEventDestroy(c->ev_join);
+  if (c->ev_fork2) hipEventDestroy(c->ev_fork2);
+  if (c->ev_join2) hipEventDestroy(c->ev_join2);
   if (c->stream2) hipStreamDestroy(c->stream2);
   delete c;
 }
