@@ -95,6 +95,7 @@ struct fcs_ctx {
   std::vector<PatchDev> pdev;
   std::vector<int2> rowrun, colrun;
   std::vector<int64_t> copy_pairs, idst, icol, bdst, bcol;
+  std::vector<int32_t> csrc;  // per point: copy donor of a lattice fringe point, else the point itself
   std::vector<int32_t> iptr, bptr;
   std::vector<double> ival, bval;
   std::vector<BcEntry> bc;
@@ -422,10 +423,13 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     return (*out)->fail(FCS_EOVERLAP, err);
   }
   c->iptr.push_back(0);
+  c->csrc.resize(P);
+  for (int64_t k = 0; k < P; ++k) c->csrc[k] = static_cast<int32_t>(k);
   for (const InterpRow& r : rows) {
     if (r.ent.size() == 1 && r.ent[0].second == 1.0) {
       c->copy_pairs.push_back(r.dst);
       c->copy_pairs.push_back(r.ent[0].first);
+      c->csrc[r.dst] = static_cast<int32_t>(r.ent[0].first);
     } else {
       c->idst.push_back(r.dst);
       for (const auto& e : r.ent) {
@@ -540,6 +544,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     o["TILE" + std::to_string(ph)] = cv.take(c->tile_cap[ph] * sizeof(GemmTile));
   }
   o["COPY"] = cv.take(c->copy_pairs.size() * 8);
+  o["CSRC"] = cv.take(P * 4);
   o["IDST"] = cv.take(c->idst.size() * 8);
   o["IPTR"] = cv.take(c->iptr.size() * 4);
   o["ICOL"] = cv.take(c->icol.size() * 8);
@@ -679,6 +684,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"ROWRUN", c->rowrun.data(), c->rowrun.size() * sizeof(int2)},
       {"COLRUN", c->colrun.data(), c->colrun.size() * sizeof(int2)},
       {"COPY", c->copy_pairs.data(), c->copy_pairs.size() * 8},
+      {"CSRC", c->csrc.data(), c->csrc.size() * 4},
       {"IDST", c->idst.data(), c->idst.size() * 8},
       {"IPTR", c->iptr.data(), c->iptr.size() * 4},
       {"ICOL", c->icol.data(), c->icol.size() * 8},
@@ -943,10 +949,13 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   FluxOut next = fo;
   if (s == 4) next.F = nullptr;
   a.flux = next;
+  // copy fringe points are updated inside the stage kernel (from their
+  // donors); the fringe kernel evaluates the interpolation rows only
+  a.csrc = c->dptr<int32_t>("CSRC");
   HIPCHK(c, launch_stage(a, c->stream));
-  HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
-                          c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
-                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), P, next, c->stream));
+  HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), 0, c->dptr<int64_t>("IDST"),
+                          c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"), c->dptr<double>("IVAL"),
+                          static_cast<int>(c->idst.size()), P, next, c->stream));
   c->cur = outp;
   return FCS_OK;
 }

@@ -49,6 +49,7 @@ struct StageArgs {
   FluxOut flux;
   const int32_t* pid;
   const PatchDev* patches;
+  const int32_t* csrc;  // per point: its copy donor (fringe points on a common lattice), else itself
 };
 
 struct ClassifyArgs {

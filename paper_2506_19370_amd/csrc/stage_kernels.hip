@@ -106,46 +106,55 @@ __global__ void k_stage(StageArgs a) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t P = a.P;
   if (k >= P) return;
-  const uint8_t f = a.flags[k];
-  if (!(f & kActive)) {
+  const uint8_t fk = a.flags[k];
+  if (!(fk & kActive)) {
     for (int q = 0; q < 4; ++q) a.out[q * P + k] = 0.0;
-    if (a.flux.F) store_flux(a.flux, P, k, f, 0.0, 0.0, 0.0, 0.0);
+    if (a.flux.F) store_flux(a.flux, P, k, fk, 0.0, 0.0, 0.0, 0.0);
     return;
   }
+  // A fringe point filled by a copy (its donor on a common lattice, never a
+  // recipient itself) takes its donor's update here instead of in the fringe
+  // kernel: the donor's inputs, this point's outputs and fluxes.  It keeps
+  // its own accumulator slot, which holds the same values as the donor's
+  // (both are formed from equal inputs), so the read-modify-write of the
+  // fourth stage does not race with the donor's thread.
+  const int64_t ks = a.csrc[k];
+  const uint8_t f = ks == k ? fk : a.flags[ks];
   const double dt = *a.dt;
   double L[4];
   if (f & kAffine) {
-    for (int q = 0; q < 4; ++q) L[q] = -(static_cast<double>(DF1[q * P + k]) + static_cast<double>(DF2[(4 + q) * P + k]));
-  } else {
-    double t1x = a.t1x[k], t1y = a.t1y[k], t2x = a.t2x[k], t2y = a.t2y[k];
     for (int q = 0; q < 4; ++q)
-      L[q] = -(t1x * static_cast<double>(DF1[q * P + k]) + t1y * static_cast<double>(DF1[(4 + q) * P + k]) +
-               t2x * static_cast<double>(DF2[q * P + k]) + t2y * static_cast<double>(DF2[(4 + q) * P + k]));
+      L[q] = -(static_cast<double>(DF1[q * P + ks]) + static_cast<double>(DF2[(4 + q) * P + ks]));
+  } else {
+    double t1x = a.t1x[ks], t1y = a.t1y[ks], t2x = a.t2x[ks], t2y = a.t2y[ks];
+    for (int q = 0; q < 4; ++q)
+      L[q] = -(t1x * static_cast<double>(DF1[q * P + ks]) + t1y * static_cast<double>(DF1[(4 + q) * P + ks]) +
+               t2x * static_cast<double>(DF2[q * P + ks]) + t2y * static_cast<double>(DF2[(4 + q) * P + ks]));
   }
   if (a.visc) {
-    double mu = a.mu[k], mu1 = a.mu1[k], mu2 = a.mu2[k];
+    double mu = a.mu[ks], mu1 = a.mu1[ks], mu2 = a.mu2[ks];
     double g11, g12, g22, l1, l2;
     if (f & kAffine) {
       // constant metrics of the subpatch; the index coordinates are harmonic
-      const PatchDev& pd = a.patches[a.pid[k]];
+      const PatchDev& pd = a.patches[a.pid[ks]];
       g11 = pd.g11;
       g12 = pd.g12;
       g22 = pd.g22;
       l1 = 0.0;
       l2 = 0.0;
     } else {
-      g11 = a.g11[k];
-      g12 = a.g12[k];
-      g22 = a.g22[k];
-      l1 = a.lap1[k];
-      l2 = a.lap2[k];
+      g11 = a.g11[ks];
+      g12 = a.g12[ks];
+      g22 = a.g22[ks];
+      l1 = a.lap1[ks];
+      l2 = a.lap2[ks];
     }
     const DT *W1 = static_cast<const DT*>(a.W1), *W2 = static_cast<const DT*>(a.W2);
     const DT *W11 = static_cast<const DT*>(a.W11), *W22 = static_cast<const DT*>(a.W22);
     const DT* W12 = static_cast<const DT*>(a.W12);
     for (int q = 0; q < 4; ++q) {
-      double w1 = W1[q * P + k], w2 = W2[q * P + k], w11 = W11[q * P + k], w22 = W22[q * P + k];
-      double w12 = W12 ? static_cast<double>(W12[q * P + k]) : 0.0;
+      double w1 = W1[q * P + ks], w2 = W2[q * P + ks], w11 = W11[q * P + ks], w22 = W22[q * P + ks];
+      double w12 = W12 ? static_cast<double>(W12[q * P + ks]) : 0.0;
       double lap = g11 * w11 + 2.0 * g12 * w12 + g22 * w22 + l1 * w1 + l2 * w2;
       double grad = g11 * mu1 * w1 + g12 * (mu1 * w2 + mu2 * w1) + g22 * mu2 * w2;
       L[q] = L[q] + mu * lap + grad;
@@ -153,22 +162,22 @@ __global__ void k_stage(StageArgs a) {
   }
   double o[4];
   for (int q = 0; q < 4; ++q) {
-    const double in = a.in[q * P + k], u0 = a.U0[q * P + k];
+    const double in = a.in[q * P + ks];
     switch (a.stage) {
       case 0:
-        o[q] = u0 + a.c[0] * dt * L[q];
+        o[q] = in + a.c[0] * dt * L[q];  // the input of the first stage is U0
         break;
       case 1:
-        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       case 2:
         a.acc[q * P + k] = a.c[4] * in;
-        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       case 3: {
         double acc = a.acc[q * P + k];
         a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
-        o[q] = a.c[1] * u0 + a.c[2] * in + a.c[3] * dt * L[q];
+        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
         break;
       }
       default:
@@ -186,10 +195,10 @@ __global__ void k_stage(StageArgs a) {
   if (bad) *a.bad_flag = 1;
   if (f & kBoundary) {
     const double t = *a.bcs.t + a.bcs.frac * dt;
-    apply_bc(a.bcs.bc[a.bcs.bcidx[k]], a.bcs.gamma, t, a.bcs.vortex, o[0], o[1], o[2], o[3]);
+    apply_bc(a.bcs.bc[a.bcs.bcidx[ks]], a.bcs.gamma, t, a.bcs.vortex, o[0], o[1], o[2], o[3]);
   }
   for (int q = 0; q < 4; ++q) a.out[q * P + k] = o[q];
-  if (a.flux.F) store_flux(a.flux, P, k, f, o[0], o[1], o[2], o[3]);
+  if (a.flux.F) store_flux(a.flux, P, k, fk, o[0], o[1], o[2], o[3]);
 }
 
 // Fringe fill (Sec. 3.3): rows 0 .. ncopy-1 copy one donor value (common
