@@ -1146,26 +1146,44 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
   // Short queues are padded with empty tiles.
   // A queue that fits in about two rounds of the XCD's resident workgroups
   // (at most 8 per CU on its 32 CUs) runs longest tile first (cost ~
-  // operator depth x outputs of the tile): the dispatcher hands consecutive
-  // workgroups of an XCD to different CUs, so every CU receives a mix of
-  // long and short tiles and the short ones fill the last round.  Longer
-  // queues keep each task's tiles together, which keeps its operator rows
-  // and operand lines in L2 while they run.
+  // operator depth x outputs of the tile), in snake order over bands of 32:
+  // the dispatcher hands consecutive workgroups of an XCD to different CUs,
+  // so every CU receives a mix of long and short tiles and the short ones
+  // fill the last round.  Longer queues keep each task's tiles together,
+  // which keeps its operator rows and operand lines in L2 while they run.
   constexpr int kXcd = 8;
+  constexpr int kCusPerXcd = 32;
   std::vector<std::vector<GemmTile>> queue(kXcd);
   std::vector<double> load(kXcd, 0.0);
-  for (size_t q = 0; q < ntasks; ++q) {
+  // tasks go to the least-loaded queue, heaviest first; each queue keeps its
+  // tasks in task order
+  auto task_load = [&](size_t q) { return static_cast<double>((nlines[q] + kLB - 1) / kLB) * n[q] * n[q]; };
+  std::vector<size_t> order(ntasks);
+  for (size_t q = 0; q < ntasks; ++q) order[q] = q;
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_load(a) > task_load(b); });
+  std::vector<int> task_queue(ntasks, 0);
+  for (size_t q : order) {
     const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    task_queue[q] = x;
+    load[x] += task_load(q);
+  }
+  for (size_t q = 0; q < ntasks; ++q) {
     const int nblk = (nlines[q] + kLB - 1) / kLB;
     for (int b = 0; b < nblk; ++b)
-      for (int t0 = 0; t0 < n[q]; t0 += step) queue[x].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
-    load[x] += static_cast<double>(nblk) * n[q] * n[q];
+      for (int t0 = 0; t0 < n[q]; t0 += step) queue[task_queue[q]].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
   }
-  constexpr size_t kSortedQueue = 2 * 8 * 32;
+  constexpr size_t kSortedQueue = 2 * 8 * kCusPerXcd;
   auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
   for (auto& qx : queue)
-    if (v.persist || qx.size() <= kSortedQueue)
+    if (v.persist || qx.size() <= kSortedQueue) {
       std::stable_sort(qx.begin(), qx.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
+      // snake order: every other band of one tile per CU reversed, so that
+      // the CU that receives a band's largest tile receives the next band's
+      // smallest
+      if (!v.persist)
+        for (size_t b0 = kCusPerXcd; b0 < qx.size(); b0 += 2 * kCusPerXcd)
+          std::reverse(qx.begin() + b0, qx.begin() + std::min(qx.size(), b0 + kCusPerXcd));
+    }
   size_t len = 0;
   for (const auto& qx : queue) len = std::max(len, qx.size());
   for (size_t r = 0; r < len; ++r)
