@@ -144,6 +144,10 @@ struct fcs_ctx {
   hipGraphExec_t pgexec[2] = {nullptr, nullptr};
   hipEvent_t pev[2][12] = {};  // stage pairs (stages 1..4 used), then an empty pair (event-node latency)
   bool capturing_prof = false;
+  bool in_capture = false;  // a whole step is being captured into a graph
+  // the proxy values (PS) hold the current state's: the last stage of a step
+  // evaluates them; set_state invalidates them
+  bool ps_valid = false;
   int prof_wf = 0, prof_stage = 0;
 
   template <typename T>
@@ -819,7 +823,9 @@ fcs_status per_step(fcs_ctx* c) {
   ViscArgs v{};
   if (c->visc) {
     v = visc_args(c);
-    HIPCHK(c, launch_proxy(v, c->stream));
+    // a captured step relies on the previous step's last stage (or on the
+    // proxy launch that precedes the graph's first replay)
+    if (!c->in_capture && !c->ps_valid) HIPCHK(c, launch_proxy(v, c->stream));
   }
   // Alg. 4 (filter) reads and rewrites the state, which after the proxy
   // kernel no part of Alg. 3 reads: with a second stream the two run side by
@@ -952,10 +958,13 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   // copy fringe points are updated inside the stage kernel (from their
   // donors); the fringe kernel evaluates the interpolation rows only
   a.csrc = c->dptr<int32_t>("CSRC");
+  // the last stage also leaves the next step's proxy values
+  a.ps = (s == 4 && c->visc) ? c->dptr<double2>("PS") : nullptr;
   HIPCHK(c, launch_stage(a, c->stream));
   HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), 0, c->dptr<int64_t>("IDST"),
                           c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"), c->dptr<double>("IVAL"),
-                          static_cast<int>(c->idst.size()), P, next, c->stream));
+                          static_cast<int>(c->idst.size()), P, next, a.ps, p.gamma, c->stream));
+  if (s == 4) c->ps_valid = c->visc;
   c->cur = outp;
   return FCS_OK;
 }
@@ -983,6 +992,7 @@ extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, con
   if (!c || !src) return FCS_EINVAL;
   if (!c->bound) return c->fail(FCS_ESTATE, "fcs_set_state before fcs_bind");
   if (patch < 0 || patch >= static_cast<int32_t>(c->grids.size())) return c->fail(FCS_EINVAL, "bad patch index");
+  c->ps_valid = false;
   const Grid& g = c->grids[patch];
   const size_t np = g.np();
   std::vector<double> h(4 * np);
@@ -1058,8 +1068,10 @@ fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
   int64_t saved = c->steps;
   c->steps = with_filter ? 1 : 0;
   bool saved_prof = c->prof;
+  const bool saved_ps = c->ps_valid;
   c->prof = false;
   c->capturing_prof = profiled;
+  c->in_capture = true;
   c->prof_wf = with_filter;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   fcs_status st = FCS_OK;
@@ -1070,6 +1082,8 @@ fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
   c->steps = saved;
   c->prof = saved_prof;
   c->capturing_prof = false;
+  c->in_capture = false;
+  c->ps_valid = saved_ps;
   if (st != FCS_OK) return st;
   if (e != hipSuccess) return c->fail(FCS_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
   e = hipGraphInstantiate(slot, graph, nullptr, nullptr, 0);
@@ -1145,7 +1159,9 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
       int wf = (c->prm.filter && c->steps > 0) ? 1 : 0;
       if (graph) {
         if ((st = capture_step(c, wf, c->prof)) != FCS_OK) return st;
+        if (c->visc && !c->ps_valid) HIPCHK(c, launch_proxy(visc_args(c), c->stream));
         HIPCHK(c, hipGraphLaunch(c->prof ? c->pgexec[wf] : c->gexec[wf], c->stream));
+        c->ps_valid = c->visc;
         c->cur = c->arr[A_U0];
         if (c->prof) {
           // the events of a profiled graph are re-recorded by every replay

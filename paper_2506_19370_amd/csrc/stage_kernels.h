@@ -50,6 +50,7 @@ struct StageArgs {
   const int32_t* pid;
   const PatchDev* patches;
   const int32_t* csrc;  // per point: its copy donor (fringe points on a common lattice), else itself
+  double2* ps;          // last stage of a step: proxy and wave speed of the new state (Alg. 3 input), or null
 };
 
 struct ClassifyArgs {
@@ -104,9 +105,10 @@ hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo,
 hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 // Fringe fill (copy pairs and interpolation rows) and, if fo.F, the fluxes
 // of the filled points.
+// ps (or null): also store the proxy and wave speed of each filled point.
 hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
                          const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
-                         const FluxOut& fo, hipStream_t s);
+                         const FluxOut& fo, double2* ps, double gamma, hipStream_t s);
 // Alg. 3 in two parts: the proxy variable and wave speeds (the only part
 // that reads the state), then classification, preliminary viscosity,
 // dilation and blend.

@@ -51,6 +51,14 @@ __device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t
   for (int q = 0; q < 8; ++q) fo.F[q * P + k] = v[q];
 }
 
+// Mach-number proxy and wave speed |u| + a of one state (the inputs of the
+// smoothness classifier and of the preliminary viscosity, Alg. 3).
+__device__ __forceinline__ double2 proxy_speed(double r, double mx, double my, double E, double gamma) {
+  const double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
+  const double speed = sqrt(mx * mx + my * my) / r;
+  return double2{speed * sqrt(r / (gamma * p)), speed + sqrt(gamma * p / r)};
+}
+
 __global__ void k_flux(const double* __restrict__ U, const uint8_t* __restrict__ flags, FluxOut fo, int64_t P) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
@@ -110,6 +118,7 @@ __global__ void k_stage(StageArgs a) {
   if (!(fk & kActive)) {
     for (int q = 0; q < 4; ++q) a.out[q * P + k] = 0.0;
     if (a.flux.F) store_flux(a.flux, P, k, fk, 0.0, 0.0, 0.0, 0.0);
+    if (a.ps) a.ps[k] = double2{0.0, 0.0};
     return;
   }
   // A fringe point filled by a copy (its donor on a common lattice, never a
@@ -199,6 +208,8 @@ __global__ void k_stage(StageArgs a) {
   }
   for (int q = 0; q < 4; ++q) a.out[q * P + k] = o[q];
   if (a.flux.F) store_flux(a.flux, P, k, fk, o[0], o[1], o[2], o[3]);
+  // the last stage also evaluates the next step's proxy (Alg. 3 input)
+  if (a.ps) a.ps[k] = proxy_speed(o[0], o[1], o[2], o[3], a.bcs.gamma);
 }
 
 // Fringe fill (Sec. 3.3): rows 0 .. ncopy-1 copy one donor value (common
@@ -208,7 +219,7 @@ __global__ void k_stage(StageArgs a) {
 __global__ void k_fringe(double* __restrict__ U, const uint8_t* __restrict__ flags, const int64_t* __restrict__ pairs,
                          int ncopy, const int64_t* __restrict__ dst, const int32_t* __restrict__ ptr,
                          const int64_t* __restrict__ col, const double* __restrict__ val, int ninterp, int64_t P,
-                         FluxOut fo) {
+                         FluxOut fo, double2* __restrict__ ps, double gamma) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= ncopy + ninterp) return;
   double s[4] = {0, 0, 0, 0};
@@ -228,6 +239,7 @@ __global__ void k_fringe(double* __restrict__ U, const uint8_t* __restrict__ fla
   }
   for (int m = 0; m < 4; ++m) U[m * P + k] = s[m];
   if (fo.F) store_flux(fo, P, k, flags[k], s[0], s[1], s[2], s[3]);
+  if (ps) ps[k] = proxy_speed(s[0], s[1], s[2], s[3], gamma);
 }
 
 // Proxy (Mach number) and |u| + a at every point.
@@ -239,10 +251,7 @@ __global__ void k_proxy(const double* __restrict__ U, const uint8_t* __restrict_
     ps[k] = double2{0.0, 0.0};
     return;
   }
-  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
-  double p = (gamma - 1.0) * (E - 0.5 * (mx * mx + my * my) / r);
-  double speed = sqrt(mx * mx + my * my) / r;
-  ps[k] = double2{speed * sqrt(r / (gamma * p)), speed + sqrt(gamma * p / r)};
+  ps[k] = proxy_speed(U[k], U[P + k], U[2 * P + k], U[3 * P + k], gamma);
 }
 
 // Window geometry of point k along direction dir: start index of the
@@ -554,10 +563,10 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
 
 hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
                          const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
-                         const FluxOut& fo, hipStream_t s) {
+                         const FluxOut& fo, double2* ps, double gamma, hipStream_t s) {
   if (ncopy + ninterp)
     hipLaunchKernelGGL(k_fringe, grid_for(ncopy + ninterp), dim3(256), 0, s, U, flags, copy_pairs, ncopy, idst, iptr,
-                       icol, ival, ninterp, P, fo);
+                       icol, ival, ninterp, P, fo, ps, gamma);
   return hipGetLastError();
 }
 
