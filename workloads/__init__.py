@@ -107,6 +107,47 @@ def annular_sector(n1=48, n2=32, r0=1.0, r1=2.0, th0=0.0, th1=np.pi / 3):
     return [PatchSpec(r * np.cos(th), r * np.sin(th), None, {k: EXACT for k in "WESN"}, SLIP, None, "S")]
 
 
+# ---------------------------------------------------------------- reflecting Sod box
+SOD_LEFT = (1.0, 0.0, 0.0, 1.0)
+SOD_RIGHT = (0.125, 0.0, 0.0, 0.1)
+
+
+def sod_reflect(h_index=200, nsub=4):
+    """2-D Sod problem on [0, 1] x [0, 0.25] (lattice spacing 1 / h_index):
+    one patch split along x into nsub overlapping subpatches (neighbouring
+    cores share 17 points), reflecting (slip) walls on all four sides."""
+    h = 1.0 / h_index
+    XE, YT = h_index, h_index // 4
+    e = 8
+    cuts = [int(round(XE * k / nsub)) for k in range(nsub + 1)]
+    out = []
+    for k in range(nsub):
+        X0 = cuts[k] - (e if k > 0 else 0)
+        X1 = cuts[k + 1] + (e if k < nsub - 1 else 0)
+        sides = {"W": SLIP if k == 0 else INTERNAL, "E": SLIP if k == nsub - 1 else INTERNAL, "S": SLIP, "N": SLIP}
+        out.append(lattice_patch(h, X0, X1, 0, YT, sides, "I"))
+    return out
+
+
+def sod_reflect_cores(h_index=200, nsub=4):
+    """Global lattice column ranges [c0, c1) owned by each subpatch of
+    sod_reflect (its core; the last one includes x = 1), for integrals over
+    the union without counting overlaps twice."""
+    XE = h_index
+    cuts = [int(round(XE * k / nsub)) for k in range(nsub + 1)]
+    return [(cuts[k], cuts[k + 1] + (1 if k == nsub - 1 else 0)) for k in range(nsub)]
+
+
+def sod_state(patch_list):
+    """Primitive Sod data: left state for x < 0.5, right state for x >= 0.5."""
+    out = []
+    for s in patch_list:
+        left = (s.x < 0.5)[None]
+        out.append(np.where(left, np.asarray(SOD_LEFT, float)[:, None, None],
+                            np.asarray(SOD_RIGHT, float)[:, None, None]))
+    return out
+
+
 # ---------------------------------------------------------------- Mach 3 step channel
 STEP_INFLOW = (1.4, 3.0, 0.0, 1.0)
 
