@@ -1155,12 +1155,18 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
   constexpr int kCusPerXcd = 32;
   std::vector<std::vector<GemmTile>> queue(kXcd);
   std::vector<double> load(kXcd, 0.0);
-  // tasks go to the least-loaded queue, heaviest first; each queue keeps its
-  // tasks in task order
+  // tasks go to the least-loaded queue (heaviest first when the queues will
+  // be sorted, in task order otherwise); each queue keeps its tasks in task
+  // order
+  constexpr size_t kSortedQueue = 2 * 8 * kCusPerXcd;
   auto task_load = [&](size_t q) { return static_cast<double>((nlines[q] + kLB - 1) / kLB) * n[q] * n[q]; };
+  size_t total = 0;
+  for (size_t q = 0; q < ntasks; ++q)
+    total += static_cast<size_t>((nlines[q] + kLB - 1) / kLB) * ((n[q] + step - 1) / step);
   std::vector<size_t> order(ntasks);
   for (size_t q = 0; q < ntasks; ++q) order[q] = q;
-  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_load(a) > task_load(b); });
+  if (total <= kXcd * kSortedQueue)
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_load(a) > task_load(b); });
   std::vector<int> task_queue(ntasks, 0);
   for (size_t q : order) {
     const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
@@ -1172,7 +1178,6 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
     for (int b = 0; b < nblk; ++b)
       for (int t0 = 0; t0 < n[q]; t0 += step) queue[task_queue[q]].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
   }
-  constexpr size_t kSortedQueue = 2 * 8 * kCusPerXcd;
   auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
   for (auto& qx : queue)
     if (v.persist || qx.size() <= kSortedQueue) {

@@ -107,7 +107,9 @@ __device__ __forceinline__ void apply_bc(const BcEntry& b, double gamma, double 
 
 // DT: element type of the stage derivatives (double, or float in the mixed
 // forms, where the contractions themselves are FP32 or split BF16).
-template <typename DT>
+// S: the stage (0..4), so that each instantiation reads only the registers
+// its combination uses and can issue all its loads up front.
+template <typename DT, int S>
 __global__ void k_stage(StageArgs a) {
   const DT* DF1 = static_cast<const DT*>(a.DF1);
   const DT* DF2 = static_cast<const DT*>(a.DF2);
@@ -170,28 +172,22 @@ __global__ void k_stage(StageArgs a) {
     }
   }
   double o[4];
+#pragma unroll
   for (int q = 0; q < 4; ++q) {
     const double in = a.in[q * P + ks];
-    switch (a.stage) {
-      case 0:
-        o[q] = in + a.c[0] * dt * L[q];  // the input of the first stage is U0
-        break;
-      case 1:
-        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
-        break;
-      case 2:
-        a.acc[q * P + k] = a.c[4] * in;
-        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
-        break;
-      case 3: {
-        double acc = a.acc[q * P + k];
-        a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
-        o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
-        break;
-      }
-      default:
-        o[q] = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
-        break;
+    if constexpr (S == 0) {
+      o[q] = in + a.c[0] * dt * L[q];  // the input of the first stage is U0
+    } else if constexpr (S == 1) {
+      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+    } else if constexpr (S == 2) {
+      a.acc[q * P + k] = a.c[4] * in;
+      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+    } else if constexpr (S == 3) {
+      const double acc = a.acc[q * P + k];
+      a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
+      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+    } else {
+      o[q] = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
     }
   }
   bool bad = false;
@@ -553,11 +549,23 @@ hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo,
   return hipGetLastError();
 }
 
+template <typename DT>
+void launch_stage_dt(const StageArgs& a, hipStream_t s) {
+  switch (a.stage) {
+    case 0: hipLaunchKernelGGL((k_stage<DT, 0>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_stage<DT, 1>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_stage<DT, 2>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_stage<DT, 3>), grid_for(a.P), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_stage<DT, 4>), grid_for(a.P), dim3(256), 0, s, a); break;
+  }
+}
+
 hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
+  if (a.stage < 0 || a.stage > 4) return hipErrorInvalidValue;
   if (a.deriv_f32)
-    hipLaunchKernelGGL(k_stage<float>, grid_for(a.P), dim3(256), 0, s, a);
+    launch_stage_dt<float>(a, s);
   else
-    hipLaunchKernelGGL(k_stage<double>, grid_for(a.P), dim3(256), 0, s, a);
+    launch_stage_dt<double>(a, s);
   return hipGetLastError();
 }
 
