@@ -36,17 +36,17 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 # 256 MiB copy in the same runs); profiles/stage_contraction_fp64_traffic.md.
 # Valid for the kernels as they were when the counters were taken.
 STAGE_TRAFFIC_FP64 = {
-    "k_gemm_fp<double, 16, 1, 4, 1>": 108.79e6,
-    "k_gemm_fp<double, 16, 2, 4, 1>": 92.36e6,
-    "k_gemm_fp_persist<double, 16, 1>": 154.02e6,
-    "k_gemm_fp_persist<double, 16, 2>": 91.92e6,
-    "k_gemm_xs<double, 16, 2>": 93.18e6,
-    "k_gemm_xs<double, 16, 4>": 90.80e6,
-    "k_gemm_xw<double, 64, 2>": 93.08e6,
-    "k_gemm_xw<double, 64, 4>": 88.96e6,
-    "k_gemm_fp<double, 8, 1, 7, 1>": 109.08e6,
-    "k_gemm_fp<double, 16, 1, 3, 2>": 121.01e6,
-    "k_gemm_fp<double, 8, 1, 4, 2>": 109.14e6,
+    "k_gemm_fp<double, 16, 1, 4, 1>": 95.28e6,
+    "k_gemm_fp<double, 16, 2, 4, 1>": 84.64e6,
+    "k_gemm_fp_persist<double, 16, 1>": 139.41e6,
+    "k_gemm_fp_persist<double, 16, 2>": 85.57e6,
+    "k_gemm_xs<double, 16, 2>": 82.94e6,
+    "k_gemm_xs<double, 16, 4>": 82.99e6,
+    "k_gemm_xw<double, 64, 2>": 83.43e6,
+    "k_gemm_xw<double, 64, 4>": 82.49e6,
+    "k_gemm_fp<double, 8, 1, 7, 1>": 98.05e6,
+    "k_gemm_fp<double, 16, 1, 3, 2>": 103.46e6,
+    "k_gemm_fp<double, 8, 1, 4, 2>": 95.31e6,
 }
 HBM_PEAK = 8.0e12
 
