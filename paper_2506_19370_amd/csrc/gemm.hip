@@ -846,53 +846,73 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
       *reinterpret_cast<uint4*>(&Dl[b][t][kk]) = lr[p];
     }
   };
-  f32x4 am[TB][4], ac[TB][4];
-#pragma unroll
-  for (int i = 0; i < TB; ++i)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) am[i][b] = ac[i][b] = f32x4{0, 0, 0, 0};
   const int nk = (n + KC - 1) / KC;
   load_x(0);
   load_d(0);
   stage(0);
   __syncthreads();
   const int rr = lane & 15, kb = 8 * (lane >> 4);
-  for (int c = 0; c < nk; ++c) {
-    const int b = c & 1;
-    if (c + 1 < nk) {
-      load_x((c + 1) * KC);
-      load_d((c + 1) * KC);
+  // Wave w owns the 16 lines 16 w .. 16 w + 15 and every output block of the
+  // tile; blocks past the line end are skipped by all waves alike (the chunk
+  // loop is instantiated per count of live blocks, as in the FP64/FP32
+  // kernel).
+  const int nb = 16 * wave < nl ? (nt + 15) >> 4 : 0;
+  const double* rowsum = ops.rowsum + ops.roff[T.op];
+  with_live<4 * TB>(nb, [&](auto live) {
+    constexpr int NL = decltype(live)::value;
+    f32x4 bm[NL > 0 ? NL : 1], bc[NL > 0 ? NL : 1];
+#pragma unroll
+    for (int ob = 0; ob < NL; ++ob) bm[ob] = bc[ob] = f32x4{0, 0, 0, 0};
+    for (int c = 0; c < nk; ++c) {
+      const int b = c & 1;
+      if (c + 1 < nk) {
+        load_x((c + 1) * KC);
+        load_d((c + 1) * KC);
+      }
+      if constexpr (NL > 0) {
+        const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[b][16 * wave + rr][kb]));
+        const bf16x8 xlo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[b][16 * wave + rr][kb]));
+#pragma unroll
+        for (int ob = 0; ob < NL; ++ob) {
+          const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * ob + rr][kb]));
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * ob + rr][kb]));
+          if (q1) {
+            bm[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bh, bm[ob], 0, 0, 0);
+            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl, bc[ob], 0, 0, 0);
+            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xlo, bh, bc[ob], 0, 0, 0);
+          } else {
+            bm[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xh, bm[ob], 0, 0, 0);
+            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xlo, bc[ob], 0, 0, 0);
+            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, xh, bc[ob], 0, 0, 0);
+          }
+        }
+      }
+      if (c + 1 < nk) stage(b ^ 1);
+      __syncthreads();
     }
-    bf16x8 xh[4], xlo[4];
+    // the two FP32 accumulations are added in FP64 at the store, with the
+    // exact offset term x0 * rowsum
+    if constexpr (NL > 0) {
 #pragma unroll
-    for (int lb = 0; lb < 4; ++lb) {
-      xh[lb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[b][16 * lb + rr][kb]));
-      xlo[lb] = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[b][16 * lb + rr][kb]));
-    }
+      for (int ob = 0; ob < NL; ++ob) {
+        if (16 * ob >= nt) continue;
 #pragma unroll
-    for (int i = 0; i < TB; ++i) {
-      const int tb = wave + 4 * i;
-      if (16 * tb >= nt) continue;  // block past the line end: no products
-      const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * tb + rr][kb]));
-      const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * tb + rr][kb]));
-#pragma unroll
-      for (int lb = 0; lb < 4; ++lb) {
-        if (q1) {
-          am[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[lb], bh, am[i][lb], 0, 0, 0);
-          ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh[lb], bl, ac[i][lb], 0, 0, 0);
-          ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xlo[lb], bh, ac[i][lb], 0, 0, 0);
-        } else {
-          am[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xh[lb], am[i][lb], 0, 0, 0);
-          ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xlo[lb], ac[i][lb], 0, 0, 0);
-          ac[i][lb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, xh[lb], ac[i][lb], 0, 0, 0);
+        for (int r = 0; r < 4; ++r) {
+          const int row = 4 * (lane >> 4) + r, col = lane & 15;
+          const int lloc = 16 * wave + (q1 ? row : col);
+          const int tloc = 16 * ob + (q1 ? col : row);
+          if (tloc >= nt || lloc >= nl) continue;
+          const double v = static_cast<double>(bm[ob][r]) + static_cast<double>(bc[ob][r]) +
+                           x0s[lloc] * rowsum[t0 + tloc];
+          const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
+          if (T.out_f32)
+            gdst32(T.dst)[o] = static_cast<float>(v);
+          else
+            gdst64(T.dst)[o] = v;
         }
       }
     }
-    if (c + 1 < nk) stage(b ^ 1);
-    __syncthreads();
-  }
-  // the two FP32 accumulations are added in FP64 at the store
-  store_tile<false, TB>(T, dst, nl, t0, nt, q1, wave, lane, am, ac, x0s, ops.rowsum + ops.roff[T.op]);
+  });
 }
 
 template <int TB>
