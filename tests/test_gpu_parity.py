@@ -61,6 +61,32 @@ def test_sweep_parity(prec, tol, variant):
         _check_sweep(d1.cpu().numpy(), d2.cpu().numpy(), fields, r1, r2, tol, (prec, variant))
 
 
+@pytest.mark.parametrize("prec,tol,variant", _variants())
+def test_sweep_extreme_sizes(prec, tol, variant):
+    """The largest subpatch side (1024 points: 16 output tiles of 64 per line,
+    operator tables of 1024 rows) and the shortest line (2 d = 10 points: one
+    ragged block of a single chunk) in one grouped launch, every variant.  The
+    operator row sums of |entries| reach 19.5 at n = 1024, which keeps the
+    FP32 and split-BF16 bounds of test_sweep_parity.  FP64: on lines of 10-12
+    points the d = 5 continuation dominates the operator and the library's
+    and the oracle's operators differ by up to the 3e-12 (relative to max|f|)
+    of the module's error model, so the bound is twice that."""
+    if prec == "fp64":
+        tol = 6e-12
+    sizes = np.array([(1024, 12), (12, 1024), (10, 37), (37, 10), (10, 10), (257, 11)])
+    fields = W.sweep_fields(sizes, W.rng(3, 7))
+    flat = np.concatenate([f.ravel() for f in fields])
+    sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
+    sw.set_variant(variant)
+    x = torch.tensor(flat, device="cuda")
+    d1 = torch.zeros_like(x)
+    d2 = torch.zeros_like(x)
+    r1, r2 = _sweep_ref(fields)
+    sw.run(x, d1, d2)
+    torch.cuda.synchronize()
+    _check_sweep(d1.cpu().numpy(), d2.cpu().numpy(), fields, r1, r2, tol, (prec, variant))
+
+
 def _check_sweep(g1, g2, fields, r1, r2, tol, tag):
     off = 0
     for f, a, b in zip(fields, r1, r2):

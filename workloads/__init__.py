@@ -222,6 +222,12 @@ def deriv_sweep(npatch=2000, nmin=64, nmax=256, config_index=3, seed_salt=0):
     Returns (sizes (npatch, 2) as (n1, n2), list of fields (4, n2, n1))."""
     g = rng(config_index, seed_salt)
     sizes = g.integers(nmin, nmax + 1, size=(npatch, 2))
+    return sizes, sweep_fields(sizes, g)
+
+
+def sweep_fields(sizes, g):
+    """The four fields of deriv_sweep on patches of the given (n1, n2) sizes,
+    drawn from the generator g."""
     fields = []
     for (n1, n2) in sizes:
         q1 = np.linspace(0, 1, n1)[None, :]
@@ -245,7 +251,7 @@ def deriv_sweep(npatch=2000, nmin=64, nmax=256, config_index=3, seed_salt=0):
                 v[:, i] += g.uniform(0.1, 1.0) * (q2[:, 0] >= qj)
             f[c] = off + sc * v
         fields.append(f)
-    return sizes, fields
+    return fields
 
 
 # ---------------------------------------------------------------- classifier weights
