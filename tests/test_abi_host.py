@@ -115,3 +115,31 @@ def test_create_rejects_invalid_parameters():
         with pytest.raises(L.FcsError) as e:
             _create(specs, **bad)
         assert e.value.status == L.FCS_EINVAL
+
+
+def test_create_rejects_empty_and_out_of_range_patch_sets():
+    from paper_2506_19370_amd import _lib as L
+    from paper_2506_19370_amd.api import SolverParams
+    # no subpatch at all
+    with pytest.raises(L.FcsError) as e:
+        _create([], fc_d=2, fc_C=27)
+    assert e.value.status == L.FCS_EINVAL
+    # sides below 2 d points or above 1024 points
+    for n1, n2 in ((3, 40), (40, 3), (1025, 12)):
+        spec = W.box_patch(0.0, 1.0, 0.0, 1.0, n1, n2, {k: W.SLIP for k in "WESN"})
+        with pytest.raises(L.FcsError) as e:
+            _create([spec], fc_d=2, fc_C=27)
+        assert e.value.status == L.FCS_EINVAL
+
+
+def test_sweep_create_validates_sizes():
+    from paper_2506_19370_amd import _lib as L
+    import ctypes
+    h = ctypes.c_void_p()
+    for sizes, d in (([], 5), ([(9, 40)], 5), ([(40, 1025)], 5), ([(40, 40)], 0)):
+        sz = np.ascontiguousarray(np.asarray(sizes, dtype=np.int32).reshape(-1, 2))
+        st = L.fcs_sweep_create(len(sz), sz.ctypes.data if len(sz) else None, 4, 0, d, 27, ctypes.byref(h))
+        assert st == L.FCS_EINVAL, (sizes, d, st)
+    sz = np.array([[10, 1024]], dtype=np.int32)  # the smallest and largest sides for d = 5
+    assert L.fcs_sweep_create(1, sz.ctypes.data, 4, 0, 5, 27, ctypes.byref(h)) == L.FCS_OK
+    L.fcs_sweep_destroy(h)
