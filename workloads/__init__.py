@@ -148,6 +148,45 @@ def sod_state(patch_list):
     return out
 
 
+# ---------------------------------------------------------------- Mach-M shock tube
+def mach_shock_states(M, gamma=1.4):
+    """Primitive states behind and ahead of a shock travelling at speed M into
+    gas at rest with (rho, p) = (1.4, 1) (sound speed 1): the
+    Rankine-Hugoniot jump of pressure zeta, velocity (zeta - 1) / (gamma M)
+    and density ratio (gamma + 1) M^2 / ((gamma - 1) M^2 + 2)."""
+    zeta = (2 * gamma * M * M - gamma + 1) / (gamma + 1)
+    ratio = (gamma + 1) * M * M / ((gamma - 1) * M * M + 2)
+    ahead = (1.4, 0.0, 0.0, 1.0)
+    behind = (1.4 * ratio, (zeta - 1) / (gamma * M), 0.0, zeta)
+    return behind, ahead
+
+
+def mach_shock_tube(M, h_index=200, nsub=4):
+    """Channel [0, 1] x [0, 0.25] split along x into nsub overlapping
+    subpatches (neighbouring cores share 17 points): inflow of the post-shock
+    state at x = 0, outflow at x = 1, slip walls at y = 0 and y = 0.25."""
+    behind, _ = mach_shock_states(M)
+    h = 1.0 / h_index
+    XE, YT = h_index, h_index // 4
+    e = 8
+    cuts = [int(round(XE * k / nsub)) for k in range(nsub + 1)]
+    out = []
+    for k in range(nsub):
+        X0 = cuts[k] - (e if k > 0 else 0)
+        X1 = cuts[k + 1] + (e if k < nsub - 1 else 0)
+        sides = {"W": INFLOW if k == 0 else INTERNAL, "E": OUTFLOW if k == nsub - 1 else INTERNAL,
+                 "S": SLIP, "N": SLIP}
+        out.append(lattice_patch(h, X0, X1, 0, YT, sides, "I", behind))
+    return out
+
+
+def mach_shock_state(patch_list, M, x_s):
+    """The Mach-M shock data: post-shock state for x < x_s, gas at rest ahead."""
+    behind, ahead = mach_shock_states(M)
+    return [np.where((s.x < x_s)[None], np.asarray(behind, float)[:, None, None],
+                     np.asarray(ahead, float)[:, None, None]) for s in patch_list]
+
+
 # ---------------------------------------------------------------- Mach 3 step channel
 STEP_INFLOW = (1.4, 3.0, 0.0, 1.0)
 
