@@ -31,22 +31,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
-# HBM bytes per stage-contraction launch on the step channel (FP64), from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.0, WRITE_SIZE x 1.0, factors from a
-# 256 MiB copy in the same runs); profiles/stage_contraction_fp64_traffic.md.
-# Valid for the kernels as they were when the counters were taken.
+# HBM bytes per stage-contraction launch on the step channel (FP64): the
+# launches the roofline times (the last step's stage contraction, back to
+# back), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the
+# factors a 256 MiB copy gives in the same runs.  The work per launch follows
+# the flow (viscous lines are skipped where mu vanishes), so a figure holds
+# for its kernel after the same number of steps and warm-up steps, and for
+# the kernels as they were when the counters were taken.
 STAGE_TRAFFIC_FP64 = {
-    "k_gemm_fp<double, 16, 1, 4, 1>": 95.28e6,
-    "k_gemm_fp<double, 16, 2, 4, 1>": 84.64e6,
-    "k_gemm_fp_persist<double, 16, 1>": 139.41e6,
-    "k_gemm_fp_persist<double, 16, 2>": 85.57e6,
-    "k_gemm_xs<double, 16, 2>": 82.94e6,
-    "k_gemm_xs<double, 16, 4>": 82.99e6,
-    "k_gemm_xw<double, 64, 2>": 83.43e6,
-    "k_gemm_xw<double, 64, 4>": 82.49e6,
-    "k_gemm_fp<double, 8, 1, 7, 1>": 98.05e6,
-    "k_gemm_fp<double, 16, 1, 3, 2>": 103.46e6,
-    "k_gemm_fp<double, 8, 1, 4, 2>": 95.31e6,
+    # profiles/stage_contraction_fp64_traffic.md: fetched 28.63 MB + written 25.37 MB
+    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 53.99e6,
 }
 HBM_PEAK = 8.0e12
 
@@ -63,6 +57,9 @@ def parse():
                                                            "(for per-dispatch counter runs)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (byte-counter calibration)")
+    ap.add_argument("--stage-variant", default=None,
+                    help="pin the FP64 stage-contraction tile shape (a kernel name as reported in roofline.kernel) "
+                         "instead of tuning it (for counter runs, whose dispatch serialization skews the tuner)")
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -162,8 +159,16 @@ def make_solver(F, W, torch, weights, precision, stream, use_graph=True):
     return S, specs
 
 
-def timed_run(S, torch, stream, steps, warmup):
-    S.advance(5 * warmup, sync=True)
+def timed_run(S, torch, stream, steps, warmup, retune=True):
+    # The first advance tunes the contraction tile on the initial state, where
+    # no viscous line is active yet; the last warm-up step tunes it again on
+    # the developed flow (and captures the step graphs anew).
+    if warmup > 0 and retune:
+        S.advance(5 * (warmup - 1), sync=True)
+        S.retune()
+        S.advance(5, sync=True)
+    elif warmup > 0:
+        S.advance(5 * warmup, sync=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     S.advance(5 * steps)
@@ -189,14 +194,18 @@ def field_errors(ref_solver, solver, specs):
     return errs
 
 
-def contraction_profile(S, torch, nsteps=20):
-    """Average duration of the grouped derivative contraction, from HIP events
-    recorded around each launch on the solver stream (eager replay)."""
+def contraction_profile(S, torch, nsteps=20, reps=50):
+    """Duration of the stage contraction: (1) HIP events around each launch in
+    nsteps replayed steps (event-record nodes in the graph; the interval also
+    holds the dispatch latency those nodes add), then (2) the last of those
+    steps' stage contraction alone, reps launches back to back between two
+    HIP events on the solver stream: the kernel's own average duration."""
     S.profile(True)
     S.advance(5 * nsteps, sync=True)
-    r = S.profile_read()
+    graph = S.profile_read()
     S.profile(False)
-    return r
+    alone = S.profile_stage(reps)
+    return alone, graph
 
 
 def cpu_baseline(W, steps):
@@ -230,17 +239,17 @@ def main():
     weights = train_classifier(F, W, torch)
     stream = torch.cuda.Stream()
     S, specs = make_solver(F, W, torch, weights, "fp64", stream, use_graph=not a.eager)
+    if a.stage_variant:
+        S.set_stage_variant(a.stage_variant)
     npts = int(sum(s.npoints() for s in specs))
-    el = timed_run(S, torch, stream, a.steps, a.warmup)
+    el = timed_run(S, torch, stream, a.steps, a.warmup, retune=not a.stage_variant)
     value = npts * 5 * a.steps / el
-    prof = contraction_profile(S, torch)
-    # event-bracketed interval inside the replayed graph (it includes the
-    # latency of the event nodes themselves, reported separately)
+    prof, gprof = contraction_profile(S, torch)
     kernel_ms = prof["avg_ms"]
     achieved = prof["flops"] / (kernel_ms * 1e-3)
     from paper_2506_19370_amd import _lib as L
     kernel = L.gemm_variant_name("fp64", S.stats()["stage_variant"])
-    traffic = STAGE_TRAFFIC_FP64.get(kernel)
+    traffic = STAGE_TRAFFIC_FP64.get((kernel, a.steps, a.warmup))
     out = {
         "metric": "point-stage updates/s, plain FP64 vs mixed-precision batched form at stated error",
         "value": value, "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
@@ -253,9 +262,11 @@ def main():
         "roofline": {"bound": "mfma", "kernel": kernel + " (grouped FC stage contraction, autotuned tile)",
                      "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / PEAK["fp64"], "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "avg_launch_ms": kernel_ms, "event_pair_latency_ms": prof["event_latency_ms"],
+                     "avg_launch_ms": kernel_ms, "launches_timed": prof["launches"],
+                     "timing": "the last step's stage contraction, launches back to back between HIP events",
+                     "in_graph_event_bracket_ms": gprof["avg_ms"], "event_pair_latency_ms": gprof["event_latency_ms"],
                      "flops_per_launch": prof["flops"],
-                     "algorithmic_bytes_per_launch": prof["bytes"], "launches_timed": prof["launches"]},
+                     "algorithmic_bytes_per_launch": prof["bytes"]},
     }
     if not a.no_mixed:
         # mixed forms: FP32 or split-BF16 contractions, FP64 state and stage arithmetic
@@ -264,7 +275,7 @@ def main():
                            ("bf16x3", "split-BF16 x3 contractions (FP32 accumulate, FP64 recombination), FP64 state")):
             Sm, _ = make_solver(F, W, torch, weights, prec, stream)
             elm = timed_run(Sm, torch, stream, a.steps, a.warmup)
-            pm = contraction_profile(Sm, torch)
+            pm, _ = contraction_profile(Sm, torch)
             err_long = field_errors(S, Sm, specs)
             # short horizons: fresh runs from the same state
             errs = {}

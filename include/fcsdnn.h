@@ -101,6 +101,12 @@ typedef struct {
   int32_t use_graph;   /* nonzero: replay whole steps as a captured hipGraph */
   int32_t autotune;    /* nonzero: time the contraction tile shapes on the
                           first advance and keep the fastest               */
+  int32_t visc_all_lines; /* nonzero: evaluate the viscous derivatives on
+                          every grid line.  0 (default): on lattice
+                          subpatches a row or column along which mu vanishes
+                          in a step is skipped; its derivatives only meet
+                          exact zeros there (Sec. 4, localized viscosity),
+                          so the state is the same                         */
   const float* sdnn_weights; /* host, FCS_SDNN_NPARAM floats; copied        */
   double vortex[5];    /* EXACT sides: beta, x0, y0, u0, v0 of the isentropic
                           vortex (background rho = p = 1)                    */
@@ -183,11 +189,29 @@ fcs_status fcs_stats(fcs_ctx* ctx, fcs_stats_t* out);
  * candidates not timed).  FCS_EINVAL for n out of range or a NULL ms. */
 fcs_status fcs_autotune_times(const fcs_ctx* ctx, int32_t n, double* ms);
 
+/* Tune again (autotune in fcs_params): the next advance times the
+ * candidates on the current state, with the viscous lines its viscosity
+ * needs, keeps the fastest and captures its step graphs anew.  For runs
+ * whose localized viscosity grows or shrinks far from where the first
+ * tuning saw it.  Synchronizes the stream; the state is not changed.
+ * FCS_ESTATE before fcs_bind. */
+fcs_status fcs_retune(fcs_ctx* ctx);
+
+/* Pin the stage-contraction tile shape to candidate `index` (the order of
+ * fcs_gemm_variant_name for the context's precision) instead of tuning it;
+ * a later fcs_retune tunes again.  Synchronizes the stream; the step graphs
+ * are captured anew at the next advance.  FCS_EINVAL for an index out of
+ * range, FCS_ESTATE before fcs_bind. */
+fcs_status fcs_set_stage_variant(fcs_ctx* ctx, int32_t index);
+
 /* Average duration (ms) of the dominant derivative-contraction launch (the
  * stage contraction of stages 2 to 5 of each step; the first stage's launch
  * also carries the viscosity gradient) over the advance calls since the last
  * reset, measured with HIP events on the bound stream, and the algorithmic
- * flops and bytes of one such launch.
+ * flops and bytes of one such launch, averaged over the same launches: the
+ * lines each step needed (viscous lines skipped in a step, see
+ * visc_all_lines, are not counted; before any profiled step, all lines).
+ * Profiling synchronizes the stream after every step.
  * Timing is recorded only after fcs_profile_enable(ctx, 1).  Whole steps
  * then replay a separate graph that carries event-record nodes around each
  * stage contraction and one empty pair of event nodes; *event_latency_ms
@@ -195,6 +219,16 @@ fcs_status fcs_autotune_times(const fcs_ctx* ctx, int32_t n, double* ms);
  * event pair adds to each measured interval.  Without a stream or graphs
  * the events are recorded eagerly and *event_latency_ms is 0. */
 fcs_status fcs_profile_enable(fcs_ctx* ctx, int32_t on);
+/* The stage contraction of the last step, timed alone: `reps` launches back
+ * to back on the bound stream between two HIP events (after one untimed
+ * launch), on the current state with the tiles the last step's viscosity
+ * needed; *avg_ms is the average per launch, *flops and *bytes (nullable)
+ * the useful work of one launch, as for fcs_profile_read.  The launches
+ * overwrite the stage derivatives only, which every stage recomputes before
+ * reading them, so the solution is not changed.  Synchronizes the stream.
+ * FCS_EINVAL for reps <= 0 or a NULL avg_ms; FCS_ESTATE before the first
+ * advance. */
+fcs_status fcs_profile_stage(fcs_ctx* ctx, int32_t reps, double* avg_ms, double* flops, double* bytes);
 fcs_status fcs_profile_read(fcs_ctx* ctx, double* avg_ms, double* flops_per_launch,
                             double* bytes_per_launch, int64_t* launches, double* event_latency_ms);
 

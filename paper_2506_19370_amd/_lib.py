@@ -45,7 +45,7 @@ class Params(ctypes.Structure):
         ("dt_fixed", ctypes.c_double),
         ("fc_d", ctypes.c_int32), ("fc_C", ctypes.c_int32), ("n_f", ctypes.c_int32), ("n_v", ctypes.c_int32),
         ("precision", ctypes.c_int32), ("av_mode", ctypes.c_int32), ("filter", ctypes.c_int32),
-        ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
+        ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("visc_all_lines", ctypes.c_int32),
         ("sdnn_weights", ctypes.POINTER(ctypes.c_float)),
         ("vortex", ctypes.c_double * 5),
     ]
@@ -89,6 +89,9 @@ fcs_advance = _sig("fcs_advance", _i, [vp, _i64, ctypes.POINTER(_d)])
 fcs_get_field = _sig("fcs_get_field", _i, [vp, _i, _i, vp, _i])
 fcs_stats = _sig("fcs_stats", _i, [vp, ctypes.POINTER(Stats)])
 fcs_autotune_times = _sig("fcs_autotune_times", _i, [vp, _i, ctypes.POINTER(_d)])
+fcs_retune = _sig("fcs_retune", _i, [vp])
+fcs_set_stage_variant = _sig("fcs_set_stage_variant", _i, [vp, _i])
+fcs_profile_stage = _sig("fcs_profile_stage", _i, [vp, _i, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d)])
 fcs_profile_enable = _sig("fcs_profile_enable", _i, [vp, _i])
 fcs_profile_read = _sig("fcs_profile_read", _i, [vp, ctypes.POINTER(_d), ctypes.POINTER(_d), ctypes.POINTER(_d),
                                                  ctypes.POINTER(_i64), ctypes.POINTER(_d)])
@@ -118,7 +121,7 @@ fcs_lines_apply = _sig("fcs_lines_apply", _i, [_i, _i64, _i, _i, _i, vp, vp, vp,
 
 EXPORTED = [
     "fcs_version", "fcs_create", "fcs_workspace_size", "fcs_bind", "fcs_set_state", "fcs_set_time",
-    "fcs_set_tau", "fcs_advance", "fcs_get_field", "fcs_stats", "fcs_autotune_times", "fcs_profile_enable", "fcs_profile_read",
+    "fcs_set_tau", "fcs_advance", "fcs_get_field", "fcs_stats", "fcs_autotune_times", "fcs_retune", "fcs_set_stage_variant", "fcs_profile_stage", "fcs_profile_enable", "fcs_profile_read",
     "fcs_last_error", "fcs_destroy", "fcs_fc_continuation", "fcs_fc_operator", "fcs_sweep_create",
     "fcs_sweep_workspace_size", "fcs_sweep_bind", "fcs_sweep_run", "fcs_sweep_profile", "fcs_sweep_points",
     "fcs_sweep_destroy", "fcs_sweep_autotune", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",

@@ -35,6 +35,7 @@ class SolverParams:
     filter: bool = False
     use_graph: bool = False
     autotune: bool = False
+    visc_all_lines: bool = False
     sdnn_weights: np.ndarray | None = None
     vortex: tuple = (5.0, 5.0, 5.0, 1.0, 1.0)
 
@@ -52,6 +53,7 @@ def create_context(specs, prm: SolverParams) -> ctypes.c_void_p:
     cp.filter = int(bool(prm.filter))
     cp.use_graph = int(bool(prm.use_graph))
     cp.autotune = int(bool(prm.autotune))
+    cp.visc_all_lines = int(bool(prm.visc_all_lines))
     if prm.sdnn_weights is not None:
         w = np.ascontiguousarray(prm.sdnn_weights, dtype=np.float32)
         if w.size != L.SDNN_NPARAM:
@@ -151,8 +153,29 @@ class Solver:
         L.check(L.fcs_autotune_times(self.h, n, ms), self.h)
         return list(ms)
 
+    def set_stage_variant(self, name: str):
+        """Pin the stage-contraction tile shape (a name from
+        gemm_variant_name for the solver's precision) instead of tuning it."""
+        n = L.fcs_gemm_variant_count(L.PREC[self.prm.precision])
+        names = [L.gemm_variant_name(self.prm.precision, i) for i in range(n)]
+        if name not in names:
+            raise ValueError(f"unknown stage variant {name!r}; candidates: {names}")
+        L.check(L.fcs_set_stage_variant(self.h, names.index(name)), self.h)
+
+    def retune(self):
+        """Tune the contraction tile shape again at the next advance, on the
+        current state's work (fcs_retune)."""
+        L.check(L.fcs_retune(self.h), self.h)
+
     def profile(self, on: bool):
         L.check(L.fcs_profile_enable(self.h, int(on)), self.h)
+
+    def profile_stage(self, reps: int = 50):
+        """The last step's stage contraction timed alone: average ms of
+        `reps` back-to-back launches and the useful flops and bytes of one."""
+        ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        L.check(L.fcs_profile_stage(self.h, int(reps), ctypes.byref(ms), ctypes.byref(fl), ctypes.byref(by)), self.h)
+        return {"avg_ms": ms.value, "flops": fl.value, "bytes": by.value, "launches": int(reps)}
 
     def profile_read(self):
         ms, fl, by, n, lat = ctypes.c_double(), ctypes.c_double(), ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()

@@ -61,6 +61,7 @@ struct TaskSpec {
   int src_arr, dst_arr;  // array ids
   int64_t src_off, dst_off;
   int32_t row_stride, s_stride, nrow, ncomp, n, op;
+  int32_t act = -1;  // activity entry of row 0 (skippable viscous task), else -1
 };
 
 enum ArrayId { A_U0, A_UA, A_UB, A_F, A_DF1, A_DF2, A_W1, A_W2, A_W11, A_W22, A_W12, A_MU, A_MU1, A_MU2, A_IN, A_NARR };
@@ -103,6 +104,12 @@ struct fcs_ctx {
   std::vector<double> metric_host[10];  // t1x t1y t2x t2y g11 g12 g22 lap1 lap2 hx
   std::vector<double> basis, wdil;
   std::vector<uint8_t> tau_host;
+  // activity flags (one per row and column of the lattice subpatches whose
+  // viscous derivatives are skipped in a step where mu vanishes along the
+  // line), and the flags of each blend row's point
+  int32_t nact = 0;
+  std::vector<int2> bact;
+  std::vector<uint8_t> act_host;
 
   // device
   char* ws = nullptr;
@@ -137,6 +144,9 @@ struct fcs_ctx {
   size_t ev_used = 0;
   double prof_ms = 0.0, prof_ovh_ms = 0.0;
   int64_t prof_n = 0, prof_ovh_n = 0;
+  // useful flops and bytes of the timed launches (lines actually needed)
+  double prof_flops = 0.0, prof_bytes = 0.0;
+  int64_t prof_fn = 0;
 
   // graphs: [0] step without filter, [1] with; the profiled copies carry
   // external event-record nodes around each stage contraction
@@ -192,8 +202,9 @@ size_t first_active(const Grid& g) {
 }
 
 // Tasks for all lines of one grid along one direction, grouped by runs.
+// span: activity entry of each line (skippable viscous tasks), else null.
 void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int src_arr, int src_comp0,
-                    int dst_arr, int dst_comp0, int ncomp) {
+                    int dst_arr, int dst_comp0, int ncomp, const int32_t* span = nullptr) {
   const int nl = dir == 0 ? g.n2 : g.n1;
   const std::vector<Run>& runs = dir == 0 ? g.rows : g.cols;
   int l = 0;
@@ -217,6 +228,7 @@ void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int 
     t.ncomp = ncomp;
     t.n = runs[l].len;
     t.op = op_id(c, runs[l].len, kind);
+    t.act = span ? span[l] : -1;
     c->phase_tasks[ph].push_back(t);
     l = l1;
   }
@@ -225,11 +237,13 @@ void add_line_tasks(fcs_ctx* c, Phase ph, const Grid& g, int dir, int kind, int 
 void build_tiles(fcs_ctx* c, int ph) {
   const auto& tasks = c->phase_tasks[ph];
   std::vector<int32_t> n(tasks.size()), nl(tasks.size());
+  std::vector<uint8_t> late(tasks.size());
   for (size_t q = 0; q < tasks.size(); ++q) {
     n[q] = tasks[q].n;
     nl[q] = tasks[q].nrow * tasks[q].ncomp;
+    late[q] = tasks[q].act >= 0;  // skippable viscous lines
   }
-  gemm_build_tiles(c->var[ph], n.data(), nl.data(), tasks.size(), c->phase_tiles[ph]);
+  gemm_build_tiles(c->var[ph], n.data(), nl.data(), tasks.size(), c->phase_tiles[ph], late.data());
 }
 
 double exact_flops(const std::vector<TaskSpec>& tasks) {
@@ -246,7 +260,7 @@ fcs_status upload(fcs_ctx* c, const char* name, const void* src, size_t bytes) {
 
 }  // namespace
 
-extern "C" int fcs_version(void) { return 100; }
+extern "C" int fcs_version(void) { return 101; }
 
 extern "C" const char* fcs_last_error(const fcs_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
 
@@ -335,6 +349,8 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     pd.row_run = rr;
     pd.col_run = cr;
     pd.affine = g.affine;
+    pd.act_row = -1;
+    pd.act_col = -1;
     if (g.affine) {
       const size_t k0 = first_active(g);
       pd.t1x = g.t1x[k0];
@@ -476,10 +492,30 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_F, 0, A_DF2, 0, 8);
     }
     if (c->visc) {
-      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_IN, 0, A_W1, 0, 4);
-      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D2, A_IN, 0, A_W11, 0, 4);
-      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_IN, 0, A_W2, 0, 4);
-      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D2, A_IN, 0, A_W22, 0, 4);
+      // Lattice subpatch (constant metric, g^12 = 0): the derivatives along
+      // a row meet only mu and d mu / dq^1 of that row, which vanish exactly
+      // where mu vanishes on the whole row (columns likewise), so its lines
+      // get activity entries and are skipped in steps where mu is zero on them.
+      // (Subpatches with an empty row or column keep every line.)
+      std::vector<int32_t> rspan, cspan;
+      const int32_t *rs = nullptr, *cs = nullptr;
+      bool full = true;
+      for (const Run& r : g.rows) full = full && r.len > 0;
+      for (const Run& r : g.cols) full = full && r.len > 0;
+      if (g.affine && c->pdev[q].g12 == 0.0 && full && !p.visc_all_lines) {
+        PatchDev& pd = c->pdev[q];
+        pd.act_row = c->nact;
+        pd.act_col = c->nact + g.n2;
+        c->nact += g.n2 + g.n1;
+        for (int l = 0; l < g.n2; ++l) rspan.push_back(pd.act_row + l);
+        for (int l = 0; l < g.n1; ++l) cspan.push_back(pd.act_col + l);
+        rs = rspan.data();
+        cs = cspan.data();
+      }
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D1, A_IN, 0, A_W1, 0, 4, rs);
+      add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D2, A_IN, 0, A_W11, 0, 4, rs);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_IN, 0, A_W2, 0, 4, cs);
+      add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D2, A_IN, 0, A_W22, 0, 4, cs);
       if (c->cross) add_line_tasks(c.get(), PH_CROSS, g, 1, FCS_OP_D1, A_W1, 0, A_W12, 0, 4);
       add_line_tasks(c.get(), PH_MUGRAD, g, 0, FCS_OP_D1, A_MU, 0, A_MU1, 0, 1);
       add_line_tasks(c.get(), PH_MUGRAD, g, 1, FCS_OP_D1, A_MU, 0, A_MU2, 0, 1);
@@ -489,6 +525,13 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_FILT2, g, 1, FCS_OP_FILTER, A_DF1, 0, A_DF2, 0, 4);
     }
   }
+  // activity flags of the row and the column of each blend row's point
+  if (c->nact)
+    for (int64_t k : c->bdst) {
+      const PatchDev& pd = c->pdev[c->pid[k]];
+      const int32_t j = c->ij[k] >> 16, i = c->ij[k] & 0xFFFF;
+      c->bact.push_back(pd.act_row >= 0 ? make_int2(pd.act_row + j, pd.act_col + i) : make_int2(-1, -1));
+    }
   c->deriv_f32 = p.precision != FCS_PREC_FP64 && !c->cross;
   if (c->visc) {
     c->phase_tasks[PH_EULER0] = c->phase_tasks[PH_EULER];
@@ -524,6 +567,8 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     o["PS"] = cv.take(2 * P * D);  // proxy and wave speed, interleaved
     o["TAU"] = cv.take(2 * P);
     o["WGEO"] = cv.take(P * 16);  // window geometry of every point (int4)
+    o["LACT"] = cv.take(c->nact);
+    o["BACT"] = cv.take(c->bact.size() * sizeof(int2));
   }
   for (int m = 0; m < 10; ++m) o["MET" + std::to_string(m)] = cv.take(P * D);
   o["FLAGS"] = cv.take(P);
@@ -644,6 +689,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       dt.clear();
       for (const TaskSpec& s : c->phase_tasks[ph]) {
         GemmTask t{};
+        t.act = s.act;
         double* sbase = s.src_arr == A_IN ? c->arr[A_U0 + v] : c->arr[s.src_arr];
         t.src = sbase + s.src_off;
         const bool f32 = c->deriv_f32 && (ph == PH_EULER || ph == PH_EULER0) && s.dst_arr != A_MU1 &&
@@ -702,6 +748,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"SDNN", c->sdnn.data(), c->sdnn.size() * 4},
       {"BASIS", c->basis.data(), c->basis.size() * 8},
       {"WDIL", c->wdil.data(), c->wdil.size() * 8},
+      {"BACT", c->bact.data(), c->bact.size() * sizeof(int2)},
   };
   for (auto& u : ups)
     if ((st = upload(c, u.n, u.p, u.b)) != FCS_OK) return st;
@@ -809,6 +856,8 @@ ViscArgs visc_args(fcs_ctx* c) {
   v.bptr = c->dptr<int32_t>("BPTR");
   v.bcol = c->dptr<int64_t>("BCOL");
   v.bval = c->dptr<double>("BVAL");
+  v.act = c->nact ? c->dptr<uint8_t>("LACT") : nullptr;
+  v.bact = c->nact ? c->dptr<int2>("BACT") : nullptr;
   v.wgeo = c->dptr<int4>("WGEO");
   return v;
 }
@@ -851,6 +900,13 @@ fcs_status per_step(fcs_ctx* c) {
   }
   if (c->visc) {
     HIPCHK(c, launch_viscosity(v, c->stream));
+    // which viscous contraction tiles this step needs (mu is frozen for it;
+    // the viscosity kernels have left the line activity flags)
+    if (c->nact)
+      HIPCHK(c, launch_tile_activity(c->d_tasks[PH_EULER][0], c->d_tiles[PH_EULER],
+                                     static_cast<int>(c->phase_tiles[PH_EULER].size()), c->d_tasks[PH_EULER0][0],
+                                     c->d_tiles[PH_EULER0], static_cast<int>(c->phase_tiles[PH_EULER0].size()),
+                                     v.act, c->stream));
   }
   if (fork) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
   return FCS_OK;  // the step size is taken by the first stage (one_stage)
@@ -977,6 +1033,43 @@ fcs_status full_step_eager(fcs_ctx* c) {
   return FCS_OK;
 }
 
+// Useful flops and bytes of one stage contraction of the last step (a
+// viscous line counts only if that step needed it).  Synchronizes.
+fcs_status stage_work(fcs_ctx* c, double* flops, double* bytes) {
+  if (c->nact) {
+    c->act_host.resize(c->nact);
+    HIPCHK(c, hipMemcpyAsync(c->act_host.data(), c->dptr<uint8_t>("LACT"), c->nact, hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
+  double f = 0, b = 0;
+  for (const TaskSpec& t : c->phase_tasks[PH_EULER]) {
+    double lines = static_cast<double>(t.nrow) * t.ncomp;
+    if (t.act >= 0) {
+      int live = 0;
+      for (int r = 0; r < t.nrow; ++r) live += c->act_host[t.act + r] != 0;
+      lines = static_cast<double>(live) * t.ncomp;
+    }
+    f += 2.0 * t.n * t.n * lines;
+    b += 2.0 * 8.0 * t.n * lines;  // each operand line read once, each output written once (FP64)
+  }
+  *flops = f;
+  *bytes = b;
+  return FCS_OK;
+}
+
+// Profile mode: accumulates the useful work of `launches` stage contractions
+// of the step just run.
+fcs_status prof_account(fcs_ctx* c, int launches) {
+  double f = 0, b = 0;
+  fcs_status st = stage_work(c, &f, &b);
+  if (st != FCS_OK) return st;
+  c->prof_flops += launches * f;
+  c->prof_bytes += launches * b;
+  c->prof_fn += launches;
+  return FCS_OK;
+}
+
 fcs_status check_bad(fcs_ctx* c) {
   int bad = 0;
   HIPCHK(c, hipMemcpyAsync(&bad, c->dptr<double>("SCAL") + 3, 4, hipMemcpyDeviceToHost, c->stream));
@@ -1098,12 +1191,26 @@ namespace {
 
 // Autotuner of the contraction tile shape: times every candidate variant on
 // the stage contraction (current state, stage-0 operands) with HIP events
-// and keeps the fastest for the stage and cross-derivative launches.
+// and keeps the fastest for the stage and cross-derivative launches.  With
+// skippable viscous lines the candidates run on the tiles the current
+// state's viscosity needs, as a step from this state would.
 fcs_status autotune(fcs_ctx* c) {
+  constexpr int kTuneReps = 10;  // timed launches per candidate
   c->tuned = true;
   if (!c->prm.autotune || c->phase_tiles[PH_EULER].empty()) return FCS_OK;
   int nv = 0;
   const GemmVariant* cand = gemm_variants(c->prm.precision, &nv);
+  std::fill(std::begin(c->tune_ms), std::end(c->tune_ms), 0.0f);
+  uint8_t* act = nullptr;
+  if (c->visc && c->nact) {
+    // the viscosity of the current state and its line activity (recomputed
+    // by the next step)
+    const ViscArgs v = visc_args(c);
+    if (!c->ps_valid) HIPCHK(c, launch_proxy(v, c->stream));
+    c->ps_valid = true;
+    HIPCHK(c, launch_viscosity(v, c->stream));
+    act = v.act;
+  }
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
@@ -1116,21 +1223,30 @@ fcs_status autotune(fcs_ctx* c) {
     fcs_status st = upload(c, "TILE0", c->phase_tiles[PH_EULER].data(),
                            c->phase_tiles[PH_EULER].size() * sizeof(GemmTile));
     if (st != FCS_OK) return st;
+    if (act)
+      HIPCHK(c, launch_tile_activity(c->d_tasks[PH_EULER][0], c->d_tiles[PH_EULER],
+                                     static_cast<int>(c->phase_tiles[PH_EULER].size()), nullptr, nullptr, 0, act,
+                                     c->stream));
     if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
     HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < 5; ++r)
+    for (int r = 0; r < kTuneReps; ++r)
       if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
     HIPCHK(c, hipEventRecord(e1, c->stream));
     HIPCHK(c, hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    c->tune_ms[q] = ms / 5;
-    if (ms < best) {
-      best = ms;
+    c->tune_ms[q] = ms / kTuneReps;
+  }
+  // the earliest candidate within 2 % of the fastest: near-ties (within the
+  // timing noise) resolve the same way from run to run
+  for (int q = 0; q < nv; ++q)
+    if (c->tune_ms[q] > 0 && c->tune_ms[q] < best) best = c->tune_ms[q];
+  for (int q = 0; q < nv; ++q)
+    if (c->tune_ms[q] > 0 && c->tune_ms[q] <= 1.02f * best) {
       bestv = cand[q];
       c->stage_variant = q;
+      break;
     }
-  }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
   for (int ph : {PH_EULER, PH_CROSS, PH_EULER0}) {
@@ -1176,9 +1292,11 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
           HIPCHK(c, hipEventElapsedTime(&ms, c->pev[wf][10], c->pev[wf][11]));
           c->prof_ovh_ms += ms;
           c->prof_ovh_n++;
+          if ((st = prof_account(c, 4)) != FCS_OK) return st;
         }
       } else {
         if ((st = full_step_eager(c)) != FCS_OK) return st;
+        if (c->prof && (st = prof_account(c, 4)) != FCS_OK) return st;
       }
       c->steps++;
       c->stages += 5;
@@ -1188,6 +1306,7 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
     if (c->stage_in_step == 0)
       if ((st = per_step(c)) != FCS_OK) return st;
     if ((st = one_stage(c, c->stage_in_step)) != FCS_OK) return st;
+    if (c->prof && c->stage_in_step > 0 && (st = prof_account(c, 1)) != FCS_OK) return st;
     c->stages++;
     n_stages--;
     if (++c->stage_in_step == 5) {
@@ -1281,6 +1400,74 @@ extern "C" fcs_status fcs_stats(fcs_ctx* c, fcs_stats_t* out) {
   return check_bad(c);
 }
 
+extern "C" fcs_status fcs_profile_stage(fcs_ctx* c, int32_t reps, double* avg_ms, double* flops, double* bytes) {
+  if (!c || reps <= 0 || !avg_ms) return FCS_EINVAL;
+  if (!c->bound || !c->tuned) return c->fail(FCS_ESTATE, "fcs_profile_stage before the first advance");
+  fcs_status st;
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  // one launch to warm up, then reps back to back between two events
+  if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
+  HIPCHK(c, hipEventRecord(e0, c->stream));
+  for (int r = 0; r < reps; ++r)
+    if ((st = run_gemm(c, PH_EULER, 0, c->prm.precision, false)) != FCS_OK) return st;
+  HIPCHK(c, hipEventRecord(e1, c->stream));
+  HIPCHK(c, hipEventSynchronize(e1));
+  float ms = 0;
+  HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  *avg_ms = ms / reps;
+  double f = 0, b = 0;
+  if ((st = stage_work(c, &f, &b)) != FCS_OK) return st;
+  if (flops) *flops = f;
+  if (bytes) *bytes = b;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_set_stage_variant(fcs_ctx* c, int32_t index) {
+  if (!c) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_set_stage_variant before fcs_bind");
+  int nv = 0;
+  const GemmVariant* cand = gemm_variants(c->prm.precision, &nv);
+  if (index < 0 || index >= nv) return c->fail(FCS_EINVAL, "stage variant index out of range");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto* g : {c->gexec, c->pgexec})
+    for (int k = 0; k < 2; ++k)
+      if (g[k]) {
+        HIPCHK(c, hipGraphExecDestroy(g[k]));
+        g[k] = nullptr;
+      }
+  for (int ph : {PH_EULER, PH_CROSS, PH_EULER0}) {
+    c->var[ph] = cand[index];
+    build_tiles(c, ph);
+    if (c->phase_tiles[ph].empty()) continue;
+    if (c->phase_tiles[ph].size() > c->tile_cap[ph]) return c->fail(FCS_EINVAL, "tile list exceeds its capacity");
+    std::string name = "TILE" + std::to_string(ph);
+    fcs_status st = upload(c, name.c_str(), c->phase_tiles[ph].data(), c->phase_tiles[ph].size() * sizeof(GemmTile));
+    if (st != FCS_OK) return st;
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->stage_variant = index;
+  c->tuned = true;
+  return FCS_OK;
+}
+
+extern "C" fcs_status fcs_retune(fcs_ctx* c) {
+  if (!c) return FCS_EINVAL;
+  if (!c->bound) return c->fail(FCS_ESTATE, "fcs_retune before fcs_bind");
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  for (auto* g : {c->gexec, c->pgexec})
+    for (int k = 0; k < 2; ++k)
+      if (g[k]) {
+        HIPCHK(c, hipGraphExecDestroy(g[k]));
+        g[k] = nullptr;
+      }
+  c->tuned = false;
+  return FCS_OK;
+}
+
 extern "C" fcs_status fcs_profile_enable(fcs_ctx* c, int32_t on) {
   if (!c) return FCS_EINVAL;
   if (on && c->ev.empty()) {
@@ -1293,6 +1480,9 @@ extern "C" fcs_status fcs_profile_enable(fcs_ctx* c, int32_t on) {
   c->prof_n = 0;
   c->prof_ovh_ms = 0;
   c->prof_ovh_n = 0;
+  c->prof_flops = 0;
+  c->prof_bytes = 0;
+  c->prof_fn = 0;
   return FCS_OK;
 }
 
@@ -1308,12 +1498,14 @@ extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops
   }
   c->ev_used = 0;
   if (avg_ms) *avg_ms = c->prof_n ? c->prof_ms / c->prof_n : 0.0;
-  if (flops) *flops = exact_flops(c->phase_tasks[PH_EULER]);
+  // useful work per timed launch: the lines each step needed (all lines
+  // before any profiled step)
+  if (flops) *flops = c->prof_fn ? c->prof_flops / c->prof_fn : exact_flops(c->phase_tasks[PH_EULER]);
   if (bytes) {
     // algorithmic bytes: each operand line read once, each output written once (FP64)
     double b = 0;
     for (const auto& t : c->phase_tasks[PH_EULER]) b += 2.0 * 8.0 * t.n * static_cast<double>(t.nrow) * t.ncomp;
-    *bytes = b;
+    *bytes = c->prof_fn ? c->prof_bytes / c->prof_fn : b;
   }
   if (launches) *launches = c->prof_n;
   if (event_latency_ms) *event_latency_ms = c->prof_ovh_n ? c->prof_ovh_ms / c->prof_ovh_n : 0.0;

@@ -62,8 +62,10 @@ hipError_t launch_gemm_step(const GemmTask* tasks, const GemmTile* tiles, int nt
 int gemm_lines_per_tile();
 int gemm_outputs_per_tile(const GemmVariant& v);
 // Tiles of one task set (operator sizes n, lines nrow * ncomp per task).
+// late (or null): tasks whose tiles a launch may skip; they are placed after
+// the other tiles of each XCD queue.
 void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nlines, size_t ntasks,
-                      std::vector<GemmTile>& tiles);
+                      std::vector<GemmTile>& tiles, const uint8_t* late = nullptr);
 // Candidate variants for the autotuner.
 const GemmVariant* gemm_variants(int precision, int* count);
 }  // namespace fcs

@@ -59,6 +59,11 @@ __device__ __forceinline__ gdouble* gdst64(void* p) { return (gdouble*)p; }
 __device__ __forceinline__ gfloat* gdst32(void* p) { return (gfloat*)p; }
 
 // Element offset of position 0 of a line (row fastest numbering).
+// A tile with nothing to compute: padding of an XCD-ordered list, or a tile
+// none of whose lines is needed in this step (the skip flag is uniform over
+// the workgroup, so the whole workgroup leaves together).
+__device__ __forceinline__ bool tile_idle(const GemmTile& t) { return t.task < 0 || t.skip != 0; }
+
 __device__ __forceinline__ int64_t line_base(const GemmTask& T, int line) {
   const int c = line / T.nrow, r = line - c * T.nrow;
   return static_cast<int64_t>(c) * T.comp_stride + static_cast<int64_t>(r) * T.row_stride;
@@ -454,7 +459,7 @@ template <typename Elem, int KC, int TB>
 __global__ __launch_bounds__(256, sizeof(Elem) == 8 ? 2 : 1) void k_gemm_xs(const GemmTask* __restrict__ tasks,
                                                  const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   gemm_xs<Elem, KC, TB>(tasks, tile, ops);
 }
 
@@ -573,7 +578,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw(const GemmTask* __restrict__ ta
                                                  OpTables ops) {
   __shared__ SmemXw<Elem, SLAB> sm;
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
     gemm_xw_dir<Elem, SLAB, TB, true>(T, tile, ops, sm);
@@ -699,7 +704,7 @@ __global__ __launch_bounds__(256) void k_gemm_xw_bf16x3(const GemmTask* __restri
                                                         const GemmTile* __restrict__ tiles, OpTables ops) {
   __shared__ SmemXwBf<SLAB> sm;
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
     gemm_xw_bf16x3_dir<SLAB, TB, true>(T, tile, ops, sm);
@@ -739,17 +744,18 @@ __device__ __forceinline__ void xcd_queue_tiles(int ntiles, int* ctr, Body body)
 
 // Stage contractions (every SSPRK stage) ...
 // Launch bounds: the second argument asks for that many waves per SIMD, which
-// bounds the registers per lane (no spills at these shapes).
+// bounds the registers per lane.
 // MINB workgroups per CU (the launch bound caps the registers at 512 /
 // MINB per lane): 8-column FP64 chunks (19 KB of LDS) let seven share a CU,
-// enough for the step-channel stage task set in one round; the two-chunk
-// prefetch of 16-column FP64 chunks needs the registers of three.
+// enough for the whole step-channel stage task set in one round (that form
+// spills 24 bytes per lane; the others do not); the two-chunk prefetch of
+// 16-column FP64 chunks needs the registers of three.
 // PF: chunks whose loads are in flight while a chunk is on the matrix cores.
 template <typename Elem, int KC, int TB, int MINB, int PF>
 __global__ __launch_bounds__(256, MINB) void k_gemm_fp(const GemmTask* __restrict__ tasks,
                                                     const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   gemm_fp<Elem, KC, TB, PF>(tasks, tile, ops);
 }
 
@@ -759,7 +765,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm_fp_persist(const GemmTask* __re
                                                          OpTables ops, int* ctr) {
   xcd_queue_tiles(ntiles, ctr, [&](int t) {
     const GemmTile tile = tiles[t];
-    if (tile.task >= 0) gemm_fp<Elem, KC, TB>(tasks, tile, ops);
+    if (!tile_idle(tile)) gemm_fp<Elem, KC, TB>(tasks, tile, ops);
   });
 }
 
@@ -768,7 +774,7 @@ __global__ __launch_bounds__(256, 4) void k_gemm_fp_persist(const GemmTask* __re
 __global__ __launch_bounds__(256, 4) void k_gemm_step(const GemmTask* __restrict__ tasks,
                                                    const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   gemm_fp<double, 16, 1>(tasks, tile, ops);
 }
 
@@ -930,7 +936,7 @@ template <int TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict__ tasks,
                                                      const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile.task < 0) return;  // padding tile of the XCD-ordered list
+  if (tile_idle(tile)) return;
   gemm_bf16x3<TB>(tasks, tile, ops);
 }
 
@@ -940,7 +946,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x3_persist(const GemmTask* __r
                                                              OpTables ops, int* ctr) {
   xcd_queue_tiles(ntiles, ctr, [&](int t) {
     const GemmTile tile = tiles[t];
-    if (tile.task >= 0) gemm_bf16x3<TB>(tasks, tile, ops);
+    if (!tile_idle(tile)) gemm_bf16x3<TB>(tasks, tile, ops);
   });
 }
 
@@ -1155,7 +1161,7 @@ const GemmVariant* gemm_variants(int precision, int* count) {
 }
 
 void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nlines, size_t ntasks,
-                      std::vector<GemmTile>& tiles) {
+                      std::vector<GemmTile>& tiles, const uint8_t* late) {
   tiles.clear();
   const int step = gemm_outputs_per_tile(v);
   // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
@@ -1171,15 +1177,21 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
   // so every CU receives a mix of long and short tiles and the short ones
   // fill the last round.  Longer queues keep each task's tiles together,
   // which keeps its operator rows and operand lines in L2 while they run.
+  // Tasks marked late (tiles that a launch may skip) are balanced over the
+  // queues on their own and follow all other tiles of their queue, so the
+  // tiles that always run are dispatched first and spread evenly over the
+  // CUs whatever the skipped set.
   constexpr int kXcd = 8;
   constexpr int kCusPerXcd = 32;
-  std::vector<std::vector<GemmTile>> queue(kXcd);
-  std::vector<double> load(kXcd, 0.0);
-  // tasks go to the least-loaded queue (heaviest first when the queues will
-  // be sorted, in task order otherwise); each queue keeps its tasks in task
-  // order
+  std::vector<std::vector<GemmTile>> queue[2] = {std::vector<std::vector<GemmTile>>(kXcd),
+                                                 std::vector<std::vector<GemmTile>>(kXcd)};
+  std::vector<double> load[2] = {std::vector<double>(kXcd, 0.0), std::vector<double>(kXcd, 0.0)};
+  // tasks go to the least-loaded queue of their class (heaviest first when
+  // the queues will be sorted, in task order otherwise); each queue keeps
+  // its tasks in task order
   constexpr size_t kSortedQueue = 2 * 8 * kCusPerXcd;
   auto task_load = [&](size_t q) { return static_cast<double>((nlines[q] + kLB - 1) / kLB) * n[q] * n[q]; };
+  auto cls = [&](size_t q) { return late && late[q] ? 1 : 0; };
   size_t total = 0;
   for (size_t q = 0; q < ntasks; ++q)
     total += static_cast<size_t>((nlines[q] + kLB - 1) / kLB) * ((n[q] + step - 1) / step);
@@ -1189,30 +1201,40 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
     std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) { return task_load(a) > task_load(b); });
   std::vector<int> task_queue(ntasks, 0);
   for (size_t q : order) {
-    const int x = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+    std::vector<double>& ld = load[cls(q)];
+    const int x = static_cast<int>(std::min_element(ld.begin(), ld.end()) - ld.begin());
     task_queue[q] = x;
-    load[x] += task_load(q);
+    ld[x] += task_load(q);
   }
   for (size_t q = 0; q < ntasks; ++q) {
     const int nblk = (nlines[q] + kLB - 1) / kLB;
     for (int b = 0; b < nblk; ++b)
-      for (int t0 = 0; t0 < n[q]; t0 += step) queue[task_queue[q]].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
+      for (int t0 = 0; t0 < n[q]; t0 += step)
+        queue[cls(q)][task_queue[q]].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
   }
   auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
-  for (auto& qx : queue)
-    if (v.persist || qx.size() <= kSortedQueue) {
-      std::stable_sort(qx.begin(), qx.end(), [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
-      // snake order: every other band of one tile per CU reversed, so that
-      // the CU that receives a band's largest tile receives the next band's
-      // smallest
-      if (!v.persist)
-        for (size_t b0 = kCusPerXcd; b0 < qx.size(); b0 += 2 * kCusPerXcd)
-          std::reverse(qx.begin() + b0, qx.begin() + std::min(qx.size(), b0 + kCusPerXcd));
-    }
   size_t len = 0;
-  for (const auto& qx : queue) len = std::max(len, qx.size());
+  std::vector<std::vector<GemmTile>> merged(kXcd);
+  for (int x = 0; x < kXcd; ++x) {
+    const size_t qlen = queue[0][x].size() + queue[1][x].size();
+    for (auto& part : queue) {
+      std::vector<GemmTile>& qx = part[x];
+      if (v.persist || qlen <= kSortedQueue) {
+        std::stable_sort(qx.begin(), qx.end(),
+                         [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
+        // snake order: every other band of one tile per CU reversed, so that
+        // the CU that receives a band's largest tile receives the next
+        // band's smallest
+        if (!v.persist)
+          for (size_t b0 = kCusPerXcd; b0 < qx.size(); b0 += 2 * kCusPerXcd)
+            std::reverse(qx.begin() + b0, qx.begin() + std::min(qx.size(), b0 + kCusPerXcd));
+      }
+      merged[x].insert(merged[x].end(), qx.begin(), qx.end());
+    }
+    len = std::max(len, merged[x].size());
+  }
   for (size_t r = 0; r < len; ++r)
-    for (int x = 0; x < kXcd; ++x) tiles.push_back(r < queue[x].size() ? queue[x][r] : GemmTile{-1, 0, 0, 0});
+    for (int x = 0; x < kXcd; ++x) tiles.push_back(r < merged[x].size() ? merged[x][r] : GemmTile{-1, 0, 0, 0});
 }
 
 }  // namespace fcs

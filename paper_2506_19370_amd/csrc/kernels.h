@@ -20,12 +20,17 @@ struct GemmTask {
   int32_t n;        // line length = operator size
   int32_t op;       // operator index (into the operator tables)
   int32_t out_f32;  // results stored as FP32 (mixed-precision stage derivatives)
-  int32_t pad;
+  // Viscous derivatives on a lattice subpatch: entry of row 0 in the
+  // per-line activity flags (row r at act + r); -1 for tasks always computed.
+  int32_t act;
 };
 
+// skip: nonzero when none of the tile's lines is needed in the current step
+// (written on the device from the line activity flags; 0 from the host).
 struct GemmTile {
-  int32_t task, line0, t0, pad;
+  int32_t task, line0, t0, skip;
 };
+
 
 // Operator tables: FP64, FP32 and split BF16 copies of every dense operator
 // (zero-padded, row-major with leading dimension ld[k]), and FP64 row sums
@@ -47,6 +52,9 @@ struct PatchDev {
   int32_t row_run;  // index of row 0 in the run tables
   int32_t col_run;  // index of column 0
   int32_t affine;
+  // lattice subpatch with skippable viscous lines: activity flag of row j at
+  // act_row + j and of column i at act_col + i; -1 otherwise
+  int32_t act_row, act_col;
   int32_t pad;
   // affine subpatches: the metric terms, the same at every active point
   // (q^k_x, q^k_y and g^{kl}; the Laplacian terms of the index coordinates

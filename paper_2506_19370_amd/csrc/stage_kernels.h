@@ -97,8 +97,17 @@ struct ViscArgs {
   const int32_t* bptr;
   const int64_t* bcol;
   const double* bval;
+  // (or null) line activity flags of lattice subpatches, one per row and
+  // column: 1 where the final mu is nonzero somewhere on the line; bact:
+  // the flags of the row and the column of each blend row's point
+  uint8_t* act;
+  const int2* bact;
 };
 
+// Skip flags of the tiles of two contraction task lists from the line
+// activity flags that the viscosity kernels leave (see ViscArgs::act).
+hipError_t launch_tile_activity(const GemmTask* tasks0, GemmTile* tiles0, int n0, const GemmTask* tasks1,
+                                GemmTile* tiles1, int n1, const uint8_t* act, hipStream_t s);
 hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo, int64_t P, hipStream_t s);
 // Stage update, boundary conditions and (if a.flux.F) the fluxes of the new
 // state at every active point.

@@ -142,8 +142,11 @@ __global__ void k_stage(StageArgs a) {
       L[q] = -(t1x * static_cast<double>(DF1[q * P + ks]) + t1y * static_cast<double>(DF1[(4 + q) * P + ks]) +
                t2x * static_cast<double>(DF2[q * P + ks]) + t2y * static_cast<double>(DF2[(4 + q) * P + ks]));
   }
-  if (a.visc) {
-    double mu = a.mu[ks], mu1 = a.mu1[ks], mu2 = a.mu2[ks];
+  const double mu = a.visc ? a.mu[ks] : 0.0, mu1 = a.visc ? a.mu1[ks] : 0.0, mu2 = a.visc ? a.mu2[ks] : 0.0;
+  // Where mu and both of its derivatives vanish the viscous term is an exact
+  // zero: the derivatives of w there are not read (on skipped lines they
+  // may be those of an earlier step).
+  if (mu != 0.0 || mu1 != 0.0 || mu2 != 0.0) {
     double g11, g12, g22, l1, l2;
     if (f & kAffine) {
       // constant metrics of the subpatch; the index coordinates are harmonic
@@ -404,12 +407,18 @@ __global__ __launch_bounds__(256) void k_sdnn_pack(const float* __restrict__ W, 
 __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out, const int32_t* __restrict__ pid,
                          const int32_t* __restrict__ ijs, const PatchDev* __restrict__ patches,
                          const uint8_t* __restrict__ flags, int64_t P, int dir, int nv, const double* __restrict__ w,
-                         double* __restrict__ mu) {
+                         double* __restrict__ mu, uint8_t* __restrict__ act) {
   int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   if (k >= P) return;
   const PatchDev pd = patches[pid[k]];
   const int32_t ij = ijs[k];
   const int j = ij >> 16, i = ij & 0xFFFF;
+  // line activity flags of lattice subpatches: cleared by the first pass (the
+  // thread of each row's and column's first index), set by the final pass
+  if (act && !mu && pd.act_row >= 0) {
+    if (i == 0) act[pd.act_row + j] = 0;
+    if (j == 0) act[pd.act_col + i] = 0;
+  }
   const int pos = dir == 0 ? i : j, len = dir == 0 ? pd.n1 : pd.n2;
   const int64_t stride = dir == 0 ? 1 : pd.n1;
   double best = 0.0;
@@ -436,19 +445,33 @@ __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out
     // overwrite the points covered by several subpatches
     if (!(flags[k] & kActive)) best = 0.0;
     mu[k] = fmax(best, 0.0);
+    if (act && pd.act_row >= 0 && best > 0.0) {
+      act[pd.act_row + j] = 1;
+      act[pd.act_col + i] = 1;
+    }
   }
   out[k] = best;
 }
 
 
+// bact (or null): activity flags of the row and the column of each blended
+// point (x < 0: not on a lattice subpatch with activity flags).
 __global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu, const int64_t* __restrict__ dst,
                              const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
-                             const double* __restrict__ val, int n) {
+                             const double* __restrict__ val, int n, const int2* __restrict__ bact,
+                             uint8_t* __restrict__ act) {
   int q = blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
   double s = 0.0;
   for (int e = ptr[q]; e < ptr[q + 1]; ++e) s += val[e] * mut[col[e]];
   mu[dst[q]] = fmax(s, 0.0);
+  if (act && s > 0.0) {
+    const int2 a = bact[q];
+    if (a.x >= 0) {
+      act[a.x] = 1;
+      act[a.y] = 1;
+    }
+  }
 }
 
 __global__ void k_filter_pre(const double* __restrict__ U, double* __restrict__ Q, const uint8_t* __restrict__ flags,
@@ -623,12 +646,56 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   else
     hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
-                     0, v.nv, v.wdil, nullptr);
+                     0, v.nv, v.wdil, nullptr, v.act);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.ij, v.patches, v.flags, v.P,
-                     1, v.nv, v.wdil, v.mu);
+                     1, v.nv, v.wdil, v.mu, v.act);
   if (v.nblend)
     hipLaunchKernelGGL(k_blend_rows, grid_for(v.nblend), dim3(256), 0, s, v.mut, v.mu, v.bdst, v.bptr, v.bcol,
-                       v.bval, v.nblend);
+                       v.bval, v.nblend, v.bact, v.act);
+  return hipGetLastError();
+}
+
+// Localized viscosity (Sec. 4): the viscous derivatives of a line are only
+// needed where mu or its gradient is nonzero.  On a lattice subpatch
+// (constant diagonal metric) the derivatives along a row enter the operator
+// only through mu and d mu / dq^1 on that row, and both vanish identically
+// when mu vanishes at every point of the row (the FC derivative of a zero
+// line is an exact zero); columns likewise.  The dilation and blend kernels
+// leave act[line] = 1 for the lines where mu is nonzero somewhere.  One wave
+// per contraction tile: the tile is skipped when none of its lines
+// (line = component * nrow + row) lies on an active grid line; tiles of
+// tasks without activity entries are always computed.  The two tile lists
+// (n0 + n1 tiles) are marked in one launch.
+__global__ __launch_bounds__(256) void k_tile_activity(const GemmTask* __restrict__ tasks0, GemmTile* tiles0, int n0,
+                                                        const GemmTask* __restrict__ tasks1, GemmTile* tiles1, int n1,
+                                                        const uint8_t* __restrict__ act) {
+  int t = blockIdx.x * 4 + static_cast<int>(threadIdx.x >> 6);
+  const int lane = threadIdx.x & 63;
+  if (t >= n0 + n1) return;
+  const GemmTask* tasks = tasks0;
+  GemmTile* tiles = tiles0;
+  if (t >= n0) {
+    t -= n0;
+    tasks = tasks1;
+    tiles = tiles1;
+  }
+  const GemmTile tile = tiles[t];
+  if (tile.task < 0) return;
+  const GemmTask T = tasks[tile.task];
+  bool need = true;
+  if (T.act >= 0) {
+    const int line = tile.line0 + lane;
+    need = line < T.nrow * T.ncomp && act[T.act + line % T.nrow] != 0;
+  }
+  const bool any = __ballot(need) != 0;
+  if (lane == 0) tiles[t].skip = any ? 0 : 1;
+}
+
+hipError_t launch_tile_activity(const GemmTask* tasks0, GemmTile* tiles0, int n0, const GemmTask* tasks1,
+                                GemmTile* tiles1, int n1, const uint8_t* act, hipStream_t s) {
+  if (n0 + n1 <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_activity, dim3((n0 + n1 + 3) / 4), dim3(256), 0, s, tasks0, tiles0, n0, tasks1, tiles1,
+                     n1, act);
   return hipGetLastError();
 }
 
