@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--stage-variant", default=None,
                     help="pin the FP64 stage-contraction tile shape (a kernel name as reported in roofline.kernel) "
                          "instead of tuning it (for counter runs, whose dispatch serialization skews the tuner)")
+    ap.add_argument("--no-tiled", action="store_true",
+                    help="skip the tiled step channel at 1.17e7 points (FP64 and split-BF16, 500 steps)")
+    ap.add_argument("--tiled-steps", type=int, default=500)
     ap.add_argument("--cpu-steps", type=int, default=3)
     return ap.parse_args()
 
@@ -147,8 +150,8 @@ def classifier_bench(F, W, torch, weights):
     return out
 
 
-def make_solver(F, W, torch, weights, precision, stream, use_graph=True):
-    specs = W.step_channel()
+def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=None):
+    specs = W.step_channel() if specs is None else specs
     prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=use_graph,
                          precision=precision, sdnn_weights=weights, autotune=True)
     with torch.cuda.stream(stream):
@@ -206,6 +209,37 @@ def contraction_profile(S, torch, nsteps=20, reps=50):
     S.profile(False)
     alone = S.profile_stage(reps)
     return alone, graph
+
+
+def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
+    """The step channel tiled by 235 subpatches of uneven sizes (sides drawn
+    from 150-300; 1.17e7 points, C1 and C2 corner patches): FP64 and
+    split-BF16 runs of the same steps from the uniform inflow state, their
+    throughput and the per-field difference of the split-BF16 state from the
+    FP64 one after the run."""
+    specs = W.step_channel_tiled()
+    npts = int(sum(s.npoints() for s in specs))
+    out = {"workload": "Mach-3 step channel tiled by %d subpatches of sides 150-300 (seeded), %d points, "
+                       "SDNN viscosity, filter, CFL 0.5, FC-Gram d=2 C=27" % (len(specs), npts),
+           "points": npts, "subpatches": len(specs), "steps": steps, "warmup": warmup}
+    solvers = {}
+    for prec in ("fp64", "bf16x3"):
+        stream = torch.cuda.Stream()
+        t0 = time.perf_counter()
+        S, _ = make_solver(F, W, torch, weights, prec, stream, specs=specs)
+        setup = time.perf_counter() - t0
+        el = timed_run(S, torch, stream, steps, warmup)
+        from paper_2506_19370_amd import _lib as L
+        out[prec] = {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "ms_per_step": el / steps * 1e3,
+                     "stage_kernel": L.gemm_variant_name(prec, S.stats()["stage_variant"]),
+                     "host_setup_s": setup}
+        solvers[prec] = S
+    out["bf16x3"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["bf16x3"]["ms_per_step"]
+    out["bf16x3"]["error_vs_fp64_after_%d_steps" % (steps + warmup)] = field_errors(solvers["fp64"],
+                                                                                     solvers["bf16x3"], specs)
+    del solvers
+    torch.cuda.synchronize()
+    return out
 
 
 def cpu_baseline(W, steps):
@@ -297,6 +331,9 @@ def main():
     if not a.no_extras:
         out["derivative_sweep"] = sweep_bench(F, W, torch)
         out["classifier"] = classifier_bench(F, W, torch, weights)
+    if not a.no_tiled:
+        del S
+        out["tiled_channel"] = tiled_channel_run(F, W, torch, weights, a.tiled_steps)
     if not a.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(W, a.cpu_steps)
     if a.calibration_copy:

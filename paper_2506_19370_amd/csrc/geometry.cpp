@@ -447,11 +447,30 @@ bool build_grid(Grid& g, int d, int C, int n_f, std::string& err) {
   return true;
 }
 
+// The subpatches whose bounding box (widened by the tolerance of
+// bbox_candidate) meets that of subpatch p, in ascending order: the only
+// ones that can pass bbox_candidate for a point of p.
+static std::vector<size_t> box_neighbours(const std::vector<Grid>& grids, size_t p) {
+  std::vector<size_t> out;
+  const Grid& gp = grids[p];
+  for (size_t s = 0; s < grids.size(); ++s) {
+    if (s == p) continue;
+    const Grid& gs = grids[s];
+    const double tol = 1e-9 * std::max({gs.bb[1] - gs.bb[0], gs.bb[3] - gs.bb[2], 1.0});
+    if (gp.bb[1] < gs.bb[0] - tol || gp.bb[0] > gs.bb[1] + tol || gp.bb[3] < gs.bb[2] - tol ||
+        gp.bb[2] > gs.bb[3] + tol)
+      continue;
+    out.push_back(s);
+  }
+  return out;
+}
+
 bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& rows, std::string& err) {
   rows.clear();
   std::vector<Entry> ent;
   for (size_t p = 0; p < grids.size(); ++p) {
     const Grid& gp = grids[p];
+    const std::vector<size_t> nb = box_neighbours(grids, p);
     for (int j = 0; j < gp.n2; ++j)
       for (int i = 0; i < gp.n1; ++i) {
         size_t k = gp.at(j, i);
@@ -460,8 +479,7 @@ bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& r
         double best = -kInf;
         int bs = -1;
         std::vector<Entry> bent;
-        for (size_t s = 0; s < grids.size(); ++s) {
-          if (s == p) continue;
+        for (size_t s : nb) {
           const Grid& gs = grids[s];
           if (!bbox_candidate(gs, px, py)) continue;
           double xi, eta;
@@ -509,14 +527,14 @@ void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<Inter
   std::vector<Contrib> lst;
   for (size_t p = 0; p < grids.size(); ++p) {
     const Grid& gp = grids[p];
+    const std::vector<size_t> nb = box_neighbours(grids, p);
     for (int j = 0; j < gp.n2; ++j)
       for (int i = 0; i < gp.n1; ++i) {
         size_t k = gp.at(j, i);
         if (!gp.mask[k]) continue;
         double px = gp.x[k], py = gp.y[k];
         lst.clear();
-        for (size_t s = 0; s < grids.size(); ++s) {
-          if (s == p) continue;
+        for (size_t s : nb) {
           const Grid& gs = grids[s];
           if (!bbox_candidate(gs, px, py)) continue;
           double xi, eta;

@@ -257,6 +257,64 @@ def test_step_channel_modal_viscosity(filt):
     assert _rel(S, O, specs) < 1e-11
 
 
+def test_tiled_step_channel_modal_viscosity():
+    """The step channel tiled by 73 subpatches of uneven sizes (seeded; the
+    decomposition of the full-size tiled configuration at h = 1/200): T
+    junctions, a C1 and a C2 corner patch.  Modal viscosity and filter, FP64
+    on both sides: classes equal, viscosity and state to FP64 rounding."""
+    specs = W.step_channel_tiled(200, 36, 72, 16)
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True)
+    S = F.Solver(specs, prm)
+    w = _jump_state(specs)
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+    O = osolver.Solver(osolver.patches_from_specs(specs), osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal",
+                                                                         filter=True))
+    O.set_prim(w)
+    for step in range(2):
+        S.advance(5, sync=True)
+        O.step()
+        for p in range(len(specs)):
+            assert np.array_equal(S.field(p, "tau0"), O.last_tau[p][0]), (step, p)
+            assert np.array_equal(S.field(p, "tau1"), O.last_tau[p][1]), (step, p)
+            mref = O.field(O.mu[0], p)
+            assert np.abs(S.field(p, "mu") - mref).max() <= 1e-12 * max(1e-300, np.abs(O.mu[0]).max())
+    assert _rel(S, O, specs) < 1e-11
+
+
+def test_tiled_step_channel_full_size():
+    """The full-size tiled channel (235 subpatches, 1.17e7 points, sides
+    150-300): graph replay equals eager launches bit for bit, the state stays
+    finite and physical, and one split-BF16 step differs from the FP64 step
+    from the same state by less than the split-BF16 contraction bound (1e-4
+    of max|U|).  Error model as for the frozen-class mixed test: the bound
+    reaches the state as dt/h (about 0.12 at CFL 0.5) x 2 directions x 1 step
+    x max|F| / max|U| (about 1.5), i.e. about 0.4 x the bound; the modal
+    classes of the step are those of the common initial state."""
+    specs = W.step_channel_tiled()
+    assert len(specs) == 235 and sum(s.npoints() for s in specs) == 11666791
+    w = _jump_state(specs)
+    res = {}
+    for name, prec, graph in (("graph", "fp64", True), ("eager", "fp64", False), ("bf16x3", "bf16x3", True)):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, use_graph=graph,
+                                               precision=prec), stream=stream)
+            for p in range(len(specs)):
+                S.set_state(p, w[p])
+            S.advance(5, sync=True)
+            res[name] = [S.cons(p) for p in range(len(specs))]
+            if name == "graph":
+                S.advance(10, sync=True)  # raises if the state turns non-finite or non-physical
+            del S
+        torch.cuda.synchronize()
+    for p in range(len(specs)):
+        assert np.array_equal(res["graph"][p], res["eager"][p]), p
+    scale = max(np.abs(r).max() for r in res["graph"])
+    err = max(np.abs(a - b).max() for a, b in zip(res["bf16x3"], res["graph"])) / scale
+    assert err < 1e-4, err
+
+
 def _sector():
     spec = W.annular_sector(48, 40)[0]
     spec.sides = {k: W.OUTFLOW for k in "WESN"}

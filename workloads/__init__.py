@@ -245,6 +245,64 @@ def step_channel(h_index=250):
     return pts
 
 
+def _split(lo, hi, cmin, cmax, g):
+    """Cut points lo = c_0 < ... < c_k = hi: k pieces of lengths drawn
+    uniformly in [cmin, cmax], rescaled to fill [lo, hi] exactly."""
+    span = hi - lo
+    k = max(1, int(round(span / (0.5 * (cmin + cmax)))))
+    w = g.uniform(cmin, cmax, k)
+    c = lo + np.rint(np.cumsum(w) / w.sum() * span).astype(int)
+    return [lo] + [int(v) for v in c]
+
+
+def step_channel_tiled(h_index=2000, smin=150, smax=300, corner=140, config_index=5, seed_salt=0):
+    """The Mach-3 step channel ([0, 3] x [0, 1], step [0.6, 3] x [0, 0.2]) on
+    one lattice of spacing 1 / h_index, tiled by subpatches of uneven sizes:
+    core extents are drawn (seeded) so that a subpatch side, with the
+    17-point overlaps on its internal sides, lies in [smin, smax].  Columns of
+    cores in front of the step; a corner column of width 2 corner around
+    x = 0.6 with a C2 patch at the foot of the step face, an L-shaped C1
+    patch around the step corner and cores above it; columns of cores over
+    the step.  Side kinds: inflow at x = 0, outflow at x = 3, slip walls on
+    y = 0, y = 1, the step face and the step top."""
+    assert h_index % 5 == 0
+    g = rng(config_index, seed_salt)
+    h = 1.0 / h_index
+    XS, YS, XE, YT = 3 * h_index // 5, h_index // 5, 3 * h_index, h_index
+    a, e = corner, 8
+    assert 2 * e < YS - a and a + 2 * e < YS
+    cmin, cmax = smin - 2 * e - 1, smax - 2 * e - 1
+    pts = []
+
+    def add(x0, x1, y0, y1, W, E, S, N, kind=None, notch=None):
+        X0, X1 = x0 - (e if W == INTERNAL else 0), x1 + (e if E == INTERNAL else 0)
+        Y0, Y1 = y0 - (e if S == INTERNAL else 0), y1 + (e if N == INTERNAL else 0)
+        if kind is None:
+            kind = "I" if (W, E, S, N) == (INTERNAL,) * 4 else "S"
+        pts.append(lattice_patch(h, X0, X1, Y0, Y1, {"W": W, "E": E, "S": S, "N": N}, kind, STEP_INFLOW, notch))
+
+    def column(x0, x1, ylo, yhi, wall_below):
+        ys = _split(ylo, yhi, cmin, cmax, g)
+        for r in range(len(ys) - 1):
+            add(x0, x1, ys[r], ys[r + 1], INFLOW if x0 == 0 else INTERNAL, OUTFLOW if x1 == XE else INTERNAL,
+                SLIP if (r == 0 and wall_below) else INTERNAL, SLIP if ys[r + 1] == YT else INTERNAL)
+
+    # in front of the step
+    xs = _split(0, XS - a, cmin, cmax, g)
+    for c in range(len(xs) - 1):
+        column(xs[c], xs[c + 1], 0, YT, True)
+    # corner column: C2 at the foot of the step face, C1 around the step corner, cores above
+    add(XS - a, XS, 0, YS - a, INTERNAL, SLIP, SLIP, INTERNAL, "C2")
+    add(XS - a, XS + a, YS - a, YS + a, INTERNAL, INTERNAL, INTERNAL, INTERNAL, "C1",
+        notch=(XS + 1, XS + a + e, YS - a - e, YS - 1))
+    column(XS - a, XS + a, YS + a, YT, False)
+    # over the step
+    xs = _split(XS + a, XE, cmin, cmax, g)
+    for c in range(len(xs) - 1):
+        column(xs[c], xs[c + 1], YS, YT, True)
+    return pts
+
+
 def uniform_state(patch_list, prim):
     return [np.broadcast_to(np.asarray(prim, dtype=float)[:, None, None], (4,) + p.shape).copy()
             for p in patch_list]
