@@ -39,8 +39,10 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 # for its kernel after the same number of steps and warm-up steps, and for
 # the kernels as they were when the counters were taken.
 STAGE_TRAFFIC_FP64 = {
-    # profiles/stage_contraction_fp64_traffic.md: fetched 28.63 MB + written 25.37 MB
-    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 53.99e6,
+    # profiles/stage_contraction_fp64_traffic.md (fetched + written MB)
+    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 53.99e6,  # 28.63 + 25.37
+    ("k_gemm_fp<double, 16, 1, 4, 1>", 2000, 20): 53.82e6,  # 28.59 + 25.23
+    ("k_gemm_fp<double, 16, 1, 3, 2>", 2000, 20): 54.67e6,  # 29.63 + 25.04
 }
 HBM_PEAK = 8.0e12
 
@@ -63,7 +65,7 @@ def parse():
     ap.add_argument("--no-tiled", action="store_true",
                     help="skip the tiled step channel at 1.17e7 points (FP64 and split-BF16, 500 steps)")
     ap.add_argument("--tiled-steps", type=int, default=500)
-    ap.add_argument("--cpu-steps", type=int, default=3)
+    ap.add_argument("--cpu-steps", type=int, default=10)
     return ap.parse_args()
 
 
