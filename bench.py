@@ -40,9 +40,9 @@ PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
 # the kernels as they were when the counters were taken.
 STAGE_TRAFFIC_FP64 = {
     # profiles/stage_contraction_fp64_traffic.md (fetched + written MB)
-    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 53.99e6,  # 28.63 + 25.37
-    ("k_gemm_fp<double, 16, 1, 4, 1>", 2000, 20): 53.82e6,  # 28.59 + 25.23
-    ("k_gemm_fp<double, 16, 1, 3, 2>", 2000, 20): 54.67e6,  # 29.63 + 25.04
+    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 52.25e6,  # 28.58 + 23.67
+    ("k_gemm_fp<double, 16, 1, 4, 1>", 2000, 20): 52.08e6,  # 28.55 + 23.53
+    ("k_gemm_fp<double, 16, 1, 3, 2>", 2000, 20): 52.91e6,  # 29.55 + 23.36
 }
 HBM_PEAK = 8.0e12
 

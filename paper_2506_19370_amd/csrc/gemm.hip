@@ -60,9 +60,11 @@ __device__ __forceinline__ gfloat* gdst32(void* p) { return (gfloat*)p; }
 
 // Element offset of position 0 of a line (row fastest numbering).
 // A tile with nothing to compute: padding of an XCD-ordered list, or a tile
-// none of whose lines is needed in this step (the skip flag is uniform over
-// the workgroup, so the whole workgroup leaves together).
-__device__ __forceinline__ bool tile_idle(const GemmTile& t) { return t.task < 0 || t.skip != 0; }
+// none of whose lines is needed in this step (the skip flags are uniform
+// over the workgroup, so the whole workgroup leaves together).  A set bit w
+// alone (lines 16 w .. 16 w + 15 not needed) lets the staged kernels' wave w
+// take the path of a wave past the task's end: no products, no stores.
+__device__ __forceinline__ bool tile_idle(const GemmTile& t) { return t.task < 0 || (t.skip & 15) == 15; }
 
 __device__ __forceinline__ int64_t line_base(const GemmTask& T, int line) {
   const int c = line / T.nrow, r = line - c * T.nrow;
@@ -241,7 +243,7 @@ __device__ __forceinline__ void gemm_fp_dir(const GemmTask& T, const GemmTile ti
   // task's end); the same count on every wave of a full line tile.  The
   // chunk loop is instantiated per count, so the accumulators keep static
   // registers; every instantiation takes part in the same loads and barriers.
-  const int nb = 16 * wave < nl ? (nt + 15) >> 4 : 0;
+  const int nb = 16 * wave < nl && !((tile.skip >> wave) & 1) ? (nt + 15) >> 4 : 0;
   const int nk = (n + KC - 1) / KC;
   // With two chunks in flight every load is issued unconditionally (chunk
   // indices past the end clamped to the last chunk, inside the padded
@@ -862,7 +864,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   // tile; blocks past the line end are skipped by all waves alike (the chunk
   // loop is instantiated per count of live blocks, as in the FP64/FP32
   // kernel).
-  const int nb = 16 * wave < nl ? (nt + 15) >> 4 : 0;
+  const int nb = 16 * wave < nl && !((tile.skip >> wave) & 1) ? (nt + 15) >> 4 : 0;
   const double* rowsum = ops.rowsum + ops.roff[T.op];
   with_live<4 * TB>(nb, [&](auto live) {
     constexpr int NL = decltype(live)::value;

@@ -25,7 +25,8 @@ struct GemmTask {
   int32_t act;
 };
 
-// skip: nonzero when none of the tile's lines is needed in the current step
+// skip: bit w set when none of the tile's lines 16 w .. 16 w + 15 is needed
+// in the current step; all four bits: the tile is not needed at all
 // (written on the device from the line activity flags; 0 from the host).
 struct GemmTile {
   int32_t task, line0, t0, skip;

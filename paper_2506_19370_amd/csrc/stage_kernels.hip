@@ -662,9 +662,11 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
 // when mu vanishes at every point of the row (the FC derivative of a zero
 // line is an exact zero); columns likewise.  The dilation and blend kernels
 // leave act[line] = 1 for the lines where mu is nonzero somewhere.  One wave
-// per contraction tile: the tile is skipped when none of its lines
-// (line = component * nrow + row) lies on an active grid line; tiles of
-// tasks without activity entries are always computed.  The two tile lists
+// per contraction tile: bit w of its skip flag is set when none of the
+// tile's lines 16 w .. 16 w + 15 (line = component * nrow + row) lies on an
+// active grid line (the contraction wave that owns them then neither
+// multiplies nor stores); all four bits skip the tile.  Tiles of tasks
+// without activity entries are always computed.  The two tile lists
 // (n0 + n1 tiles) are marked in one launch.
 __global__ __launch_bounds__(256) void k_tile_activity(const GemmTask* __restrict__ tasks0, GemmTile* tiles0, int n0,
                                                         const GemmTask* __restrict__ tasks1, GemmTile* tiles1, int n1,
@@ -687,8 +689,11 @@ __global__ __launch_bounds__(256) void k_tile_activity(const GemmTask* __restric
     const int line = tile.line0 + lane;
     need = line < T.nrow * T.ncomp && act[T.act + line % T.nrow] != 0;
   }
-  const bool any = __ballot(need) != 0;
-  if (lane == 0) tiles[t].skip = any ? 0 : 1;
+  const uint64_t m = __ballot(need);
+  int skip = 0;
+  for (int w = 0; w < 4; ++w)
+    if (!((m >> (16 * w)) & 0xFFFFull)) skip |= 1 << w;
+  if (lane == 0) tiles[t].skip = skip;
 }
 
 hipError_t launch_tile_activity(const GemmTask* tasks0, GemmTile* tiles0, int n0, const GemmTask* tasks1,
