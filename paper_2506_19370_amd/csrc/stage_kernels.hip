@@ -373,9 +373,12 @@ __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
       }
       sp = fmax(sp, __shfl_xor(sp, 16));
       sp = fmax(sp, __shfl_xor(sp, 32));
-      float x[4], z[3];
+      float x[4], z[3] = {0.0f, 0.0f, 0.0f};
       const bool live = sdnn_features(v, x);
-      sdnn_mfma(F, x, z);  // all 64 lanes take part
+      // a flat window is smooth without the network: a round of 16 flat
+      // windows skips it (the branch is uniform over the wave, and when taken
+      // all 64 lanes run the matrix instructions)
+      if (__ballot(live) != 0) sdnn_mfma(F, x, z);
       if (vc) {
         smax = fmax(smax, sp);
         tau[dir] = live ? sdnn_argmax(z) : 0;
