@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--no-tiled", action="store_true",
                     help="skip the tiled step channel at 1.17e7 points (FP64 and split-BF16, 500 steps)")
     ap.add_argument("--tiled-steps", type=int, default=500)
+    ap.add_argument("--tiled-only", action="store_true",
+                    help="run only the tiled step channel (for its kernel profile); prints its object alone")
     ap.add_argument("--cpu-steps", type=int, default=10)
     return ap.parse_args()
 
@@ -235,6 +237,14 @@ def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
         out[prec] = {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "ms_per_step": el / steps * 1e3,
                      "stage_kernel": L.gemm_variant_name(prec, S.stats()["stage_variant"]),
                      "host_setup_s": setup}
+        if prec == "fp64":
+            # the last step's stage contraction alone (useful flops of the
+            # lines that step needed), as for the roofline of the main run
+            pr = S.profile_stage(20)
+            ach = pr["flops"] / (pr["avg_ms"] * 1e-3)
+            out[prec]["stage_contraction"] = {"avg_launch_ms": pr["avg_ms"], "flops_per_launch": pr["flops"],
+                                              "achieved_tflops": ach / 1e12, "frac_of_fp64_peak": ach / PEAK["fp64"],
+                                              "algorithmic_bytes_per_launch": pr["bytes"]}
         solvers[prec] = S
     out["bf16x3"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["bf16x3"]["ms_per_step"]
     out["bf16x3"]["error_vs_fp64_after_%d_steps" % (steps + warmup)] = field_errors(solvers["fp64"],
@@ -273,6 +283,9 @@ def main():
     import workloads as W
 
     weights = train_classifier(F, W, torch)
+    if a.tiled_only:
+        print(json.dumps({"tiled_channel": tiled_channel_run(F, W, torch, weights, a.tiled_steps)}))
+        return
     stream = torch.cuda.Stream()
     S, specs = make_solver(F, W, torch, weights, "fp64", stream, use_graph=not a.eager)
     if a.stage_variant:
