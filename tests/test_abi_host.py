@@ -143,3 +143,22 @@ def test_sweep_create_validates_sizes():
     sz = np.array([[10, 1024]], dtype=np.int32)  # the smallest and largest sides for d = 5
     assert L.fcs_sweep_create(1, sz.ctypes.data, 4, 0, 5, 27, ctypes.byref(h)) == L.FCS_OK
     L.fcs_sweep_destroy(h)
+
+
+def test_tuning_and_profile_controls_need_a_bound_context():
+    """fcs_retune, fcs_set_stage_variant and fcs_profile_stage act on a bound
+    context; before fcs_bind they report FCS_ESTATE, and bad arguments
+    FCS_EINVAL, without touching the device."""
+    from paper_2506_19370_amd import _lib as L
+    h = _create(W.step_channel(), fc_d=2, fc_C=27, av="modal", filter=True)
+    try:
+        ms = ctypes.c_double()
+        assert L.fcs_retune(h) == L.FCS_ESTATE
+        assert L.fcs_set_stage_variant(h, 0) == L.FCS_ESTATE
+        assert L.fcs_profile_stage(h, 5, ctypes.byref(ms), None, None) == L.FCS_ESTATE
+        assert L.fcs_profile_stage(h, 0, ctypes.byref(ms), None, None) == L.FCS_EINVAL
+        assert L.fcs_profile_stage(h, 5, None, None, None) == L.FCS_EINVAL
+    finally:
+        L.fcs_destroy(h)
+    assert L.fcs_retune(None) == L.FCS_EINVAL
+    assert L.fcs_set_stage_variant(None, 0) == L.FCS_EINVAL

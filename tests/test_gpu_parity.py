@@ -452,6 +452,42 @@ def test_viscous_line_skip_is_exact():
     assert 0.2 * prof[1]["flops"] < prof[0]["flops"] < 0.9 * prof[1]["flops"], (prof[0]["flops"], prof[1]["flops"])
 
 
+def test_pinned_tile_shapes_and_retune():
+    """Two staged FP64 tile shapes accumulate every output in the same order
+    (MFMA steps of 4 columns, chunk after chunk), so pinning either gives the
+    same state bit for bit; re-tuning in the middle of a run changes the tile
+    shape only; unknown names are refused."""
+    from paper_2506_19370_amd import _lib as L
+    specs = W.step_channel()
+    w = _jump_state(specs)
+    out = []
+    for name in ("k_gemm_fp<double, 16, 1, 4, 1>", "k_gemm_fp<double, 8, 1, 4, 2>", None):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, use_graph=True,
+                                               autotune=name is None), stream=stream)
+            for p in range(len(specs)):
+                S.set_state(p, w[p])
+            if name is None:
+                S.advance(10, sync=True)
+                S.retune()
+                S.advance(20, sync=True)
+            else:
+                S.set_stage_variant(name)
+                assert L.gemm_variant_name("fp64", S.stats()["stage_variant"]) == name
+                S.advance(30, sync=True)
+                assert L.gemm_variant_name("fp64", S.stats()["stage_variant"]) == name
+            out.append([S.cons(p) for p in range(len(specs))])
+            if name is None:
+                with pytest.raises(ValueError):
+                    S.set_stage_variant("k_gemm_fp<double, 3, 3, 3, 3>")
+    for a, b in zip(out[0], out[1]):
+        assert np.array_equal(a, b)
+    # the tuned run may pick a shape with another reduction order: FP64 rounding
+    scale = max(np.abs(a).max() for a in out[0])
+    assert max(np.abs(a - b).max() for a, b in zip(out[0], out[2])) <= 1e-12 * scale
+
+
 def test_nonfinite_is_reported():
     specs = W.vortex_box(41)
     S = F.Solver(specs, F.SolverParams(fc_d=5, fc_C=27))
