@@ -226,6 +226,7 @@ def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
     out = {"workload": "Mach-3 step channel tiled by %d subpatches of sides 150-300 (seeded), %d points, "
                        "SDNN viscosity, filter, CFL 0.5, FC-Gram d=2 C=27" % (len(specs), npts),
            "points": npts, "subpatches": len(specs), "steps": steps, "warmup": warmup}
+    from paper_2506_19370_amd import _lib as L
     solvers = {}
     for prec in ("fp64", "bf16x3"):
         stream = torch.cuda.Stream()
@@ -233,7 +234,6 @@ def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
         S, _ = make_solver(F, W, torch, weights, prec, stream, specs=specs)
         setup = time.perf_counter() - t0
         el = timed_run(S, torch, stream, steps, warmup)
-        from paper_2506_19370_amd import _lib as L
         out[prec] = {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "ms_per_step": el / steps * 1e3,
                      "stage_kernel": L.gemm_variant_name(prec, S.stats()["stage_variant"]),
                      "host_setup_s": setup}
