@@ -275,7 +275,7 @@ def cpu_baseline(W, steps):
 def main():
     a = parse()
     if a.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
+        print(json.dumps({"error": "this library runs on one GPU; --gpus must be 1 (multi-GPU sharding is a design "
                                    "note, not an implemented path)"}))
         sys.exit(2)
     import torch
