@@ -158,9 +158,20 @@ fcs_status fcs_workspace_size(const fcs_ctx* ctx, size_t* bytes);
 fcs_status fcs_bind(fcs_ctx* ctx, void* workspace, size_t bytes, void* stream);
 
 /* Set the state of one subpatch from (4, n2, n1) conserved or primitive
- * values (host or device).  Stream-ordered. */
+ * values (host or device; vars = FCS_VARS_*); masked points are ignored.
+ * The copy is complete when the call returns (it synchronizes the bound
+ * stream).  Only at a step boundary: inside a partial step (after an
+ * fcs_advance whose stage count was not a multiple of 5) it fails with
+ * FCS_ESTATE and changes nothing.  Together with fcs_get_field and
+ * fcs_set_time it checkpoints and resumes a run (Alg. 1 output): a context
+ * given the conserved fields and the time of another at a step boundary
+ * continues it bit for bit (same parameters and contraction tile shape). */
 fcs_status fcs_set_state(fcs_ctx* ctx, int32_t patch, int32_t vars,
                          const double* src, int32_t src_on_device);
+/* Set the simulated time t (finite).  The filter of Alg. 4 applies to every
+ * step that starts at t > 0, so resuming at t > 0 filters the first step as
+ * the uninterrupted run does.  FCS_ESTATE inside a partial step; FCS_EINVAL
+ * for a non-finite t.  Synchronizes the bound stream. */
 fcs_status fcs_set_time(fcs_ctx* ctx, double t);
 
 /* Frozen smoothness classes (FCS_AV_FROZEN): (2, n2, n1) uint8 values of
@@ -306,6 +317,7 @@ fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int32_t t, flo
                                const float* x, const int32_t* labels, const float* class_weight,
                                int32_t batch, float* loss, float* grads, int32_t flags,
                                void* workspace, size_t bytes, void* stream);
+
 
 /* Apply a dense FC operator (FCS_OP_*) along lines: nlines lines of n
  * points, device in/out (nlines x n doubles), FP64.  workspace: device,

@@ -135,6 +135,9 @@ struct fcs_ctx {
   // time stepping
   int stage_in_step = 0;
   int64_t steps = 0, stages = 0;
+  // the solution is past t = 0 (a step completed, or fcs_set_time set t > 0):
+  // the filter of Alg. 4 applies from then on
+  bool past_t0 = false;
   double t_host = 0.0;
   double* cur = nullptr;  // buffer that holds the latest state
 
@@ -879,7 +882,7 @@ fcs_status per_step(fcs_ctx* c) {
   // Alg. 4 (filter) reads and rewrites the state, which after the proxy
   // kernel no part of Alg. 3 reads: with a second stream the two run side by
   // side and join before the step size is taken.
-  const bool filt = p.filter && c->steps > 0;
+  const bool filt = p.filter && c->past_t0;
   const bool fork = filt && c->visc && c->stream2 != nullptr;
   if (filt) {
     hipStream_t fs = c->stream;
@@ -930,7 +933,7 @@ fcs_status one_stage(fcs_ctx* c, int s) {
              c->dptr<PatchDev>("PATCH")};
   // after the filter (every step but the first) the filter's last kernel has
   // already stored the fluxes of the stage input
-  if (s == 0 && !(p.filter && c->steps > 0)) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
+  if (s == 0 && !(p.filter && c->past_t0)) HIPCHK(c, launch_flux(in, flags, fo, P, c->stream));
   // The step size (CFL and viscous limits) reads only the filtered state and
   // mu: it runs on the second stream beside the first stage's contraction
   // and joins before the stage update that uses it.
@@ -1085,6 +1088,9 @@ extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, con
   if (!c || !src) return FCS_EINVAL;
   if (!c->bound) return c->fail(FCS_ESTATE, "fcs_set_state before fcs_bind");
   if (patch < 0 || patch >= static_cast<int32_t>(c->grids.size())) return c->fail(FCS_EINVAL, "bad patch index");
+  // the state lives in U0 at step boundaries only
+  if (c->stage_in_step != 0) return c->fail(FCS_ESTATE, "fcs_set_state inside a step: advance to a step boundary first");
+  if (vars != FCS_VARS_CONS && vars != FCS_VARS_PRIM) return c->fail(FCS_EINVAL, "bad variable kind");
   c->ps_valid = false;
   const Grid& g = c->grids[patch];
   const size_t np = g.np();
@@ -1109,11 +1115,6 @@ extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, con
       for (int q = 0; q < 4; ++q) e[q * np + k] = h[q * np + k];
     }
   }
-  // the state lives in U0 at step boundaries; a partial step is dropped
-  if (c->stage_in_step != 0) {
-    HIPCHK(c, hipMemcpyAsync(c->arr[A_U0], c->cur, 4 * c->P * 8, hipMemcpyDeviceToDevice, c->stream));
-    c->stage_in_step = 0;
-  }
   for (int q = 0; q < 4; ++q)
     HIPCHK(c, hipMemcpyAsync(c->arr[A_U0] + q * c->P + g.offset, e.data() + q * np, np * 8, hipMemcpyHostToDevice,
                              c->stream));
@@ -1123,8 +1124,10 @@ extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, con
 }
 
 extern "C" fcs_status fcs_set_time(fcs_ctx* c, double t) {
-  if (!c) return FCS_EINVAL;
+  if (!c || !std::isfinite(t)) return FCS_EINVAL;
+  if (c->stage_in_step != 0) return c->fail(FCS_ESTATE, "fcs_set_time inside a step: advance to a step boundary first");
   c->t_host = t;
+  c->past_t0 = t != 0.0;
   if (c->bound) {
     HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL") + 4, &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
@@ -1158,8 +1161,8 @@ fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
     for (auto& e : c->pev[with_filter])
       if (!e) HIPCHK(c, hipEventCreate(&e));
   hipGraph_t graph;
-  int64_t saved = c->steps;
-  c->steps = with_filter ? 1 : 0;
+  const bool saved = c->past_t0;
+  c->past_t0 = with_filter != 0;
   bool saved_prof = c->prof;
   const bool saved_ps = c->ps_valid;
   c->prof = false;
@@ -1172,7 +1175,7 @@ fcs_status capture_step(fcs_ctx* c, int with_filter, bool profiled) {
     st = record_in_capture(c, c->pev[with_filter][11]);
   if (st == FCS_OK) st = full_step_eager(c);
   hipError_t e = hipStreamEndCapture(c->stream, &graph);
-  c->steps = saved;
+  c->past_t0 = saved;
   c->prof = saved_prof;
   c->capturing_prof = false;
   c->in_capture = false;
@@ -1272,7 +1275,7 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
   const bool graph = c->prm.use_graph && c->stream != nullptr;
   while (n_stages > 0) {
     if (c->stage_in_step == 0 && n_stages >= 5) {
-      int wf = (c->prm.filter && c->steps > 0) ? 1 : 0;
+      int wf = (c->prm.filter && c->past_t0) ? 1 : 0;
       if (graph) {
         if ((st = capture_step(c, wf, c->prof)) != FCS_OK) return st;
         if (c->visc && !c->ps_valid) HIPCHK(c, launch_proxy(visc_args(c), c->stream));
@@ -1299,6 +1302,7 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
         if (c->prof && (st = prof_account(c, 4)) != FCS_OK) return st;
       }
       c->steps++;
+      c->past_t0 = true;
       c->stages += 5;
       n_stages -= 5;
       continue;
@@ -1312,6 +1316,7 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
     if (++c->stage_in_step == 5) {
       c->stage_in_step = 0;
       c->steps++;
+      c->past_t0 = true;
     }
   }
   if (t_out) {

@@ -87,6 +87,31 @@ def vortex_multipatch(n=41):
     return out
 
 
+def vortex_curved_pair(n=61):
+    """Two overlapping curvilinear patches covering [0, 10]^2 for the vortex:
+    A maps q in [0, 6] x [0, 10], B maps q in [4, 10] x [0, 10] (spacing
+    0.93 of A's), each perturbed by a different smooth bump that vanishes on
+    the outer box edges, so the overlap's grid lines are curved and do not
+    coincide: the fringe is filled by interpolation with donors found by
+    Newton inversion of a curved mapping.  Outer sides carry exact vortex
+    data, the curved inner sides are internal."""
+    h = 10.0 / (n - 1)
+    out = []
+    for (qa, qb, hh, ax, ay, sx) in ((0.0, 6.0, h, 0.3, 0.2, 1.0), (4.0, 10.0, 0.93 * h, -0.25, -0.15, -1.0)):
+        n1 = int(round((qb - qa) / hh)) + 1
+        n2 = int(round(10.0 / hh)) + 1
+        q1 = np.linspace(qa, qb, n1)[None, :]
+        q2 = np.linspace(0.0, 10.0, n2)[:, None]
+        # bump: zero on the outer edge of the patch (x = 0 or x = 10) and on y = 0, 10
+        r = (q1 - qa) / (qb - qa) if sx > 0 else (qb - q1) / (qb - qa)
+        X = q1 + ax * np.sin(np.pi * q2 / 10.0) * r * r
+        Y = q2 + ay * np.sin(np.pi * (q1 - qa) / (qb - qa)) * np.sin(np.pi * q2 / 10.0) * r
+        sides = {k: EXACT for k in "WESN"}
+        sides["E" if sx > 0 else "W"] = INTERNAL
+        out.append(PatchSpec(X, Y, None, sides, SLIP, None, "I"))
+    return out
+
+
 def curved_patch(n1=48, n2=40, amp=0.05):
     """A curvilinear patch (sinusoidally perturbed unit square), for
     freestream-preservation checks."""
