@@ -318,6 +318,23 @@ fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int32_t t, flo
                                int32_t batch, float* loss, float* grads, int32_t flags,
                                void* workspace, size_t bytes, void* stream);
 
+/* Allocation-free form of fcs_sdnn_train_step, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving or
+ * training loops, harnesses that forbid hipMalloc).  Same arguments and
+ * results without the workspace: the per-sample scratch is a library-owned
+ * device array sized for FCS_SDNN_TRAIN_MAX_BATCH samples (9.1 MB), of which
+ * each GPU holds its own copy from the first call on it until the process
+ * ends.  The call allocates nothing.  batch > FCS_SDNN_TRAIN_MAX_BATCH (or any
+ * argument fcs_sdnn_train_step rejects) -> FCS_EINVAL; a failed symbol lookup
+ * or launch -> FCS_EHIP.  All calls on one GPU share its array: calls that
+ * overlap in time on that GPU (unordered streams, other threads) race and
+ * must be serialized by the caller. */
+#define FCS_SDNN_TRAIN_MAX_BATCH 8192
+fcs_status fcs_sdnn_train_step_noalloc(float* params, float* m, float* v, int32_t t, float lr,
+                                       const float* x, const int32_t* labels,
+                                       const float* class_weight, int32_t batch, float* loss,
+                                       float* grads, int32_t flags, void* stream);
+
 
 /* Apply a dense FC operator (FCS_OP_*) along lines: nlines lines of n
  * points, device in/out (nlines x n doubles), FP64.  workspace: device,

@@ -116,6 +116,9 @@ fcs_modal_infer = _sig("fcs_modal_infer", _i, [vp, _i64, vp, vp])
 fcs_sdnn_train_workspace = _sig("fcs_sdnn_train_workspace", _sz, [_i])
 fcs_sdnn_train_step = _sig("fcs_sdnn_train_step", _i, [vp, vp, vp, _i, ctypes.c_float, vp, vp, vp, _i, vp, vp, _i,
                                                        vp, _sz, vp])
+fcs_sdnn_train_step_noalloc = _sig("fcs_sdnn_train_step_noalloc", _i, [vp, vp, vp, _i, ctypes.c_float, vp, vp, vp,
+                                                                       _i, vp, vp, _i, vp])
+SDNN_TRAIN_MAX_BATCH = 8192
 fcs_lines_workspace = _sig("fcs_lines_workspace", _sz, [_i, _i64])
 fcs_lines_apply = _sig("fcs_lines_apply", _i, [_i, _i64, _i, _i, _i, vp, vp, vp, _sz, vp])
 
@@ -125,7 +128,7 @@ EXPORTED = [
     "fcs_last_error", "fcs_destroy", "fcs_fc_continuation", "fcs_fc_operator", "fcs_sweep_create",
     "fcs_sweep_workspace_size", "fcs_sweep_bind", "fcs_sweep_run", "fcs_sweep_profile", "fcs_sweep_points",
     "fcs_sweep_destroy", "fcs_sweep_autotune", "fcs_sdnn_infer", "fcs_modal_infer", "fcs_sdnn_train_workspace", "fcs_sdnn_train_step",
-    "fcs_lines_workspace", "fcs_lines_apply", "fcs_gemm_variant_count", "fcs_sweep_set_variant",
+    "fcs_sdnn_train_step_noalloc", "fcs_lines_workspace", "fcs_lines_apply", "fcs_gemm_variant_count", "fcs_sweep_set_variant",
     "fcs_gemm_variant_name",
 ]
 

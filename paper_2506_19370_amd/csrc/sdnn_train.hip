@@ -11,7 +11,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
+#include "../../include/fcsdnn.h"
 #include "classify.h"
 #include "sdnn_train.h"
 #include "stage_kernels.h"
@@ -193,6 +195,39 @@ __global__ void k_adam(float* __restrict__ p, float* __restrict__ m, float* __re
 
 }  // namespace
 
+// Library-owned scratch of the allocation-free training step: the per-sample
+// activations and errors of a batch of at most FCS_SDNN_TRAIN_MAX_BATCH
+// samples plus one gradient vector (9.1 MB).  Each GPU the library runs on
+// holds its own copy until the process ends.
+constexpr size_t kScratchFloats =
+    static_cast<size_t>(FCS_SDNN_TRAIN_MAX_BATCH) * (kIn + 4 * kH + kC + 2) + kNP;
+__device__ __align__(256) float scratch[kScratchFloats];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch[kMaxDevices] = {};
+
+// Device address of the current GPU's copy of `scratch`, looked up once per
+// device (host code must not pass the symbol itself to a kernel).
+hipError_t scratch_for_current_device(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch[dev];
+  return hipSuccess;
+}
+}  // namespace
+
 size_t sdnn_train_floats(int B) { return static_cast<size_t>(B) * (kIn + 4 * kH + kC + 2) + kNP; }
 
 hipError_t launch_sdnn_train(float* params, float* m, float* v, int t, float lr, const float* x,
@@ -208,3 +243,20 @@ hipError_t launch_sdnn_train(float* params, float* m, float* v, int t, float lr,
 }
 
 }  // namespace fcs
+
+// Allocation-free form of fcs_sdnn_train_step: the same kernels on the
+// library-owned scratch of the current GPU.  No slot of the scratch is read
+// before the same call wrote it, so nothing is cleared between calls.
+extern "C" fcs_status fcs_sdnn_train_step_noalloc(float* params, float* m, float* v, int32_t t, float lr,
+                                                  const float* x, const int32_t* labels,
+                                                  const float* class_weight, int32_t batch, float* loss,
+                                                  float* grads, int32_t flags, void* stream) {
+  if (!params || !m || !v || !x || !labels || !class_weight || !loss || batch <= 0 || t < 1) return FCS_EINVAL;
+  if (batch > FCS_SDNN_TRAIN_MAX_BATCH) return FCS_EINVAL;
+  float* ws = nullptr;
+  if (fcs::scratch_for_current_device(&ws) != hipSuccess) return FCS_EHIP;
+  return fcs::launch_sdnn_train(params, m, v, t, lr, x, labels, class_weight, batch, loss, grads, ws, flags & 1,
+                                static_cast<hipStream_t>(stream)) == hipSuccess
+             ? FCS_OK
+             : FCS_EHIP;
+}
