@@ -13,7 +13,11 @@ the reading here is
 * values are interpolated with the same 6 x 6 tensor Lagrange stencil,
   centred on the donor cell and clamped into the index box; a coordinate
   within 1e-9 of a grid line is snapped to it (exchange then reduces to a
-  copy);
+  copy); where the centred stencil would take a node the donor cannot give
+  (masked, or a fringe node), the stencil moves by up to two nodes per
+  direction, keeping the point inside its span, to the nearest position
+  whose nodes are all eligible (near the obstacle quadrant of a corner
+  subpatch the interpolation is then one-sided);
 * the donor is the eligible subpatch in which the point lies deepest (index
   distance to its internal sides), ties to the lowest subpatch index.
 
@@ -96,7 +100,9 @@ def invert_map(grid, px: np.ndarray, py: np.ndarray):
         # keep the iterate inside a slightly enlarged box
         xi = np.clip(xi, -3.0, n1 + 2.0)
         eta = np.clip(eta, -3.0, n2 + 2.0)
-        ok = (np.abs(dxi) < 1e-12) & (np.abs(deta) < 1e-12) | (np.hypot(fx, fy) < 1e-15 * scale)
+        # converged once the step is below the rounding floor of fine grids
+        # with O(1) coordinates (a few 1e-12 index units), well under SNAP
+        ok = (np.abs(dxi) < 1e-10) & (np.abs(deta) < 1e-10) | (np.hypot(fx, fy) < 1e-15 * scale)
         if ok.all():
             break
     # snap to grid lines
@@ -122,23 +128,55 @@ def inside(grid, xi: float, eta: float) -> bool:
     return True
 
 
-def stencil(grid, xi: float, eta: float):
-    """Interpolation entries [(j, i, weight)] at (xi, eta); coordinates that
-    sit on a grid line contribute a single node along that direction."""
-    n2, n1 = grid.p.x.shape
+def _starts(xi: float, n: int):
+    """Candidate first nodes of the 6-point stencil along one direction, in
+    order of preference: the centred (clamped) start, then shifted by +1,
+    -1, +2, -2, keeping 0 <= start <= n - 6 and the point inside the span.
+    A coordinate on a grid line has the single node itself."""
     if xi == np.rint(xi):
-        ii, wi = [int(xi)], [1.0]
-    else:
-        i0 = int(stencil_start(np.array([xi]), n1)[0])
-        ii = list(range(i0, i0 + ORDER))
-        wi = list(lagrange_weights(np.array([xi - i0]))[0])
-    if eta == np.rint(eta):
-        jj, wj = [int(eta)], [1.0]
-    else:
-        j0 = int(stencil_start(np.array([eta]), n2)[0])
-        jj = list(range(j0, j0 + ORDER))
-        wj = list(lagrange_weights(np.array([eta - j0]))[0])
-    return [(j, i, wj[b] * wi[a]) for b, j in enumerate(jj) for a, i in enumerate(ii)]
+        return [None]
+    c = int(stencil_start(np.array([xi]), n)[0])
+    out = []
+    for s in (c, c + 1, c - 1, c + 2, c - 2):
+        if 0 <= s <= n - ORDER and s <= xi <= s + ORDER - 1:
+            out.append(s)
+    return out
+
+
+def stencil(grid, xi: float, eta: float, eligible=None):
+    """Interpolation entries [(j, i, weight)] at (xi, eta); coordinates that
+    sit on a grid line contribute a single node along that direction.  With
+    ``eligible(j, i)``, the first stencil position (in the order of _starts,
+    by the sum of the two ranks, then the rank along q^1) whose nodes are
+    all eligible; None when there is none."""
+    n2, n1 = grid.p.x.shape
+    si, sj = _starts(xi, n1), _starts(eta, n2)
+    for total in range(len(si) + len(sj) - 1):
+        for ri in range(total + 1):
+            rj = total - ri
+            if ri >= len(si) or rj >= len(sj):
+                continue
+            i0, j0 = si[ri], sj[rj]
+            ii = [int(xi)] if i0 is None else list(range(i0, i0 + ORDER))
+            jj = [int(eta)] if j0 is None else list(range(j0, j0 + ORDER))
+            if eligible is not None and not all(eligible(j, i) for j in jj for i in ii):
+                continue
+            wi = [1.0] if i0 is None else _lagrange_scalar(xi - i0)
+            wj = [1.0] if j0 is None else _lagrange_scalar(eta - j0)
+            return [(j, i, wj[b] * wi[a]) for b, j in enumerate(jj) for a, i in enumerate(ii)]
+    return None
+
+
+def _lagrange_scalar(u: float):
+    """lagrange_weights for one position, as plain floats."""
+    w = []
+    for k in range(ORDER):
+        v = 1.0
+        for m in range(ORDER):
+            if m != k:
+                v *= (u - m) / (k - m)
+        w.append(v)
+    return w
 
 
 def _bbox_candidates(g_p, g_s, pts):
@@ -169,8 +207,8 @@ def fringe_rows(grids):
             for k, c in enumerate(cand):
                 if not ok[k] or not inside(gs, xi[k], eta[k]):
                     continue
-                ent = stencil(gs, xi[k], eta[k])
-                if not all(gs.p.mask[j, i] and not gs.fringe[j, i] for j, i, _ in ent):
+                ent = stencil(gs, xi[k], eta[k], lambda j, i: gs.p.mask[j, i] and not gs.fringe[j, i])
+                if ent is None:
                     continue
                 dep = gs.depth_at(xi[k], eta[k])
                 if dep > best[c][0] + 1e-9:
@@ -227,8 +265,8 @@ def blend_rows(grids, n_v: int):
                 w = float(blend_weight(gs.depth_at(xi[k], eta[k]), n_v))
                 if w <= 0.0:
                     continue
-                ent = stencil(gs, xi[k], eta[k])
-                if not all(gs.p.mask[j, i] for j, i, _ in ent):
+                ent = stencil(gs, xi[k], eta[k], lambda j, i: gs.p.mask[j, i])
+                if ent is None:
                     continue
                 contrib[c].append((s, w, ent))
         rows = {}

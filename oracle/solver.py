@@ -222,6 +222,12 @@ class Solver:
 
     def step(self):
         prm = self.prm
+        if self.nstep == 0:
+            # the initial data are made to satisfy the boundary conditions
+            # (walls, inflow, exact data, then the fringe fill), as the
+            # solution does after every stage; the first step's viscosity
+            # then sees the jumps the walls impose
+            self.U = self.enforce(self.U, self.t)
         self.mu = self.compute_viscosity(self.U) if prm.av != "off" else None
         if prm.filter and self.nstep > 0:
             self.U = self.apply_filter(self.U)

@@ -23,7 +23,7 @@ HIP_SOURCES = ["gemm.hip", "stage_kernels.hip", "window_kernels.hip", "sdnn_trai
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 HIP_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
              "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-GXX_FLAGS = ["-O2", "-std=gnu++17", "-fext-numeric-literals", "-fPIC"]
+GXX_FLAGS = ["-O2", "-std=gnu++17", "-fext-numeric-literals", "-fPIC", "-pthread"]
 
 
 def _run(cmd):
@@ -49,7 +49,7 @@ def build(verbose: bool = False) -> str:
                 print(out)
     objs = [os.path.join(BUILD, s + ".o") for s in GXX_SOURCES + HIP_SOURCES]
     tmp = OUT + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lquadmath"])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs, "-lquadmath", "-lpthread"])
     os.replace(tmp, OUT)
     return OUT
 

@@ -138,6 +138,9 @@ struct fcs_ctx {
   // the solution is past t = 0 (a step completed, or fcs_set_time set t > 0):
   // the filter of Alg. 4 applies from then on
   bool past_t0 = false;
+  // the initial data have been made to satisfy the boundary conditions (done
+  // once before the first step from t = 0; set_state and set_time reset it)
+  bool t0_prepared = false;
   double t_host = 0.0;
   double* cur = nullptr;  // buffer that holds the latest state
 
@@ -326,10 +329,13 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
     }
     g.offset = offset;
     offset += static_cast<int64_t>(np);
-    if (!build_grid(g, p.fc_d, p.fc_C, p.n_f, err)) {
-      *out = c.release();
-      return (*out)->fail(FCS_EINVAL, "subpatch " + std::to_string(q) + ": " + err);
-    }
+  }
+  // runs, metrics, fringe and hashes of every subpatch (independent of each
+  // other; host threads)
+  int bad = -1;
+  if (!build_grids(c->grids, p.fc_d, p.fc_C, p.n_f, err, bad)) {
+    *out = c.release();
+    return (*out)->fail(FCS_EINVAL, "subpatch " + std::to_string(bad) + ": " + err);
   }
   c->P = offset;
   if (offset >= (int64_t{1} << 31)) {  // point indices are stored as int32 in the window table
@@ -1028,6 +1034,31 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   return FCS_OK;
 }
 
+// Before the first step from t = 0: the initial data are made to satisfy
+// the boundary conditions (walls, inflow, exact data, then the fringe fill
+// from the donors), as the solution does after every stage; the first
+// step's viscosity then sees the jumps that the walls impose.
+fcs_status prepare_t0(fcs_ctx* c) {
+  const fcs_params& p = c->prm;
+  double* U0 = c->arr[A_U0];
+  const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
+  BcArgs b{};
+  b.bc = c->dptr<BcEntry>("BC");
+  b.bcidx = c->dptr<int32_t>("BCIDX");
+  b.gamma = p.gamma;
+  b.vortex = VortexArgs{p.vortex[0], p.vortex[1], p.vortex[2], p.vortex[3], p.vortex[4]};
+  if (!c->bc.empty()) HIPCHK(c, launch_bc_state(U0, flags, b, c->t_host, c->P, c->stream));
+  FluxOut none{};
+  none.F = nullptr;
+  HIPCHK(c, launch_fringe(U0, flags, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
+                          c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
+                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), c->P, none, nullptr, p.gamma,
+                          c->stream));
+  c->ps_valid = false;
+  c->t0_prepared = true;
+  return FCS_OK;
+}
+
 fcs_status full_step_eager(fcs_ctx* c) {
   fcs_status st;
   if ((st = per_step(c)) != FCS_OK) return st;
@@ -1092,6 +1123,7 @@ extern "C" fcs_status fcs_set_state(fcs_ctx* c, int32_t patch, int32_t vars, con
   if (c->stage_in_step != 0) return c->fail(FCS_ESTATE, "fcs_set_state inside a step: advance to a step boundary first");
   if (vars != FCS_VARS_CONS && vars != FCS_VARS_PRIM) return c->fail(FCS_EINVAL, "bad variable kind");
   c->ps_valid = false;
+  c->t0_prepared = false;
   const Grid& g = c->grids[patch];
   const size_t np = g.np();
   std::vector<double> h(4 * np);
@@ -1128,6 +1160,7 @@ extern "C" fcs_status fcs_set_time(fcs_ctx* c, double t) {
   if (c->stage_in_step != 0) return c->fail(FCS_ESTATE, "fcs_set_time inside a step: advance to a step boundary first");
   c->t_host = t;
   c->past_t0 = t != 0.0;
+  c->t0_prepared = false;
   if (c->bound) {
     HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL"), &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
     HIPCHK(c, hipMemcpyAsync(c->dptr<double>("SCAL") + 4, &c->t_host, 8, hipMemcpyHostToDevice, c->stream));
@@ -1274,6 +1307,7 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
   if (!c->tuned && (st = autotune(c)) != FCS_OK) return st;
   const bool graph = c->prm.use_graph && c->stream != nullptr;
   while (n_stages > 0) {
+    if (c->stage_in_step == 0 && !c->past_t0 && !c->t0_prepared && (st = prepare_t0(c)) != FCS_OK) return st;
     if (c->stage_in_step == 0 && n_stages >= 5) {
       int wf = (c->prm.filter && c->past_t0) ? 1 : 0;
       if (graph) {

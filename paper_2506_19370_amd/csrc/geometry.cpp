@@ -17,6 +17,9 @@
 #include <cmath>
 #include <limits>
 
+#include <atomic>
+#include <thread>
+
 #include "fc_builder.h"
 
 namespace fcs {
@@ -24,6 +27,10 @@ namespace fcs {
 namespace {
 
 constexpr double kSnap = 1e-9;
+// Newton steps below this (index units) end the donor inversion: with O(1)
+// coordinates and spacings down to 1e-4 the rounding floor of a step is a
+// few 1e-12, and the snap to grid lines (kSnap) is coarser anyway.
+constexpr double kNewtonTol = 1e-10;
 constexpr int kOrder = 6;
 constexpr double kInf = std::numeric_limits<double>::infinity();
 
@@ -170,7 +177,7 @@ bool invert(const Grid& g, double px, double py, double& xi, double& eta) {
     double deta = (-ya * fx + xa * fy) / det;
     xi = std::max(-3.0, std::min(g.n1 + 2.0, xi - dxi));
     eta = std::max(-3.0, std::min(g.n2 + 2.0, eta - deta));
-    ok = (std::abs(dxi) < 1e-12 && std::abs(deta) < 1e-12) || std::hypot(fx, fy) < 1e-15 * scale;
+    ok = (std::abs(dxi) < kNewtonTol && std::abs(deta) < kNewtonTol) || std::hypot(fx, fy) < 1e-15 * scale;
     if (ok) break;
   }
   double rx = std::nearbyint(xi), ry = std::nearbyint(eta);
@@ -212,33 +219,66 @@ struct Entry {
   double w;
 };
 
-void stencil(const Grid& g, double xi, double eta, std::vector<Entry>& out) {
-  out.clear();
-  int ii[kOrder], jj[kOrder];
-  double wi[kOrder], wj[kOrder];
-  int ni, nj;
+// First nodes of the 6-point stencil along one direction, most preferred
+// first: the centred start clamped into the index box, then that start
+// moved by +1, -1, +2, -2 while it stays in the box and its span still
+// holds the point.  A coordinate on a grid line uses the node itself (-1).
+int stencil_starts(double xi, int n, int* out) {
   if (xi == std::nearbyint(xi)) {
-    ni = 1;
-    ii[0] = static_cast<int>(xi);
-    wi[0] = 1.0;
-  } else {
-    ni = kOrder;
-    int i0 = stencil_start(xi, g.n1);
-    lagrange(xi - i0, wi);
-    for (int a = 0; a < kOrder; ++a) ii[a] = i0 + a;
+    out[0] = -1;
+    return 1;
   }
-  if (eta == std::nearbyint(eta)) {
-    nj = 1;
-    jj[0] = static_cast<int>(eta);
-    wj[0] = 1.0;
-  } else {
-    nj = kOrder;
-    int j0 = stencil_start(eta, g.n2);
-    lagrange(eta - j0, wj);
-    for (int b = 0; b < kOrder; ++b) jj[b] = j0 + b;
+  const int c = stencil_start(xi, n), shift[5] = {0, 1, -1, 2, -2};
+  int cnt = 0;
+  for (int s : shift) {
+    int v = c + s;
+    if (v >= 0 && v <= n - kOrder && v <= xi && xi <= v + kOrder - 1) out[cnt++] = v;
   }
-  for (int b = 0; b < nj; ++b)
-    for (int a = 0; a < ni; ++a) out.push_back({jj[b], ii[a], wj[b] * wi[a]});
+  return cnt;
+}
+
+// Interpolation stencil at (xi, eta) whose nodes all satisfy `ok`: the
+// candidate positions are tried by the sum of their ranks along the two
+// directions, then by the rank along q^1 (where the centred stencil would
+// reach a masked or fringe node, e.g. beside the obstacle quadrant of a
+// corner subpatch, the interpolation becomes one-sided).  false if none.
+template <class Pred>
+bool stencil(const Grid& g, double xi, double eta, Pred ok, std::vector<Entry>& out) {
+  int si[5], sj[5];
+  const int ni_c = stencil_starts(xi, g.n1, si), nj_c = stencil_starts(eta, g.n2, sj);
+  for (int total = 0; total <= ni_c + nj_c - 2; ++total)
+    for (int ri = 0; ri <= total; ++ri) {
+      const int rj = total - ri;
+      if (ri >= ni_c || rj >= nj_c) continue;
+      int ii[kOrder], jj[kOrder];
+      double wi[kOrder], wj[kOrder];
+      int ni = 1, nj = 1;
+      if (si[ri] < 0) {
+        ii[0] = static_cast<int>(xi);
+        wi[0] = 1.0;
+      } else {
+        ni = kOrder;
+        lagrange(xi - si[ri], wi);
+        for (int a = 0; a < kOrder; ++a) ii[a] = si[ri] + a;
+      }
+      if (sj[rj] < 0) {
+        jj[0] = static_cast<int>(eta);
+        wj[0] = 1.0;
+      } else {
+        nj = kOrder;
+        lagrange(eta - sj[rj], wj);
+        for (int b = 0; b < kOrder; ++b) jj[b] = sj[rj] + b;
+      }
+      bool good = true;
+      for (int b = 0; b < nj && good; ++b)
+        for (int a = 0; a < ni && good; ++a) good = ok(g.at(jj[b], ii[a]));
+      if (!good) continue;
+      out.clear();
+      for (int b = 0; b < nj; ++b)
+        for (int a = 0; a < ni; ++a) out.push_back({jj[b], ii[a], wj[b] * wi[a]});
+      return true;
+    }
+  return false;
 }
 
 bool bbox_candidate(const Grid& s, double px, double py) {
@@ -465,10 +505,55 @@ static std::vector<size_t> box_neighbours(const std::vector<Grid>& grids, size_t
   return out;
 }
 
+static void fringe_rows_of(const std::vector<Grid>& grids, size_t p, std::vector<InterpRow>& rows, std::string& err);
+
+// Runs fn(p) for p = 0 .. n-1 on up to 16 host threads (subpatches are
+// independent: each call reads the grids and writes only its own slot).
+template <class Fn>
+static void for_each_patch(size_t n, Fn fn) {
+  const unsigned hw = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  const size_t nt = std::min<size_t>(hw, n);
+  std::atomic<size_t> next{0};
+  auto work = [&]() {
+    for (size_t p = next++; p < n; p = next++) fn(p);
+  };
+  std::vector<std::thread> pool;
+  for (size_t t = 1; t < nt; ++t) pool.emplace_back(work);
+  work();
+  for (auto& th : pool) th.join();
+}
+
+bool build_grids(std::vector<Grid>& grids, int d, int C, int n_f, std::string& err, int& bad) {
+  std::vector<std::string> perr(grids.size());
+  std::vector<char> ok(grids.size(), 1);
+  for_each_patch(grids.size(), [&](size_t p) { ok[p] = build_grid(grids[p], d, C, n_f, perr[p]); });
+  for (size_t p = 0; p < grids.size(); ++p)
+    if (!ok[p]) {
+      err = perr[p];
+      bad = static_cast<int>(p);
+      return false;
+    }
+  return true;
+}
+
 bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& rows, std::string& err) {
   rows.clear();
+  std::vector<std::vector<InterpRow>> per(grids.size());
+  std::vector<std::string> perr(grids.size());
+  for_each_patch(grids.size(), [&](size_t p) { fringe_rows_of(grids, p, per[p], perr[p]); });
+  for (size_t p = 0; p < grids.size(); ++p)
+    if (!perr[p].empty()) {
+      err = perr[p];
+      return false;
+    }
+  for (auto& v : per)
+    for (auto& r : v) rows.push_back(std::move(r));
+  return true;
+}
+
+static void fringe_rows_of(const std::vector<Grid>& grids, size_t p, std::vector<InterpRow>& rows, std::string& err) {
   std::vector<Entry> ent;
-  for (size_t p = 0; p < grids.size(); ++p) {
+  {
     const Grid& gp = grids[p];
     const std::vector<size_t> nb = box_neighbours(grids, p);
     for (int j = 0; j < gp.n2; ++j)
@@ -484,16 +569,7 @@ bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& r
           if (!bbox_candidate(gs, px, py)) continue;
           double xi, eta;
           if (!invert(gs, px, py, xi, eta) || !inside(gs, xi, eta)) continue;
-          stencil(gs, xi, eta, ent);
-          bool ok = true;
-          for (const Entry& e : ent) {
-            size_t kk = gs.at(e.j, e.i);
-            if (!gs.mask[kk] || gs.fringe[kk]) {
-              ok = false;
-              break;
-            }
-          }
-          if (!ok) continue;
+          if (!stencil(gs, xi, eta, [&](size_t kk) { return gs.mask[kk] && !gs.fringe[kk]; }, ent)) continue;
           double dep = depth_at(gs, xi, eta);
           if (dep > best + 1e-9) {
             best = dep;
@@ -504,7 +580,7 @@ bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& r
         if (bs < 0) {
           err = "fringe point (" + std::to_string(j) + ", " + std::to_string(i) + ") of subpatch " +
                 std::to_string(p) + " has no donor";
-          return false;
+          return;
         }
         InterpRow row;
         row.dst = gp.offset + static_cast<int64_t>(k);
@@ -513,11 +589,19 @@ bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& r
         rows.push_back(std::move(row));
       }
   }
-  return true;
 }
+
+static void blend_rows_of(const std::vector<Grid>& grids, size_t p, int n_v, std::vector<InterpRow>& rows);
 
 void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<InterpRow>& rows) {
   rows.clear();
+  std::vector<std::vector<InterpRow>> per(grids.size());
+  for_each_patch(grids.size(), [&](size_t p) { blend_rows_of(grids, p, n_v, per[p]); });
+  for (auto& v : per)
+    for (auto& r : v) rows.push_back(std::move(r));
+}
+
+static void blend_rows_of(const std::vector<Grid>& grids, size_t p, int n_v, std::vector<InterpRow>& rows) {
   std::vector<Entry> ent;
   struct Contrib {
     int s;
@@ -525,7 +609,7 @@ void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<Inter
     std::vector<Entry> e;
   };
   std::vector<Contrib> lst;
-  for (size_t p = 0; p < grids.size(); ++p) {
+  {
     const Grid& gp = grids[p];
     const std::vector<size_t> nb = box_neighbours(grids, p);
     for (int j = 0; j < gp.n2; ++j)
@@ -541,14 +625,7 @@ void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<Inter
           if (!invert(gs, px, py, xi, eta) || !inside(gs, xi, eta)) continue;
           double w = smooth_step(depth_at(gs, xi, eta) / (2.0 * n_v));
           if (!(w > 0.0)) continue;
-          stencil(gs, xi, eta, ent);
-          bool ok = true;
-          for (const Entry& e : ent)
-            if (!gs.mask[gs.at(e.j, e.i)]) {
-              ok = false;
-              break;
-            }
-          if (!ok) continue;
+          if (!stencil(gs, xi, eta, [&](size_t kk) { return gs.mask[kk] != 0; }, ent)) continue;
           lst.push_back({static_cast<int>(s), w, ent});
         }
         if (lst.empty()) continue;

@@ -48,6 +48,10 @@ struct Grid {
 // hash of one subpatch; false with a message on invalid input.
 bool build_grid(Grid& g, int d, int C, int n_f, std::string& err);
 
+// build_grid of every subpatch on host threads; on failure the lowest
+// failing index and its message.
+bool build_grids(std::vector<Grid>& grids, int d, int C, int n_f, std::string& err, int& bad);
+
 // Apply a dense FC operator along the runs of a (n2, n1) field.
 void apply_lines(const Grid& g, int d, int C, int kind, int dir, const double* f, double* out);
 

@@ -118,6 +118,9 @@ hipError_t launch_stage(const StageArgs& a, hipStream_t s);
 hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pairs, int ncopy, const int64_t* idst,
                          const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
                          const FluxOut& fo, double2* ps, double gamma, hipStream_t s);
+// Boundary conditions of every boundary point of U, in place, at time t
+// (b.t and b.frac are not used).
+hipError_t launch_bc_state(double* U, const uint8_t* flags, const BcArgs& b, double t, int64_t P, hipStream_t s);
 // Alg. 3 in two parts: the proxy variable and wave speeds (the only part
 // that reads the state), then classification, preliminary viscosity,
 // dilation and blend.

@@ -105,6 +105,21 @@ __device__ __forceinline__ void apply_bc(const BcEntry& b, double gamma, double 
   }
 }
 
+// Boundary conditions of every boundary point, in place (the initial data
+// made to satisfy them before the first step; the stages apply them in
+// k_stage).
+__global__ void k_bc_state(double* __restrict__ U, const uint8_t* __restrict__ flags, BcArgs b, double t, int64_t P) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  if (!(flags[k] & kActive) || !(flags[k] & kBoundary)) return;
+  double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+  apply_bc(b.bc[b.bcidx[k]], b.gamma, t, b.vortex, r, mx, my, E);
+  U[k] = r;
+  U[P + k] = mx;
+  U[2 * P + k] = my;
+  U[3 * P + k] = E;
+}
+
 // DT: element type of the stage derivatives (double, or float in the mixed
 // forms, where the contractions themselves are FP32 or split BF16).
 // S: the stage (0..4), so that each instantiation reads only the registers
@@ -601,6 +616,11 @@ hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pa
   if (ncopy + ninterp)
     hipLaunchKernelGGL(k_fringe, grid_for(ncopy + ninterp), dim3(256), 0, s, U, flags, copy_pairs, ncopy, idst, iptr,
                        icol, ival, ninterp, P, fo, ps, gamma);
+  return hipGetLastError();
+}
+
+hipError_t launch_bc_state(double* U, const uint8_t* flags, const BcArgs& b, double t, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_bc_state, grid_for(P), dim3(256), 0, s, U, flags, b, t, P);
   return hipGetLastError();
 }
 

@@ -71,6 +71,42 @@ def test_lagrange_reproduces_quintics():
         assert np.abs(dw @ (np.arange(6.0) ** k) - k * u ** (k - 1)).max() < 1e-9 * 5 ** k
 
 
+def test_shifted_stencil_beside_the_notch_reproduces_polynomials():
+    """Interpolation inside a skewed corner subpatch (the wedge tip's C1
+    patch, affine, obstacle quadrant masked): where the centred 6 x 6
+    stencil would take masked nodes next to the notch, the stencil moves
+    (one-sided interpolation) and still reproduces a polynomial of degree 5
+    exactly; away from the notch the centred stencil is kept."""
+    geo = W.wedge_geometry(400)
+    m = 20
+    spec = W._c1_patch(1.0 / 400, geo["T"], -geo["l"], -geo["u"], m, W.WEDGE_INFLOW)
+    g = patches.Grid(solver.patches_from_specs([spec])[0], 2, 27, 5)
+    mask = g.p.mask
+    f = lambda x, y: 1e6 * x ** 3 * y ** 2 - 3e4 * y ** 4 + 7e2 * x * y + x - 2 * y
+    shifted = 0
+    for xi, eta in ((m + 0.4, m - 3.7), (m + 1.3, m - 7.2), (m + 2.6, m - 1.5), (m - 4.3, m + 0.7),
+                    (m + 0.5, m + 0.5), (m + 10.25, m + 8.75)):
+        ent = overlap.stencil(g, xi, eta, lambda j, i: mask[j, i])
+        assert ent is not None and all(mask[j, i] for j, i, _ in ent)
+        c = overlap.stencil(g, xi, eta)
+        shifted += [(j, i) for j, i, _ in ent] != [(j, i) for j, i, _ in c]
+        # the map is affine: the point's coordinates are the same affine
+        # combination of node coordinates under either stencil
+        px = sum(w * g.p.x[j, i] for j, i, w in ent)
+        py = sum(w * g.p.y[j, i] for j, i, w in ent)
+        assert abs(px - sum(w * g.p.x[j, i] for j, i, w in c)) < 1e-14
+        assert abs(py - sum(w * g.p.y[j, i] for j, i, w in c)) < 1e-14
+        v = sum(w * f(g.p.x[j, i], g.p.y[j, i]) for j, i, w in ent)
+        assert abs(v - f(px, py)) < 1e-9 * max(1.0, abs(f(px, py)))
+    assert shifted >= 4
+    # far from the notch and inside the box: the centred stencil
+    ent = overlap.stencil(g, m + 10.25, m + 8.75, lambda j, i: mask[j, i])
+    assert ent == overlap.stencil(g, m + 10.25, m + 8.75)
+    assert min(i for _, i, _ in ent) == m + 8 and min(j for j, _, _ in ent) == m + 6
+    # no position exists when the point is inside the notch
+    assert overlap.stencil(g, m - 3.5, m - 3.5, lambda j, i: mask[j, i]) is None
+
+
 def test_newton_inversion_curved():
     spec = W.annular_sector(40, 30)[0]
     g = patches.Grid(solver.patches_from_specs([spec])[0], 5, 27, 5)

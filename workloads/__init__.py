@@ -451,3 +451,188 @@ def window_labels(pos, amp, lines, n=101, rel_tol=1e-2):
         near = np.abs(pp - i) <= 2.0
         lab = np.where(sig[:, None] & near, 2, np.where(sig[:, None] & inwin & (lab < 2), np.maximum(lab, 1), lab))
     return lab
+
+
+# ---------------------------------------------------------------- Mach-10 wedge tunnel
+WEDGE_INFLOW = (1.4, 10.0, 0.0, 1.0)
+
+
+def wedge_geometry(h_index, tip_x=0.2, length=0.2, half_angle_deg=15.0, yc=0.25):
+    """The obstacle of the wedge tunnel in lattice index units (spacing
+    1 / h_index): tip T, rear corners R+ (upper) and R- (lower), the unit
+    vectors u and l of the upper and lower faces (from the tip towards the
+    rear) and the rear half-height H."""
+    th = np.deg2rad(half_angle_deg)
+    Xt, Xr, Yc = tip_x * h_index, (tip_x + length) * h_index, yc * h_index
+    H = (Xr - Xt) * np.tan(th)
+    u = np.array([np.cos(th), np.sin(th)])
+    l = np.array([np.cos(th), -np.sin(th)])
+    return dict(T=np.array([Xt, Yc]), Rp=np.array([Xr, Yc + H]), Rm=np.array([Xr, Yc - H]), u=u, l=l, H=H,
+                Xt=Xt, Xr=Xr, Yc=Yc, theta=th)
+
+
+def _affine_patch(h, origin, e1, e2, i0, i1, j0, j1, sides, kind, inflow, mask=None, notch=SLIP):
+    """Nodes origin + i e1 + j e2 (index units, scaled by h) for integer i in
+    [i0, i1], j in [j0, j1]."""
+    I = np.arange(i0, i1 + 1, dtype=float)[None, :]
+    J = np.arange(j0, j1 + 1, dtype=float)[:, None]
+    X = (origin[0] + I * e1[0] + J * e2[0]) * h
+    Y = (origin[1] + I * e1[1] + J * e2[1]) * h
+    return PatchSpec(X, Y, mask, dict(sides), notch, inflow, kind)
+
+
+def _c1_patch(h, C, e1, e2, m, inflow):
+    """C1 corner subpatch around the corner C of two straight walls: the map
+    q -> l_A(q^1) + l_B(q^2) - C with straight arcs l_A, l_B of directions e1,
+    e2 (index units), on (2m + 1)^2 nodes; the quadrant i < m, j < m (the
+    obstacle, C - a e1 - b e2 with a, b > 0) is masked; the mask boundary is
+    the two walls, the four outer sides are internal."""
+    n = 2 * m + 1
+    II, JJ = np.meshgrid(np.arange(n), np.arange(n))
+    mask = ~((II < m) & (JJ < m))
+    return _affine_patch(h, C - m * e1 - m * e2, e1, e2, 0, n - 1, 0, n - 1,
+                         {k: INTERNAL for k in "WESN"}, "C1", inflow, mask, SLIP)
+
+
+def _mirror(spec, Yc_phys):
+    """Mirror image of a subpatch in the line y = Yc_phys, rows reversed so
+    that the node ordering keeps its orientation (S and N sides swap)."""
+    sides = dict(spec.sides)
+    sides["S"], sides["N"] = spec.sides["N"], spec.sides["S"]
+    mask = None if spec.mask is None else spec.mask[::-1].copy()
+    return PatchSpec(spec.x[::-1].copy(), 2 * Yc_phys - spec.y[::-1], mask, sides, spec.notch, spec.inflow,
+                     spec.kind)
+
+
+def _keepout_extent(geo, xa, xb, delta):
+    """y-range of the points within distance delta of the obstacle over the
+    abscissae [xa, xb] (index units), or None."""
+    T, Rp, Rm = geo["T"], geo["Rp"], geo["Rm"]
+    pts = []
+    for a, b in ((T, Rp), (Rp, Rm), (Rm, T)):
+        t = np.linspace(0.0, 1.0, 4001)[:, None]
+        pts.append(a[None, :] * (1 - t) + b[None, :] * t)
+    pts = np.concatenate(pts)
+    dx = np.maximum(0.0, np.maximum(xa - pts[:, 0], pts[:, 0] - xb))
+    ok = dx <= delta
+    if not ok.any():
+        return None
+    r = np.sqrt(delta * delta - dx[ok] ** 2)
+    return float((pts[ok, 1] - r).min()), float((pts[ok, 1] + r).max())
+
+
+def wedge_tunnel(h_index=4400, smin=150, smax=300, config_index=5, seed_salt=1, tip_x=0.2, length=0.2,
+                 half_angle_deg=15.0, mach=10.0):
+    """Mach-10 flow past a wedge with a blunt rear face in the tunnel
+    [0, 1] x [0, 0.5] (lattice spacing h = 1 / h_index).  The obstacle is the
+    triangle with tip T = (tip_x, 0.25), faces at +-half_angle_deg to the
+    flow and a vertical rear face at x = tip_x + length (the prism shape of
+    the paper's flow-past-prism experiment, with a narrower front angle).
+
+    Subpatches (Sec. 3 patch types):
+    - C1 corner subpatches (2m + 1)^2 around the tip and the two rear
+      corners, each the affine map of the L-shaped parameter domain built
+      from the two straight walls (non-right angles: 30 degrees of obstacle
+      at the tip, 75 at the rear corners);
+    - skewed-affine S subpatches along each face (one axis along the face,
+      the other vertical), one axis of slip wall;
+    - S subpatches on the rear face (lattice, slip wall on the west side);
+    - lattice subpatches over the rest, in columns of seeded widths cut at the
+      tip abscissa and at the rear face, each column split into rows of
+      seeded heights and kept clear of a band of width delta around the
+      obstacle; the column behind the rear face holds a wake block that
+      starts delta downstream of the face.
+    Sides are in [smin, smax] where the seeded draws set them.  Inflow of the
+    Mach-M stream (1.4, M, 0, 1) at x = 0, outflow at x = 1, slip walls at
+    y = 0, y = 0.5 and on the obstacle."""
+    g = rng(config_index, seed_salt)
+    h = 1.0 / h_index
+    geo = wedge_geometry(h_index, tip_x, length, half_angle_deg)
+    T, Rp, Rm, u, l, H = geo["T"], geo["Rp"], geo["Rm"], geo["u"], geo["l"], geo["H"]
+    Xt, Xr, Yc = int(round(geo["Xt"])), int(round(geo["Xr"])), geo["Yc"]
+    NX, NY = h_index, h_index // 2
+    e = 8
+    cmin, cmax = smin - 2 * e - 1, smax - 2 * e - 1
+    m = min((smax - 1) // 2, int(0.45 * Xt))  # tip C1 arm (points)
+    mr = min((smax - 1) // 2, int(0.6 * H))   # rear C1 arm (points)
+    Ts = int(round(0.6 * smax))              # face S thickness (points, vertical)
+    Tr = smin - 1                            # rear S thickness
+    delta = max(3, int(round(0.02 * smax)))  # clearance of the lattice blocks
+    inflow = (1.4, float(mach), 0.0, 1.0)
+    out = []
+    # --- body-fitted subpatches of the upper half, then their mirror images
+    out.append(_c1_patch(h, T, -l, -u, m, inflow))  # on the symmetry line
+    up = []
+    up.append(_c1_patch(h, Rp, u, np.array([0.0, 1.0]), mr, inflow))
+    Lf = (Xr - Xt) / np.cos(geo["theta"])
+    nS = max(1, int(round(Lf / (0.5 * (smin + smax)))))
+    cuts = np.rint(np.linspace(0, Lf, nS + 1)).astype(int)
+    cuts[-1] = int(np.floor(Lf))
+    for k in range(nS):
+        i0 = cuts[k] - (e if k > 0 else 0)
+        i1 = cuts[k + 1] + (e if k < nS - 1 else 0)
+        up.append(_affine_patch(h, T, u, np.array([0.0, 1.0]), i0, i1, 0, Ts,
+                                {"W": INTERNAL, "E": INTERNAL, "S": SLIP, "N": INTERNAL}, "S", inflow))
+    out.extend(up)
+    out.extend(_mirror(s, Yc * h) for s in up)
+    # rear face: lattice S subpatches with the wall on the west side
+    ra = int(round(0.35 * mr))
+    Ya, Yb = int(np.ceil(Yc - H)) + ra, int(np.floor(Yc + H)) - ra
+    nR = max(1, int(round((Yb - Ya) / (0.5 * (smin + smax)))))
+    rc = np.rint(np.linspace(Ya, Yb, nR + 1)).astype(int)
+    for k in range(nR):
+        y0 = rc[k] - (e if k > 0 else 0)
+        y1 = rc[k + 1] + (e if k < nR - 1 else 0)
+        out.append(lattice_patch(h, Xr, Xr + Tr, y0, y1, {"W": SLIP, "E": INTERNAL, "S": INTERNAL, "N": INTERNAL},
+                                 "S", inflow))
+    # --- lattice blocks
+    def rows(x0, x1, y0, y1, W, E, S, N):
+        ys = _split(y0, y1, cmin, cmax, g)
+        for r in range(len(ys) - 1):
+            s_ = S if r == 0 else INTERNAL
+            n_ = N if r == len(ys) - 2 else INTERNAL
+            Y0 = ys[r] - (e if (r > 0) else 0)
+            Y1 = ys[r + 1] + (e if r < len(ys) - 2 else 0)
+            kind = "I" if (W, E, s_, n_) == (INTERNAL,) * 4 else "S"
+            out.append(lattice_patch(h, x0, x1, Y0, Y1, {"W": W, "E": E, "S": s_, "N": n_}, kind, inflow))
+
+    def colsplit(a, b, wmax):
+        return _split(a, b, cmin, min(cmax, wmax), g)
+
+    # the column just upstream of the tip is split around the axis: its width
+    # stays within the reach of the tip patch, which covers that gap
+    wl = max(cmin, min(cmax, int(1.4 * (m - 9)), int(1.93 * m - 56)))
+    xs = colsplit(0, Xt - wl, cmax) + [Xt]
+    xs = xs[:-1] + colsplit(Xt, Xr, int(0.75 * cmax))[:-1] + colsplit(Xr, NX, cmax)
+    for c in range(len(xs) - 1):
+        c0, c1 = xs[c], xs[c + 1]
+        W = INFLOW if c0 == 0 else INTERNAL
+        E = OUTFLOW if c1 == NX else INTERNAL
+        xa, xb = c0 - (e if c0 > 0 else 0), c1 + (e if c1 < NX else 0)
+        if c1 == Xt:
+            xb = Xt + 2 * e  # past the vertical edge of the face subpatches at the tip
+        ko = _keepout_extent(geo, xa, xb, delta)
+        if ko is None:
+            rows(xa, xb, 0, NY, W, E, SLIP, SLIP)
+            continue
+        ylo, yhi = int(np.floor(ko[0])), int(np.ceil(ko[1]))
+        rows(xa, xb, 0, ylo, W, E, SLIP, INTERNAL)
+        rows(xa, xb, yhi, NY, W, E, INTERNAL, SLIP)
+        if c0 == Xr:
+            # wake block behind the rear face, overlapping the blocks above and below
+            rows(Xr + delta, xb, ylo - 2 * e, yhi + 2 * e, INTERNAL, E, INTERNAL, INTERNAL)
+    return out
+
+
+def wedge_state(patch_list, quiescent_wake=False, mach=10.0):
+    """Initial data of the wedge tunnel: the uniform Mach-M stream
+    (rho, u, v, p) = (1.4, M, 0, 1) (sound speed 1) everywhere; with
+    quiescent_wake, the gas behind the rear face (x > rear, |y - 0.25| < H)
+    starts at rest."""
+    out = uniform_state(patch_list, (1.4, float(mach), 0.0, 1.0))
+    if quiescent_wake:
+        geo = wedge_geometry(1.0)
+        for s, w in zip(patch_list, out):
+            wake = (s.x > geo["Xr"]) & (np.abs(s.y - geo["Yc"]) < geo["H"])
+            w[1] = np.where(wake, 0.0, w[1])
+    return out
