@@ -167,25 +167,14 @@ class Grid:
                 return self.t1y * self.deriv(f, 0) + self.t2y * self.deriv(f, 1)
             self.lap1 = np.where(m, dx(self.t1x) + dy(self.t1y), 0.0)
             self.lap2 = np.where(m, dx(self.t2x) + dy(self.t2y), 0.0)
-        # physical grid size at each point: min distance to grid neighbours
-        hx = np.full(p.x.shape, np.inf)
-        for ax, sh in ((1, 1), (1, -1), (0, 1), (0, -1)):
-            xs = np.roll(p.x, sh, axis=ax)
-            ys = np.roll(p.y, sh, axis=ax)
-            ms = np.roll(m, sh, axis=ax)
-            valid = ms & m
-            if ax == 1:
-                if sh == 1:
-                    valid[:, 0] = False
-                else:
-                    valid[:, -1] = False
-            else:
-                if sh == 1:
-                    valid[0, :] = False
-                else:
-                    valid[-1, :] = False
-            dist = np.hypot(p.x - xs, p.y - ys)
-            hx = np.where(valid, np.minimum(hx, dist), hx)
+        # local mesh size at each point: 1 / sqrt of the largest eigenvalue
+        # of the metric tensor g^{kl} (index units), i.e. the distance
+        # between neighbouring grid lines along the most compressed
+        # direction; on an orthogonal grid the smaller spacing, on a skewed
+        # one (cells of angle a) smaller by up to sin(a/2) ... sin(a)
+        half = 0.5 * (self.g11 + self.g22)
+        lam = half + np.sqrt(0.25 * (self.g11 - self.g22) ** 2 + self.g12 ** 2)
+        hx = 1.0 / np.sqrt(np.where(m, lam, 1.0))
         self.hx = np.where(m, hx, 0.0)
 
     # --- fringe, boundary, depth (Sec. 3.3) ----------------------------

@@ -417,23 +417,18 @@ bool build_grid(Grid& g, int d, int C, int n_f, std::string& err) {
                                  : 0.0;
     }
   }
-  // physical grid size: distance to the nearest active grid neighbour
+  // local mesh size: 1 / sqrt of the largest eigenvalue of the metric tensor
+  // g^{kl} (index units), the distance between neighbouring grid lines along
+  // the most compressed direction (on a skewed grid well below the spacing
+  // of neighbouring nodes)
   g.hx.assign(np, 0.0);
-  for (int j = 0; j < n2; ++j)
-    for (int i = 0; i < n1; ++i) {
-      size_t k = g.at(j, i);
-      if (!g.mask[k]) continue;
-      double best = kInf;
-      const int di[4] = {-1, 1, 0, 0}, dj[4] = {0, 0, -1, 1};
-      for (int q = 0; q < 4; ++q) {
-        int ii = i + di[q], jj = j + dj[q];
-        if (ii < 0 || ii >= n1 || jj < 0 || jj >= n2) continue;
-        size_t kk = g.at(jj, ii);
-        if (!g.mask[kk]) continue;
-        best = std::min(best, std::hypot(g.x[k] - g.x[kk], g.y[k] - g.y[kk]));
-      }
-      g.hx[k] = best;
-    }
+  for (size_t k = 0; k < np; ++k) {
+    if (!g.mask[k]) continue;
+    const double half = 0.5 * (g.g11[k] + g.g22[k]);
+    const double dif = 0.5 * (g.g11[k] - g.g22[k]);
+    const double lam = half + std::sqrt(dif * dif + g.g12[k] * g.g12[k]);
+    g.hx[k] = 1.0 / std::sqrt(lam);
+  }
   // fringe (Sec. 3.3), exact-data layer, boundary points, depth
   g.fringe.assign(np, 0);
   g.xfringe.assign(np, 0);

@@ -334,7 +334,10 @@ def test_curvilinear_freestream_preserved():
 def test_curvilinear_viscous_parity_frozen_classes():
     """Non-affine metrics (16 line products per stage, Laplacian of the index
     coordinates, cross derivatives) with a non-zero viscosity: classes are
-    prescribed (frozen) identically on both sides."""
+    prescribed (frozen) identically on both sides.  The mesh size in the
+    viscosity (and in the step size) comes from the FC-derived metric, where
+    the two sides' d = 5 operators differ by up to 3e-12: viscosity and state
+    agree to 1e-11 relative."""
     specs = _sector()
     s = specs[0]
     r = np.hypot(s.x, s.y)
@@ -352,8 +355,8 @@ def test_curvilinear_viscous_parity_frozen_classes():
         S.advance(5, sync=True)
         O.step()
     assert np.abs(O.mu[0]).max() > 0
-    assert np.abs(S.field(0, "mu") - O.field(O.mu[0], 0)).max() < 1e-12 * np.abs(O.mu[0]).max()
-    assert _rel(S, O, specs) < 1e-12
+    assert np.abs(S.field(0, "mu") - O.field(O.mu[0], 0)).max() < 1e-11 * np.abs(O.mu[0]).max()
+    assert _rel(S, O, specs) < 1e-11
 
 
 @pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16x3", 1e-4)])

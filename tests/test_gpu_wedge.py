@@ -1,0 +1,130 @@
+"""GPU runs of the wedge tunnel (MI355X, gfx950): the obstacle with C1
+corner subpatches at the tip (30-degree obstacle angle) and at the two rear
+corners (75 degrees), skewed-affine subpatches on the faces and seeded
+lattice subpatches, at the Mach number of the headline configuration.
+
+- oracle parity on the small decomposition (h = 1/600, 72 subpatches):
+  modal viscosity and filter, two steps, classes equal and the state to
+  FP64 rounding;
+- the oblique shock off the upper face: its angle against the weak branch
+  of the theta-beta-M relation (Sec. 7, equation "deflection");
+- the full-size set (244 subpatches, 1.15e7 points): graph replay equals
+  eager launches bit for bit, and one split-BF16 step stays within the
+  split-BF16 contraction bound of the FP64 step.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("no GPU", allow_module_level=True)
+
+import os  # noqa: E402
+
+import paper_2506_19370_amd as F  # noqa: E402
+import workloads as W  # noqa: E402
+from oracle import exact, solver as osolver  # noqa: E402
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden", "sdnn_oracle_weights.npz")
+M = W.WEDGE_MACH
+
+
+def _rel(S, O, n):
+    scale = np.abs(O.U).max()
+    return max(np.abs(S.cons(p) - O.view(O.U, p)).max() for p in range(n)) / scale
+
+
+def test_wedge_small_matches_oracle():
+    specs = W.wedge_tunnel(600, 48, 96, mach=M)
+    w = W.wedge_state(specs, quiescent_wake=True, mach=M)
+    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+    O = osolver.Solver(osolver.patches_from_specs(specs),
+                       osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
+    O.set_prim(w)
+    for step in range(2):
+        t = S.advance(5, sync=True)
+        O.step()
+        assert abs(t - O.t) < 1e-12 * O.t
+        for p in range(len(specs)):
+            assert np.array_equal(S.field(p, "tau0"), O.last_tau[p][0]), (step, p)
+            assert np.array_equal(S.field(p, "tau1"), O.last_tau[p][1]), (step, p)
+        assert _rel(S, O, len(specs)) < 1e-11, step
+
+
+def _shock_angle(S, specs, xs, face, rho_mid):
+    """Least-squares angle (degrees) of the points above the face where the
+    density falls through rho_mid, on vertical lines x = xs."""
+    X, Y, R = [], [], []
+    for p, s in enumerate(specs):
+        act = np.ones(s.shape, bool) if s.mask is None else s.mask
+        X.append(s.x[act])
+        Y.append(s.y[act])
+        R.append(S.field(p, "rho")[act])
+    X, Y, R = map(np.concatenate, (X, Y, R))
+    h = 1.0 / 600
+    ys = []
+    for x0 in xs:
+        sel = (np.abs(X - x0) < 0.6 * h) & (Y > face(x0) + 2 * h) & (Y < 0.5)
+        y, r = Y[sel], R[sel]
+        o = np.argsort(y)
+        y, r = y[o], r[o]
+        above = np.flatnonzero(r >= rho_mid)
+        k = above.max()  # last point of the shock layer going up
+        y0 = y[k] + (y[k + 1] - y[k]) * (r[k] - rho_mid) / (r[k] - r[k + 1])
+        ys.append(y0)
+    slope = np.polyfit(xs, ys, 1)[0]
+    return np.rad2deg(np.arctan(slope))
+
+
+def test_wedge_shock_angle():
+    """Small decomposition run to t = 0.06 (the stream passes the face
+    length 1.5 times): the shock off the upper face between 30 % and 90 % of
+    the face lies within 2 degrees of the inviscid weak-branch angle for the
+    face's 15-degree deflection."""
+    specs = W.wedge_tunnel(600, 48, 96, mach=M)
+    w = W.wedge_state(specs, quiescent_wake=True, mach=M)
+    blob = np.load(GOLD)["params"]
+    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, sdnn_weights=blob))
+    for p in range(len(specs)):
+        S.set_state(p, w[p])
+    t = 0.0
+    while t < 0.06:
+        t = S.advance(5 * 100, sync=True)
+    geo = W.wedge_geometry(1.0)
+    face = lambda x: geo["Yc"] + (x - geo["Xt"]) * np.tan(geo["theta"])
+    beta = np.rad2deg(exact.weak_shock_angle(geo["theta"], M))
+    Mn = M * np.sin(np.deg2rad(beta))
+    rho2 = 1.4 * 2.4 * Mn ** 2 / (0.4 * Mn ** 2 + 2.0)
+    xs = geo["Xt"] + (geo["Xr"] - geo["Xt"]) * np.linspace(0.3, 0.9, 13)
+    ang = _shock_angle(S, specs, xs, face, 0.5 * (1.4 + rho2))
+    print(f"Mach {M}: shock angle {ang:.2f} deg at t = {t:.4f}, theta-beta-M {beta:.2f} deg")
+    assert abs(ang - beta) < 2.0
+
+
+def test_wedge_full_size_graph_and_split_bf16():
+    specs = W.wedge_tunnel(mach=M)
+    assert 230 <= len(specs) <= 260
+    w = W.wedge_state(specs, quiescent_wake=True, mach=M)
+    res = {}
+    for name, prec, graph in (("graph", "fp64", True), ("eager", "fp64", False), ("bf16x3", "bf16x3", True)):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, use_graph=graph,
+                                               precision=prec), stream=stream)
+            for p in range(len(specs)):
+                S.set_state(p, w[p])
+            S.advance(5, sync=True)
+            res[name] = [S.cons(p) for p in range(len(specs))]
+            if name == "graph":
+                S.advance(10, sync=True)  # raises if the state turns non-finite or non-physical
+            del S
+        torch.cuda.synchronize()
+    for p in range(len(specs)):
+        assert np.array_equal(res["graph"][p], res["eager"][p]), p
+    scale = max(np.abs(r).max() for r in res["graph"])
+    err = max(np.abs(a - b).max() for a, b in zip(res["bf16x3"], res["graph"])) / scale
+    assert err < 1e-4, err

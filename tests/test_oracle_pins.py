@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import euler, fcgram, sdnn, solver, ssprk
+from oracle import euler, fcgram, patches, sdnn, solver, ssprk
 
 
 # ---------------------------------------------------------------- viscous term
@@ -151,18 +151,39 @@ def test_filter_operator_is_applied_along_both_directions():
 # ---------------------------------------------------------------- time step
 def test_timestep_closed_form():
     """Uniform state on a Cartesian patch of spacing h: dt = CFL h / (|u| + a)
-    without viscosity, CFL h^2 / (4 mu) where that is smaller."""
+    without viscosity, CFL h^2 / (4 mu) where that is smaller (h from the
+    FC-derived metric: d = 5 rounding, about 1e-13 relative)."""
     h = 0.1
     spec = W.box_patch(0.0, 3.0, 0.0, 2.0, 31, 21, {k: W.OUTFLOW for k in "WESN"})
     S = solver.Solver(solver.patches_from_specs([spec]), solver.Params(fc_d=5, fc_C=27, cfl=0.5))
     rho, u, v, p = 1.4, 3.0, 4.0, 1.0  # |u| = 5, a = 1
     S.set_prim([np.broadcast_to(np.array([rho, u, v, p])[:, None, None], (4,) + spec.shape)])
-    assert abs(S.timestep(S.U, None) - 0.5 * h / 6.0) < 1e-15
+    rel = lambda a, b: abs(a - b) / b
+    assert rel(S.timestep(S.U, None), 0.5 * h / 6.0) < 1e-12
     mu = np.full(S.U.shape[1], 0.2)
     zero = np.zeros_like(mu)
-    assert abs(S.timestep(S.U, (mu, zero, zero)) - 0.5 * h * h / 0.8) < 1e-15
+    assert rel(S.timestep(S.U, (mu, zero, zero)), 0.5 * h * h / 0.8) < 1e-12
     mu[:] = 1e-4  # inviscid limit smaller again
-    assert abs(S.timestep(S.U, (mu, zero, zero)) - 0.5 * h / 6.0) < 1e-15
+    assert rel(S.timestep(S.U, (mu, zero, zero)), 0.5 * h / 6.0) < 1e-12
+
+
+@pytest.mark.parametrize("alpha_deg", [90.0, 75.0, 30.0])
+def test_mesh_size_of_skewed_cells(alpha_deg):
+    """On a parallelogram grid of spacing h and cell angle alpha the mesh
+    size of the step-size limits is the distance between neighbouring grid
+    lines along the most compressed direction, 1 / sqrt of the largest
+    eigenvalue of the metric tensor built from the dual basis of the two
+    cell edges: h sin(alpha) / sqrt(1 + |cos(alpha)|) (h when alpha = 90,
+    0.366 h at the 30-degree cells of a wedge apex)."""
+    h, a = 0.01, np.deg2rad(alpha_deg)
+    e1, e2 = np.array([h, 0.0]), np.array([h * np.cos(a), h * np.sin(a)])
+    I, J = np.meshgrid(np.arange(24.0), np.arange(20.0))
+    spec = W.PatchSpec(I * e1[0] + J * e2[0], I * e1[1] + J * e2[1], None, {k: W.OUTFLOW for k in "WESN"})
+    g = patches.Grid(solver.patches_from_specs([spec])[0], 2, 27, 5)
+    dual = np.linalg.inv(np.column_stack([e1, e2]))  # rows: grad q1, grad q2 (index units)
+    lam = np.linalg.eigvalsh(dual @ dual.T).max()
+    assert np.allclose(g.hx, 1.0 / np.sqrt(lam), rtol=1e-9, atol=0)
+    assert np.allclose(g.hx, h * np.sin(a) / np.sqrt(1.0 + abs(np.cos(a))), rtol=1e-9, atol=0)
 
 
 def _stability_function():
