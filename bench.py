@@ -1,21 +1,27 @@
 """Benchmark of the FC-SDNN per-stage hot path on one MI355X.
 
-Workload: the Mach-3 step channel ([0, 3] x [0, 1] with a step over
-[0.6, 3] x [0, 0.2]; 22 overlapping subpatches of up to 112 x 109 points on a
-h = 1/250 lattice, with one L-shaped C1 corner patch and one C2 corner patch;
-inflow rho = 1.4, p = 1, u = 3; slip walls; SDNN artificial viscosity with
-a classifier trained on the GPU by the library's own kernels at set-up;
-spectral filter; adaptive step at CFL 0.5).  One benchmark step is one
-solver time step: viscosity (classification, smoothing, blend), filter,
-step size and the five SSPRK stages (fluxes, grouped FC derivative
-contractions, viscous terms, update, boundary conditions, fringe
-interpolation), replayed as one captured hipGraph.
+Workload (the large single-GPU configuration): Mach-5 flow past a wedge with
+a blunt rear face in the tunnel [0, 1] x [0, 0.5] (15-degree faces, tip at
+(0.2, 0.25), rear face at x = 0.4): 244 overlapping subpatches of uneven
+sizes (C1 corner subpatches at the tip and the rear corners, skewed-affine
+subpatches on the faces, seeded lattice subpatches), 1.15e7 points at
+h = 1/4400; SDNN artificial viscosity with a classifier trained on the GPU by
+the library's own kernels at set-up; spectral filter; adaptive step at CFL
+0.5.  One benchmark step is one solver time step: viscosity
+(classification, smoothing, blend), filter, step size and the five SSPRK
+stages (fluxes, grouped FC derivative contractions, viscous terms, update,
+boundary conditions, fringe interpolation), replayed as one captured
+hipGraph.
 
-Prints one JSON line: point-stage updates/s of the plain FP64 form (the
-configuration as stated) and, in ``mixed``, of the split-BF16 contraction
-form with its error against the FP64 run at equal step counts; the roofline
-of the dominant kernel (the grouped contraction, timed with HIP events on
-the solver stream) and the CPU oracle timed on a bounded sample.
+Prints one JSON line.  ``value``: point-stage updates/s of the mixed-precision
+batched form (split-BF16 contractions with FP32 accumulation and FP64
+recombination, FP64 state); ``fp64``: the plain FP64 form on the same
+workload and steps; ``fp32``: FP32 contractions.  Per-field max / RMS
+differences from the FP64 run after the timed steps, and with the
+smoothness classes frozen to the FP64 run's (the precision alone).  The
+roofline of the dominant kernel (the grouped stage contraction, timed with
+HIP events on the solver stream); the CPU oracle on a bounded sample of the
+same workload.
 """
 from __future__ import annotations
 
@@ -30,44 +36,35 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16x3": 2.5e15}
-# HBM bytes per stage-contraction launch on the step channel (FP64): the
-# launches the roofline times (the last step's stage contraction, back to
-# back), from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by the
-# factors a 256 MiB copy gives in the same runs.  The work per launch follows
-# the flow (viscous lines are skipped where mu vanishes), so a figure holds
-# for its kernel after the same number of steps and warm-up steps, and for
-# the kernels as they were when the counters were taken.
-STAGE_TRAFFIC_FP64 = {
-    # profiles/stage_contraction_fp64_traffic.md (fetched + written MB)
-    ("k_gemm_fp<double, 8, 1, 4, 2>", 2000, 20): 52.25e6,  # 28.58 + 23.67
-    ("k_gemm_fp<double, 16, 1, 4, 1>", 2000, 20): 52.08e6,  # 28.55 + 23.53
-    ("k_gemm_fp<double, 16, 1, 3, 2>", 2000, 20): 52.91e6,  # 29.55 + 23.36
-}
+PEAK = {"fp64": 78.6e12, "fp32": 157.3e12, "bf16": 2.5e15}
 HBM_PEAK = 8.0e12
+
+
+def log(msg):
+    """One progress line on stderr per finished phase of the bench."""
+    print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-extras", action="store_true", help="skip the derivative-sweep and classifier measurements")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the step channel, derivative-sweep and classifier measurements")
+    ap.add_argument("--forms", default="bf16x3,fp64,fp32",
+                    help="contraction precisions to run on the wedge (the first is the headline value)")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying step graphs "
                                                            "(for per-dispatch counter runs)")
     ap.add_argument("--calibration-copy", action="store_true",
                     help="finish with three plain 256 MiB device copies (byte-counter calibration)")
     ap.add_argument("--stage-variant", default=None,
-                    help="pin the FP64 stage-contraction tile shape (a kernel name as reported in roofline.kernel) "
+                    help="pin the stage-contraction tile shape (a kernel name as reported in roofline.kernel) "
                          "instead of tuning it (for counter runs, whose dispatch serialization skews the tuner)")
-    ap.add_argument("--no-tiled", action="store_true",
-                    help="skip the tiled step channel at 1.17e7 points (FP64 and split-BF16, 500 steps)")
-    ap.add_argument("--tiled-steps", type=int, default=500)
-    ap.add_argument("--tiled-only", action="store_true",
-                    help="run only the tiled step channel (for its kernel profile); prints its object alone")
-    ap.add_argument("--cpu-steps", type=int, default=10)
+    ap.add_argument("--tiled", action="store_true",
+                    help="also run the tiled step channel at 1.17e7 points (FP64 and split-BF16)")
+    ap.add_argument("--cpu-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -154,13 +151,13 @@ def classifier_bench(F, W, torch, weights):
     return out
 
 
-def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=None):
+def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=None, state=None, av="sdnn"):
     specs = W.step_channel() if specs is None else specs
-    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, use_graph=use_graph,
+    prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av=av, filter=True, use_graph=use_graph,
                          precision=precision, sdnn_weights=weights, autotune=True)
     with torch.cuda.stream(stream):
         S = F.Solver(specs, prm, stream=stream)
-        w = W.uniform_state(specs, W.STEP_INFLOW)
+        w = W.uniform_state(specs, W.STEP_INFLOW) if state is None else state
         for p in range(len(specs)):
             S.set_state(p, w[p])
     return S, specs
@@ -168,7 +165,7 @@ def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=N
 
 def timed_run(S, torch, stream, steps, warmup, retune=True):
     # The first advance tunes the contraction tile on the initial state, where
-    # no viscous line is active yet; the last warm-up step tunes it again on
+    # few viscous lines are active; the last warm-up step tunes it again on
     # the developed flow (and captures the step graphs anew).
     if warmup > 0 and retune:
         S.advance(5 * (warmup - 1), sync=True)
@@ -186,19 +183,32 @@ def timed_run(S, torch, stream, steps, warmup, retune=True):
     return el
 
 
+def _active(specs, p):
+    return specs[p].mask if specs[p].mask is not None else np.ones(specs[p].shape, bool)
+
+
 def field_errors(ref_solver, solver, specs):
     """Per-field max and RMS difference over all active points, relative to
     the field's largest magnitude in the reference run."""
     errs = {}
     for name in ("rho", "mx", "my", "E"):
-        sel = [specs[p].mask if specs[p].mask is not None else np.ones(specs[p].shape, bool)
-               for p in range(len(specs))]
-        ref = np.concatenate([ref_solver.field(p, name)[sel[p]] for p in range(len(specs))])
-        got = np.concatenate([solver.field(p, name)[sel[p]] for p in range(len(specs))])
+        ref = np.concatenate([ref_solver.field(p, name)[_active(specs, p)] for p in range(len(specs))])
+        got = np.concatenate([solver.field(p, name)[_active(specs, p)] for p in range(len(specs))])
         d = got - ref
         scale = max(np.abs(ref).max(), 1e-300)
         errs[name] = {"max_rel": float(np.abs(d).max() / scale), "rms_rel": float(np.sqrt((d * d).mean()) / scale)}
     return errs
+
+
+def class_flips(a, b, specs):
+    """Points whose smoothness class (either direction) differs between two
+    runs' last steps."""
+    n = 0
+    for p in range(len(specs)):
+        m = _active(specs, p)
+        for d in ("tau0", "tau1"):
+            n += int((a.field(p, d)[m] != b.field(p, d)[m]).sum())
+    return n
 
 
 def contraction_profile(S, torch, nsteps=20, reps=50):
@@ -215,61 +225,162 @@ def contraction_profile(S, torch, nsteps=20, reps=50):
     return alone, graph
 
 
-def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
-    """The step channel tiled by 235 subpatches of uneven sizes (sides drawn
-    from 150-300; 1.17e7 points, C1 and C2 corner patches): FP64 and
-    split-BF16 runs of the same steps from the uniform inflow state, their
-    throughput and the per-field difference of the split-BF16 state from the
-    FP64 one after the run."""
-    specs = W.step_channel_tiled()
-    npts = int(sum(s.npoints() for s in specs))
-    out = {"workload": "Mach-3 step channel tiled by %d subpatches of sides 150-300 (seeded), %d points, "
-                       "SDNN viscosity, filter, CFL 0.5, FC-Gram d=2 C=27" % (len(specs), npts),
-           "points": npts, "subpatches": len(specs), "steps": steps, "warmup": warmup}
+def roofline_of(prof, precision, kernel):
+    """Roofline entries of a stage contraction timed alone: achieved
+    algorithmic HBM bytes per second against HBM, and dense MFMA flops
+    (2n per point per line operation) against the precision's MFMA peak
+    (split BF16: the BF16 peak, three products per product)."""
+    sec = prof["avg_ms"] * 1e-3
+    gbps = prof["bytes"] / sec
+    flops = prof["flops"] / sec
+    mfma_peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"]}[precision]
+    mfma_rate = flops * (3.0 if precision == "bf16x3" else 1.0)
+    return {"kernel": kernel, "avg_launch_ms": prof["avg_ms"], "launches_timed": prof["launches"],
+            "algorithmic_bytes_per_launch": prof["bytes"], "dense_flops_per_launch": prof["flops"],
+            "hbm": {"achieved_GBps": gbps / 1e9, "peak_GBps": HBM_PEAK / 1e9, "frac": gbps / HBM_PEAK},
+            "mfma": {"achieved_TFLOPs": mfma_rate / 1e12, "peak_TFLOPs": mfma_peak / 1e12,
+                     "frac": mfma_rate / mfma_peak,
+                     "fp32_equivalent_frac": flops / PEAK["fp32"]}}
+
+
+def wedge_run(F, W, torch, weights, forms, steps, warmup, eager=False, stage_variant=None):
+    """The wedge tunnel in each contraction precision, from the same initial
+    state and for the same steps; the per-field differences from the FP64
+    run (after the timed steps, and over 10 steps with the classes frozen to
+    the FP64 run's), and each form's stage contraction timed alone."""
     from paper_2506_19370_amd import _lib as L
+    specs = W.wedge_tunnel()
+    w0 = W.wedge_state(specs)
+    npts = int(sum(s.npoints() for s in specs))
+    out = {"workload": "Mach-%g wedge tunnel [0,1]x[0,0.5], 15-degree faces, blunt rear face: %d subpatches "
+                       "(3 C1 corner, skewed-affine face, rear-face and seeded lattice subpatches, sides 150-300), "
+                       "%d points (h = 1/4400), SDNN viscosity (GPU-trained), filter, CFL 0.5, FC-Gram d=2 C=27"
+                       % (W.WEDGE_MACH, len(specs), npts),
+           "points": npts, "subpatches": len(specs), "stages_per_step": 5}
     solvers = {}
-    for prec in ("fp64", "bf16x3"):
+    for prec in forms:
         stream = torch.cuda.Stream()
         t0 = time.perf_counter()
-        S, _ = make_solver(F, W, torch, weights, prec, stream, specs=specs)
+        S, _ = make_solver(F, W, torch, weights, prec, stream, use_graph=not eager, specs=specs, state=w0)
         setup = time.perf_counter() - t0
-        el = timed_run(S, torch, stream, steps, warmup)
-        out[prec] = {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "ms_per_step": el / steps * 1e3,
-                     "stage_kernel": L.gemm_variant_name(prec, S.stats()["stage_variant"]),
-                     "host_setup_s": setup}
-        if prec == "fp64":
-            # the last step's stage contraction alone (useful flops of the
-            # lines that step needed), as for the roofline of the main run
-            pr = S.profile_stage(20)
-            ach = pr["flops"] / (pr["avg_ms"] * 1e-3)
-            out[prec]["stage_contraction"] = {"avg_launch_ms": pr["avg_ms"], "flops_per_launch": pr["flops"],
-                                              "achieved_tflops": ach / 1e12, "frac_of_fp64_peak": ach / PEAK["fp64"],
-                                              "algorithmic_bytes_per_launch": pr["bytes"]}
-        solvers[prec] = S
-    out["bf16x3"]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out["bf16x3"]["ms_per_step"]
-    out["bf16x3"]["error_vs_fp64_after_%d_steps" % (steps + warmup)] = field_errors(solvers["fp64"],
-                                                                                     solvers["bf16x3"], specs)
+        if stage_variant:
+            S.set_stage_variant(stage_variant)
+        el = timed_run(S, torch, stream, steps, warmup, retune=not stage_variant)
+        kernel = L.gemm_variant_name(prec, S.stats()["stage_variant"])
+        prof, gprof = contraction_profile(S, torch, nsteps=min(20, max(steps, 1)))
+        out[prec] = {"value": npts * 5 * steps / el, "ms_per_step": el / steps * 1e3, "host_setup_s": setup,
+                     "stage_contraction": roofline_of(prof, prec, kernel),
+                     "in_graph_event_bracket_ms": gprof["avg_ms"], "event_pair_latency_ms": gprof["event_latency_ms"]}
+        solvers[prec] = (S, stream)
+        log("wedge %s: %.3f ms per step, set-up %.1f s" % (prec, out[prec]["ms_per_step"], setup))
+    if "fp64" in solvers:
+        ref = solvers["fp64"][0]
+        nst = steps + warmup + min(20, max(steps, 1))
+        for prec in forms:
+            if prec == "fp64":
+                continue
+            out[prec]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out[prec]["ms_per_step"]
+            out[prec]["error_vs_fp64_after_%d_steps" % nst] = field_errors(ref, solvers[prec][0], specs)
+            out[prec]["class_flips_vs_fp64_last_step"] = class_flips(ref, solvers[prec][0], specs)
+        # the precision alone: both forms from the FP64 run's state, 10 steps
+        # with the classes of that state's last step frozen
+        state = [ref.cons(p) for p in range(len(specs))]
+        tau = [np.stack([ref.field(p, "tau0"), ref.field(p, "tau1")]).astype(np.uint8) for p in range(len(specs))]
+        t_now = ref.stats()["t"]
+        frozen = {}
+        for prec in forms:
+            stream = torch.cuda.Stream()
+            with torch.cuda.stream(stream):
+                Sf = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="frozen", filter=True,
+                                                    precision=prec), stream=stream)
+                for p in range(len(specs)):
+                    Sf.set_state(p, state[p], prim=False)
+                    Sf.set_tau(p, tau[p])
+                Sf.set_time(t_now)
+                Sf.advance(5 * 10, sync=True)
+            frozen[prec] = Sf
+        log("wedge frozen-class runs done")
+        for prec in forms:
+            if prec != "fp64":
+                out[prec]["error_vs_fp64_frozen_classes_10_steps"] = field_errors(frozen["fp64"], frozen[prec], specs)
+        del frozen
     del solvers
     torch.cuda.synchronize()
     return out
 
 
-def cpu_baseline(W, steps):
+def channel_run(F, W, torch, weights, steps, warmup):
+    """The Mach-3 step channel (22 subpatches, 208586 points): FP64 and the
+    mixed forms, throughput and speed-up."""
+    out = {"workload": "Mach-3 step channel [0,3]x[0,1], step [0.6,3]x[0,0.2], 22 subpatches (C1 L-shaped + C2 "
+                       "corner patches), 208586 points, SDNN viscosity, filter, CFL 0.5, FC-Gram d=2 C=27"}
+    stream = torch.cuda.Stream()
+    for prec in ("fp64", "fp32", "bf16x3"):
+        S, specs = make_solver(F, W, torch, weights, prec, stream)
+        npts = int(sum(s.npoints() for s in specs))
+        el = timed_run(S, torch, stream, steps, warmup)
+        out[prec] = {"value": npts * 5 * steps / el, "ms_per_step": el / steps * 1e3}
+        del S
+    for prec in ("fp32", "bf16x3"):
+        out[prec]["speedup_vs_fp64"] = out["fp64"]["ms_per_step"] / out[prec]["ms_per_step"]
+    return out
+
+
+def tiled_channel_run(F, W, torch, weights, steps, warmup=5):
+    """The step channel tiled by 235 subpatches of uneven sizes (1.17e7
+    points): FP64 and split-BF16 throughput."""
+    specs = W.step_channel_tiled()
+    npts = int(sum(s.npoints() for s in specs))
+    out = {"workload": "Mach-3 step channel tiled by %d subpatches of sides 150-300, %d points" % (len(specs), npts)}
+    for prec in ("fp64", "bf16x3"):
+        stream = torch.cuda.Stream()
+        S, _ = make_solver(F, W, torch, weights, prec, stream, specs=specs)
+        el = timed_run(S, torch, stream, steps, warmup)
+        out[prec] = {"value": npts * 5 * steps / el, "ms_per_step": el / steps * 1e3}
+        del S
+    return out
+
+
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(W, weights, steps):
+    """The oracle on a bounded sample of the headline workload: the same
+    wedge tunnel, Mach number, initial data, SDNN weights, filter and CFL on
+    the small decomposition (h = 1/600, 72 subpatches), its first steps
+    (set-up not timed), with NumPy/SciPy on the host's cores."""
     from threadpoolctl import threadpool_limits
     from oracle import solver as osolver
-    specs = W.step_channel()
-    with threadpool_limits(limits=1):
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:  # pragma: no cover
+        ncpu = os.cpu_count() or 1
+    threads = max(1, min(16, ncpu))
+    specs = W.wedge_tunnel(600, 48, 96)
+    with threadpool_limits(limits=threads):
         O = osolver.Solver(osolver.patches_from_specs(specs),
-                           osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
-        O.set_prim(W.uniform_state(specs, W.STEP_INFLOW))
+                           osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True),
+                           sdnn_params=W.sdnn_unblob(weights))
+        O.set_prim(W.wedge_state(specs))
+        log("oracle set up (%d subpatches)" % len(specs))
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for k in range(steps):
             O.step()
+            log("oracle step %d" % (k + 1))
         el = time.perf_counter() - t0
     npts = int(sum(s.npoints() for s in specs))
-    return {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"step channel, first {steps} steps (modal-indicator viscosity, filter), "
-                      f"{npts} points, FP64 NumPy, 1 thread, {el:.1f} s"}
+    return {"value": npts * 5 * steps / el, "unit": "point-stage updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"wedge tunnel at h = 1/600 ({len(specs)} subpatches, {npts} points; same Mach number, "
+                      f"initial data, SDNN weights, filter and CFL as the GPU run), first {steps} steps, "
+                      f"FP64 NumPy/SciPy, {el:.1f} s",
+            "host": {"nproc": os.cpu_count(), "affinity_cpus": ncpu, "threads_used": threads, "cpu_model": _cpu_model()}}
 
 
 def main():
@@ -282,75 +393,41 @@ def main():
     import paper_2506_19370_amd as F
     import workloads as W
 
+    forms = [f for f in a.forms.split(",") if f]
     weights = train_classifier(F, W, torch)
-    if a.tiled_only:
-        print(json.dumps({"tiled_channel": tiled_channel_run(F, W, torch, weights, a.tiled_steps)}))
-        return
-    stream = torch.cuda.Stream()
-    S, specs = make_solver(F, W, torch, weights, "fp64", stream, use_graph=not a.eager)
-    if a.stage_variant:
-        S.set_stage_variant(a.stage_variant)
-    npts = int(sum(s.npoints() for s in specs))
-    el = timed_run(S, torch, stream, a.steps, a.warmup, retune=not a.stage_variant)
-    value = npts * 5 * a.steps / el
-    prof, gprof = contraction_profile(S, torch)
-    kernel_ms = prof["avg_ms"]
-    achieved = prof["flops"] / (kernel_ms * 1e-3)
-    from paper_2506_19370_amd import _lib as L
-    kernel = L.gemm_variant_name("fp64", S.stats()["stage_variant"])
-    traffic = STAGE_TRAFFIC_FP64.get((kernel, a.steps, a.warmup))
+    log("classifier trained")
+    wedge = wedge_run(F, W, torch, weights, forms, a.steps, a.warmup, eager=a.eager, stage_variant=a.stage_variant)
+    head = forms[0]
+    rf = wedge[head]["stage_contraction"]
+    dtype = {"bf16x3": "bf16x3+f64", "fp32": "f32+f64", "fp64": "f64"}[head]
     out = {
         "metric": "point-stage updates/s, plain FP64 vs mixed-precision batched form at stated error",
-        "value": value, "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
-        "ms_per_step": el / a.steps * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "Mach-3 step channel [0,3]x[0,1], step [0.6,3]x[0,0.2], 22 subpatches "
-                               "(C1 L-shaped + C2 corner patches), %d points, SDNN viscosity (GPU-trained), "
-                               "filter, CFL 0.5, FC-Gram d=2 C=27" % npts,
-                   "points": npts, "stages_per_step": 5},
-        "roofline": {"bound": "mfma", "kernel": kernel + " (grouped FC stage contraction, autotuned tile)",
-                     "achieved": achieved / 1e12, "peak": PEAK["fp64"] / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / PEAK["fp64"], "traffic": traffic, "traffic_unit": "bytes per launch",
-                     "avg_launch_ms": kernel_ms, "launches_timed": prof["launches"],
-                     "timing": "the last step's stage contraction, launches back to back between HIP events",
-                     "in_graph_event_bracket_ms": gprof["avg_ms"], "event_pair_latency_ms": gprof["event_latency_ms"],
-                     "flops_per_launch": prof["flops"],
-                     "algorithmic_bytes_per_launch": prof["bytes"]},
+        "value": wedge[head]["value"], "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps,
+        "warmup": a.warmup, "ms_per_step": wedge[head]["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": wedge["workload"], "form": head, "points": wedge["points"],
+                   "subpatches": wedge["subpatches"], "stages_per_step": 5},
+        "roofline": {"bound": "hbm", "kernel": rf["kernel"] + " (grouped FC stage contraction, autotuned tile)",
+                     "achieved": rf["hbm"]["achieved_GBps"], "peak": rf["hbm"]["peak_GBps"], "unit": "GB/s",
+                     "frac": rf["hbm"]["frac"], "traffic": None,
+                     "achieved_from": "algorithmic bytes of one launch (FP64 operand lines read once, derivatives "
+                                      "written once, the lines that step needs) / average launch time",
+                     "avg_launch_ms": rf["avg_launch_ms"], "mfma": rf["mfma"],
+                     "timing": "the last step's stage contraction, launches back to back between HIP events"},
+        "wedge": wedge,
     }
-    if not a.no_mixed:
-        # mixed forms: FP32 or split-BF16 contractions, FP64 state and stage arithmetic
-        forms = {}
-        for prec, desc in (("fp32", "FP32 contractions on MFMA (FP32 accumulate), FP64 state"),
-                           ("bf16x3", "split-BF16 x3 contractions (FP32 accumulate, FP64 recombination), FP64 state")):
-            Sm, _ = make_solver(F, W, torch, weights, prec, stream)
-            elm = timed_run(Sm, torch, stream, a.steps, a.warmup)
-            pm, _ = contraction_profile(Sm, torch)
-            err_long = field_errors(S, Sm, specs)
-            # short horizons: fresh runs from the same state
-            errs = {}
-            for nst in (1, 10):
-                S_ref, _ = make_solver(F, W, torch, weights, "fp64", stream)
-                S_mix, _ = make_solver(F, W, torch, weights, prec, stream)
-                S_ref.advance(5 * nst, sync=True)
-                S_mix.advance(5 * nst, sync=True)
-                errs["error_vs_fp64_after_%d_steps" % nst] = field_errors(S_ref, S_mix, specs)
-                del S_ref, S_mix
-            forms[prec] = {"precision": desc, "batched": "hipGraph of whole steps, one contraction launch per stage",
-                           "value": npts * 5 * a.steps / elm, "ms_per_step": elm / a.steps * 1e3,
-                           "speedup_vs_fp64": el / elm, **errs,
-                           "error_vs_fp64_after_%d_steps" % (a.steps + a.warmup + 20): err_long,
-                           "contraction_avg_ms": pm["avg_ms"]}
-            del Sm
-        best = max(forms, key=lambda k: forms[k]["value"])
-        out["mixed"] = {"best": best, **forms}
     if not a.no_extras:
+        out["step_channel"] = channel_run(F, W, torch, weights, min(a.steps, 2000), a.warmup)
+        log("step channel done")
         out["derivative_sweep"] = sweep_bench(F, W, torch)
+        log("derivative sweep done")
         out["classifier"] = classifier_bench(F, W, torch, weights)
-    if not a.no_tiled:
-        del S
-        out["tiled_channel"] = tiled_channel_run(F, W, torch, weights, a.tiled_steps)
+        log("classifier throughput done")
+    if a.tiled:
+        out["tiled_channel"] = tiled_channel_run(F, W, torch, weights, a.steps)
     if not a.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(W, a.cpu_steps)
+        out["cpu_baseline"] = cpu_baseline(W, weights, a.cpu_steps)
+        log("cpu baseline done")
     if a.calibration_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
