@@ -1,13 +1,13 @@
 """Benchmark of the FC-SDNN per-stage hot path on one MI355X.
 
-Workload (the large single-GPU configuration): Mach-5 flow past a wedge with
+Workload (the large single-GPU configuration): Mach-10 flow past a wedge with
 a blunt rear face in the tunnel [0, 1] x [0, 0.5] (15-degree faces, tip at
 (0.2, 0.25), rear face at x = 0.4): 244 overlapping subpatches of uneven
 sizes (C1 corner subpatches at the tip and the rear corners, skewed-affine
 subpatches on the faces, seeded lattice subpatches), 1.15e7 points at
 h = 1/4400; SDNN artificial viscosity with a classifier trained on the GPU by
-the library's own kernels at set-up; spectral filter; adaptive step at CFL
-0.5.  One benchmark step is one solver time step: viscosity
+the library's own kernels at set-up; localized smearing of the initial data
+in the first step; spectral filter; adaptive step at CFL 0.5.  One benchmark step is one solver time step: viscosity
 (classification, smoothing, blend), filter, step size and the five SSPRK
 stages (fluxes, grouped FC derivative contractions, viscous terms, update,
 boundary conditions, fringe interpolation), replayed as one captured
@@ -65,37 +65,68 @@ def parse():
     ap.add_argument("--tiled", action="store_true",
                     help="also run the tiled step channel at 1.17e7 points (FP64 and split-BF16)")
     ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--classifier-lines", type=int, default=100_000,
+                    help="synthetic lines for training the classifier (10 %% held out)")
     return ap.parse_args()
 
 
-def train_classifier(F, W, torch, steps=300, batch=4096):
+def train_classifier(F, W, torch, nlines=100_000, epochs=1, batch=8192, lr=1e-3):
     """Seeded training of the smoothness classifier on the GPU: synthetic
     lines through the solver's FC filter (d = 2, C = 27), 16-point windows,
-    class-weighted Adam with the library's training kernels."""
-    lines, pos, amp = W.classifier_lines(3000, seed_salt=51)
-    filt = F.lines_apply(torch.tensor(lines, device="cuda"), "filter", 2, 27)
+    class-weighted Adam with the library's training kernels; 10 % of the
+    lines held out.  Returns the weights and, on the held-out windows, the
+    accuracy and confusion matrix (rows: true class) of the trained network
+    and of the modal-decay fallback."""
+    t0 = time.perf_counter()
+    lines, pos, amp = W.classifier_lines(nlines, seed_salt=51)
     lab = W.window_labels(pos, amp, lines)
+    filt = F.lines_apply(torch.tensor(lines, device="cuda"), "filter", 2, 27)
     n = lines.shape[1]
     start = np.clip(np.arange(n) - 8, 0, n - 16)
     idx = torch.tensor(start[:, None] + np.arange(16)[None, :], device="cuda")
-    wins = filt[:, idx].reshape(-1, 16)
-    lo = wins.min(dim=1, keepdim=True).values
-    hi = wins.max(dim=1, keepdim=True).values
-    am = wins.abs().max(dim=1, keepdim=True).values
-    rng_ = hi - lo
-    keep = (rng_ >= 1e-3 * torch.clamp(am, min=1.0)).squeeze(1)
-    x = ((wins - lo) / torch.where(rng_ > 0, rng_, torch.ones_like(rng_)))[keep].float().contiguous()
-    y = torch.tensor(lab.reshape(-1), device="cuda")[keep].int().contiguous()
+    ntrain = nlines - nlines // 10
+    wins = filt[:, idx]  # (lines, n, 16)
+    labt = torch.tensor(lab, device="cuda")
+
+    def prep(w, y):
+        w = w.reshape(-1, 16)
+        y = y.reshape(-1)
+        lo = w.min(dim=1, keepdim=True).values
+        hi = w.max(dim=1, keepdim=True).values
+        am = w.abs().max(dim=1, keepdim=True).values
+        rng_ = hi - lo
+        keep = (rng_ >= 1e-3 * torch.clamp(am, min=1.0)).squeeze(1)
+        x = ((w - lo) / torch.where(rng_ > 0, rng_, torch.ones_like(rng_)))[keep].float().contiguous()
+        return x, y[keep].int().contiguous(), w, y
+
+    x, y, _, _ = prep(wins[:ntrain], labt[:ntrain])
     counts = torch.bincount(y, minlength=3).double()
     cw = (counts.sum() / (3.0 * torch.clamp(counts, min=1.0))).float()
     g = W.rng(4, 52)
     params = torch.tensor(W.sdnn_blob(W.sdnn_init(g)), device="cuda")
-    tr = F.SdnnTrainer(params, batch=batch, lr=2e-3)
-    for _ in range(steps):
-        sel = torch.tensor(g.integers(0, y.numel(), batch), device="cuda")
+    tr = F.SdnnTrainer(params, batch=batch, lr=lr)
+    nsteps = max(1, int(epochs * y.numel() // batch))
+    perm = torch.randperm(y.numel(), generator=torch.Generator().manual_seed(52)).to("cuda")
+    for s_ in range(nsteps):
+        sel = perm[(s_ * batch) % max(1, y.numel() - batch):][:batch]
         tr.step(x[sel].contiguous(), y[sel].contiguous(), cw)
     torch.cuda.synchronize()
-    return params.cpu().numpy()
+    train_s = time.perf_counter() - t0
+    # held-out lines: raw windows through both classifiers (flat windows are
+    # smooth by the classifiers' own rule)
+    hw = wins[ntrain:].reshape(-1, 16).contiguous()
+    hy = labt[ntrain:].reshape(-1).cpu().numpy()
+    ev = {}
+    for name, tau in (("sdnn", F.sdnn_infer(params, hw)), ("modal", F.modal_infer(hw))):
+        t = tau.cpu().numpy().astype(np.int64)
+        conf = np.zeros((3, 3), dtype=np.int64)
+        np.add.at(conf, (hy, t), 1)
+        ev[name] = {"accuracy": float((t == hy).mean()),
+                    "recall_per_class": [float(conf[c, c] / max(conf[c].sum(), 1)) for c in range(3)],
+                    "confusion_true_by_predicted": conf.tolist()}
+    info = {"lines": nlines, "train_lines": ntrain, "train_windows": int(y.numel()), "batch": batch,
+            "steps": nsteps, "epochs": epochs, "train_s": train_s, "heldout_windows": int(hy.size), **ev}
+    return params.cpu().numpy(), info
 
 
 def sweep_bench(F, W, torch):
@@ -151,10 +182,11 @@ def classifier_bench(F, W, torch, weights):
     return out
 
 
-def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=None, state=None, av="sdnn"):
+def make_solver(F, W, torch, weights, precision, stream, use_graph=True, specs=None, state=None, av="sdnn",
+                smear=False):
     specs = W.step_channel() if specs is None else specs
     prm = F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av=av, filter=True, use_graph=use_graph,
-                         precision=precision, sdnn_weights=weights, autotune=True)
+                         precision=precision, sdnn_weights=weights, autotune=True, smear=smear)
     with torch.cuda.stream(stream):
         S = F.Solver(specs, prm, stream=stream)
         w = W.uniform_state(specs, W.STEP_INFLOW) if state is None else state
@@ -254,14 +286,15 @@ def wedge_run(F, W, torch, weights, forms, steps, warmup, eager=False, stage_var
     npts = int(sum(s.npoints() for s in specs))
     out = {"workload": "Mach-%g wedge tunnel [0,1]x[0,0.5], 15-degree faces, blunt rear face: %d subpatches "
                        "(3 C1 corner, skewed-affine face, rear-face and seeded lattice subpatches, sides 150-300), "
-                       "%d points (h = 1/4400), SDNN viscosity (GPU-trained), filter, CFL 0.5, FC-Gram d=2 C=27"
+                       "%d points (h = 1/4400), SDNN viscosity (GPU-trained), initial-data smearing, filter, CFL 0.5, "
+                       "FC-Gram d=2 C=27"
                        % (W.WEDGE_MACH, len(specs), npts),
            "points": npts, "subpatches": len(specs), "stages_per_step": 5}
     solvers = {}
     for prec in forms:
         stream = torch.cuda.Stream()
         t0 = time.perf_counter()
-        S, _ = make_solver(F, W, torch, weights, prec, stream, use_graph=not eager, specs=specs, state=w0)
+        S, _ = make_solver(F, W, torch, weights, prec, stream, use_graph=not eager, specs=specs, state=w0, smear=True)
         setup = time.perf_counter() - t0
         if stage_variant:
             S.set_stage_variant(stage_variant)
@@ -366,7 +399,7 @@ def cpu_baseline(W, weights, steps):
     specs = W.wedge_tunnel(600, 48, 96)
     with threadpool_limits(limits=threads):
         O = osolver.Solver(osolver.patches_from_specs(specs),
-                           osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True),
+                           osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, smear=True),
                            sdnn_params=W.sdnn_unblob(weights))
         O.set_prim(W.wedge_state(specs))
         log("oracle set up (%d subpatches)" % len(specs))
@@ -394,8 +427,8 @@ def main():
     import workloads as W
 
     forms = [f for f in a.forms.split(",") if f]
-    weights = train_classifier(F, W, torch)
-    log("classifier trained")
+    weights, train_info = train_classifier(F, W, torch, nlines=a.classifier_lines)
+    log("classifier trained on %d lines" % a.classifier_lines)
     wedge = wedge_run(F, W, torch, weights, forms, a.steps, a.warmup, eager=a.eager, stage_variant=a.stage_variant)
     head = forms[0]
     rf = wedge[head]["stage_contraction"]
@@ -415,6 +448,7 @@ def main():
                      "avg_launch_ms": rf["avg_launch_ms"], "mfma": rf["mfma"],
                      "timing": "the last step's stage contraction, launches back to back between HIP events"},
         "wedge": wedge,
+        "classifier_training": train_info,
     }
     if not a.no_extras:
         out["step_channel"] = channel_run(F, W, torch, weights, min(a.steps, 2000), a.warmup)

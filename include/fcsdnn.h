@@ -44,7 +44,14 @@ enum {
   FCS_SIDE_INFLOW = 1,   /* Dirichlet: the subpatch's inflow state          */
   FCS_SIDE_OUTFLOW = 2,  /* supersonic outflow: nothing imposed              */
   FCS_SIDE_SLIP = 3,     /* inviscid wall: zero normal momentum, p kept     */
-  FCS_SIDE_EXACT = 4     /* n_f-point layer set to the exact vortex solution */
+  FCS_SIDE_EXACT = 4,    /* n_f-point layer set to the exact vortex solution */
+  FCS_SIDE_NOSLIP = 5    /* no-slip adiabatic wall (the paper's obstacle
+                            conditions, Sec. 7): zero momentum, rho kept,
+                            theta = p/((gamma-1) rho) chosen so that the FC
+                            first derivative along the grid line ending at
+                            the wall vanishes there (both ends of a line
+                            solved together; at a node ending two such lines,
+                            the line along q^2)                             */
 };
 
 /* Patch types of Sec. 3.1 (informational; C1 requires a mask). */
@@ -55,7 +62,9 @@ enum { FCS_PATCH_I = 0, FCS_PATCH_S = 1, FCS_PATCH_C1 = 2, FCS_PATCH_C2 = 3 };
 enum {
   FCS_PREC_FP64 = 0,    /* FP64 MFMA                                         */
   FCS_PREC_FP32 = 1,    /* FP32 operands, FP32 MFMA accumulation             */
-  FCS_PREC_BF16X3 = 2   /* split-BF16 hi/lo products (3 MFMAs), FP32 accum.  */
+  FCS_PREC_BF16X3 = 2,  /* split-BF16 hi/lo products (3 MFMAs), FP32 accum.  */
+  FCS_PREC_BF16X6 = 3   /* split-BF16 hi/mid/lo products (6 MFMAs), FP32
+                           accumulators per magnitude order, FP64 sum       */
 };
 
 /* Smoothness classifier for the artificial viscosity (Sec. 4, Alg. 3). */
@@ -66,8 +75,11 @@ enum {
   FCS_AV_FROZEN = 3     /* classes supplied by fcs_set_tau (testing)         */
 };
 
-/* Kinds of dense FC operators. */
-enum { FCS_OP_D1 = 0, FCS_OP_D2 = 1, FCS_OP_FILTER = 2 };
+/* Kinds of dense FC operators: first and second derivative (index units),
+ * the filter of Alg. 4 (t > 0: exp(-16 ln 10 eta^36) of the mode
+ * eta = 2|m|/(n + C)), and the stronger filter of the initial-data smearing
+ * (the same with eta^8). */
+enum { FCS_OP_D1 = 0, FCS_OP_D2 = 1, FCS_OP_FILTER = 2, FCS_OP_SMEAR = 3 };
 
 /* Fields for fcs_get_field. */
 enum {
@@ -110,6 +122,13 @@ typedef struct {
   const float* sdnn_weights; /* host, FCS_SDNN_NPARAM floats; copied        */
   double vortex[5];    /* EXACT sides: beta, x0, y0, u0, v0 of the isentropic
                           vortex (background rho = p = 1)                    */
+  int32_t smear;       /* nonzero: localized smearing of the initial data in
+                          the first step from t = 0 (Alg. 4, t = 0; Sec. 5
+                          item 3): where the step's classes flag a
+                          discontinuity, rho, rho u, rho v and theta are
+                          blended with their FCS_OP_SMEAR-filtered values by
+                          a window localized as the viscosity is, and E is
+                          rebuilt.  Needs av_mode != FCS_AV_OFF           */
 } fcs_params;
 
 typedef struct {

@@ -46,6 +46,9 @@ PRECISION_BITS = 256
 # Filter I-(32) reading: sigma(eta) = exp(-alpha eta^(2p)).
 FILTER_ALPHA = 16.0 * np.log(10.0)
 FILTER_ORDER = 36
+# The stronger filter of the initial-data smearing (Alg. 4 at t = 0; Part
+# I's strength is not available): the same exponential with order 8.
+SMEAR_ORDER = 8
 
 
 def gram_basis(d: int, prec: int = PRECISION_BITS):
@@ -153,6 +156,9 @@ def _multiplier(M: int, kind: str) -> np.ndarray:
     elif kind == "filter":
         eta = 2.0 * np.abs(m) / M
         mult = np.exp(-FILTER_ALPHA * eta ** FILTER_ORDER) + 0j
+    elif kind == "smear":
+        eta = 2.0 * np.abs(m) / M
+        mult = np.exp(-FILTER_ALPHA * eta ** SMEAR_ORDER) + 0j
     else:
         raise ValueError(kind)
     if M % 2 == 0:

@@ -25,7 +25,7 @@ import numpy as np
 
 from . import fcgram
 
-INTERNAL, INFLOW, OUTFLOW, SLIP, EXACT = 0, 1, 2, 3, 4
+INTERNAL, INFLOW, OUTFLOW, SLIP, EXACT, NOSLIP = 0, 1, 2, 3, 4, 5
 SIDES = ("W", "E", "S", "N")
 
 

@@ -95,6 +95,39 @@ def loss_and_grads(params, x: np.ndarray, labels: np.ndarray, class_weight=None)
     return loss, grads
 
 
+def loss_and_grads_lowp(params, x: np.ndarray, labels: np.ndarray, class_weight=None):
+    """loss_and_grads with the training's low-precision products: the
+    inputs, the weight matrices and the hidden activations rounded to bf16
+    (nearest even) wherever they enter a product, forward and backward; all
+    other arithmetic in FP64.  Gradients are those of the rounded network,
+    taken as the gradients of the unrounded weights."""
+    W1, W2, W3 = (round_bf16(np.asarray(params[k], dtype=np.float64)) for k in ("W1", "W2", "W3"))
+    xr = round_bf16(np.asarray(x, dtype=np.float64))
+    z1 = xr @ W1.T + params["b1"]
+    a1 = round_bf16(np.maximum(z1, 0.0))
+    z2 = a1 @ W2.T + params["b2"]
+    a2 = round_bf16(np.maximum(z2, 0.0))
+    logits = a2 @ W3.T + params["b3"]
+    m = xr.shape[0]
+    zmax = logits.max(axis=1, keepdims=True)
+    ex = np.exp(logits - zmax)
+    prob = ex / ex.sum(axis=1, keepdims=True)
+    w = np.ones(m) if class_weight is None else class_weight[labels]
+    wsum = w.sum()
+    loss = -(w * np.log(prob[np.arange(m), labels])).sum() / wsum
+    g3 = prob.copy()
+    g3[np.arange(m), labels] -= 1.0
+    g3 *= (w / wsum)[:, None]
+    grads = {"W3": g3.T @ a2, "b3": g3.sum(axis=0)}
+    g2 = (g3 @ W3) * (z2 > 0)
+    grads["W2"] = g2.T @ a1
+    grads["b2"] = g2.sum(axis=0)
+    g1 = (g2 @ W2) * (z1 > 0)
+    grads["W1"] = g1.T @ xr
+    grads["b1"] = g1.sum(axis=0)
+    return loss, grads
+
+
 def adam_update(params, grads, state, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
     """One Adam step (Kingma & Ba) with bias correction; state holds m, v, t."""
     state["t"] = state.get("t", 0) + 1

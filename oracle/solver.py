@@ -19,7 +19,7 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import euler, overlap, patches, sdnn, ssprk, viscosity
+from . import euler, fcgram, overlap, patches, sdnn, ssprk, viscosity
 
 
 @dataclass
@@ -33,6 +33,7 @@ class Params:
     av: str = "off"          # "off", "modal", "sdnn"
     c_mu: float = 1.0
     filter: bool = False
+    smear: bool = False      # localized smearing of the initial data (Alg. 4, t = 0)
     dt_fixed: float | None = None  # bypass the adaptive step (tests)
 
 
@@ -100,8 +101,9 @@ class Solver:
         return out
 
     # ----------------------------------------------------------- BCs + fringe
-    def enforce(self, U, t_stage):
-        """Boundary conditions, then fringe communication (Alg. 1)."""
+    def enforce(self, U, t_stage, fringe=True):
+        """Boundary conditions, then (unless fringe is False) the fringe
+        communication (Alg. 1)."""
         gam = self.prm.gamma
         U = U.copy()
         for p, g in enumerate(self.grids):
@@ -126,6 +128,44 @@ class Solver:
                     mx, my = 0.0, 0.0
                 e[1, j, i], e[2, j, i] = mx, my
                 e[3, j, i] = pr / (gam - 1.0) + 0.5 * (mx * mx + my * my) / rho
+            # no-slip adiabatic walls (reading of the obstacle conditions of
+            # Sec. 7 and of Alg. 5's boundary treatment): zero momentum, rho
+            # kept, and theta = p / ((gamma - 1) rho) at the wall set so that
+            # the FC first derivative along the grid line ending at the wall
+            # vanishes there (FC-Neumann).  A node where two such lines end
+            # uses the line along q^2; a line with such walls at both ends
+            # takes both wall values from the two conditions together.
+            walls = {}
+            for (j, i, kind, direction) in g.boundary:
+                if kind == patches.NOSLIP:
+                    walls[(j, i)] = max(walls.get((j, i), 0), direction)
+            lines = {}
+            for (j, i), direction in walls.items():
+                key = (direction, j if direction == 0 else i)
+                lines.setdefault(key, []).append((j, i))
+            ee = np.where(g.p.mask, e, np.array([1.0, 0.0, 0.0, 1.0])[:, None, None])
+            theta = euler.temperature_like(ee, gam)
+            fixed = {}
+            for (direction, l), nodes in lines.items():
+                if direction == 0:
+                    s0, n = g.row_runs[l]
+                    line = theta[l, s0:s0 + n]
+                    pos = [i - s0 for (j, i) in nodes]
+                else:
+                    s0, n = g.col_runs[l]
+                    line = theta[s0:s0 + n, l]
+                    pos = [j - s0 for (j, i) in nodes]
+                D = fcgram.dense_operator(n, self.prm.fc_d, self.prm.fc_C, "d1")
+                rest = np.ones(n, dtype=bool)
+                rest[pos] = False
+                A = D[np.ix_(pos, pos)]
+                rhs = -(D[np.ix_(pos, np.flatnonzero(rest))] @ line[rest])
+                for node, th in zip(nodes, np.linalg.solve(A, rhs)):
+                    fixed[node] = th
+            for (j, i), th in fixed.items():
+                rho = e[0, j, i]
+                e[1, j, i] = e[2, j, i] = 0.0
+                e[3, j, i] = rho * th
             # Dirichlet data: inflow sides, exact-data fringe
             for (j, i, kind, direction) in g.boundary:
                 if kind == patches.INFLOW:
@@ -134,6 +174,8 @@ class Solver:
                 jj, ii = np.nonzero(g.xfringe)
                 w = self.exact(g.p.x[jj, ii], g.p.y[jj, ii], t_stage)
                 e[:, jj, ii] = euler.prim_to_cons(w, gam)
+        if not fringe:
+            return U
         src = U.copy()
         for p, rows in enumerate(self.fringe_rows):
             e = self.view(U, p)
@@ -198,6 +240,47 @@ class Solver:
             v[...] = np.where(m, np.stack([rho, mx, my, E]), 0.0)
         return out
 
+    def smear_initial_data(self, U):
+        """Alg. 4 at t = 0 (reading of Part I's localized smearing, which is
+        not available): near discontinuities the initial data are replaced
+        by a more strongly filtered version, blended in smoothly.
+
+        1. indicator: 1 at the non-fringe points whose class (either
+           direction) flags a discontinuity in the window, from the first
+           step's classification (Alg. 3 on the same data);
+        2. window w in [0, 1]: the indicator localized exactly as the
+           preliminary viscosity (windowed max over n_v, then the
+           multi-patch blend), clipped to [0, 1];
+        3. the strong filter (order SMEAR_ORDER) along q^1 then q^2 of rho,
+           rho u, rho v and theta, as the filter of t > 0 does with its own
+           order;
+        4. (rho, rho u, rho v, theta) <- w * filtered + (1 - w) * given, and E
+           rebuilt from them."""
+        gam, n_v = self.prm.gamma, self.prm.n_v
+        w_t = []
+        for p, g in enumerate(self.grids):
+            tau = self.last_tau[p]
+            ind = (np.maximum(tau[0], tau[1]) >= 1) & g.p.mask & ~g.fringe & ~g.xfringe
+            w_t.append(np.where(g.p.mask, viscosity.smooth_fast(ind.astype(np.float64), n_v), 0.0))
+        out = U.copy()
+        for p, g in enumerate(self.grids):
+            w = w_t[p].copy()
+            if self.blend is not None:
+                for (j, i), ent in self.blend[p].items():
+                    w[j, i] = sum(c * w_t[s][jd, id_] for (s, jd, id_), c in ent)
+            w = np.clip(w, 0.0, 1.0)
+            e = self.view(U, p)
+            m = g.p.mask
+            ee = np.where(m, e, np.array([1.0, 0.0, 0.0, 1.0])[:, None, None])
+            theta = np.where(m, euler.temperature_like(ee, gam), 0.0)
+            q = np.stack([e[0], e[1], e[2], theta])
+            qs = g.deriv(g.deriv(q, 0, "smear"), 1, "smear")
+            rho, mx, my, th = w * qs + (1.0 - w) * q
+            rr = np.where(m, rho, 1.0)
+            E = rho * th + 0.5 * (mx * mx + my * my) / rr
+            self.view(out, p)[...] = np.where(m, np.stack([rho, mx, my, E]), 0.0)
+        return out
+
     def timestep(self, U, mu):
         """Adaptive step (reading of I-(31)): CFL times the minimum over all
         points of h_x / (|u| + a) and h_x^2 / (4 mu).  The factor 4 keeps the
@@ -224,13 +307,18 @@ class Solver:
         prm = self.prm
         if self.nstep == 0:
             # the initial data are made to satisfy the boundary conditions
-            # (walls, inflow, exact data, then the fringe fill), as the
-            # solution does after every stage; the first step's viscosity
-            # then sees the jumps the walls impose
-            self.U = self.enforce(self.U, self.t)
+            # (walls, inflow, exact data), as the solution does after every
+            # stage; the first step's viscosity then sees the jumps the walls
+            # impose.  The fringe points keep the data's own values (given
+            # pointwise): interpolating discontinuous initial data would
+            # overshoot, and the first stage's fringe fill follows the
+            # smearing.
+            self.U = self.enforce(self.U, self.t, fringe=False)
         self.mu = self.compute_viscosity(self.U) if prm.av != "off" else None
         if prm.filter and self.nstep > 0:
             self.U = self.apply_filter(self.U)
+        elif prm.smear and self.nstep == 0:
+            self.U = self.smear_initial_data(self.U)
         dt = self.timestep(self.U, self.mu)
         self.last_dt = dt
         ct = ssprk.stage_times()

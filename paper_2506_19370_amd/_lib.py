@@ -24,11 +24,11 @@ vp = ctypes.c_void_p
 
 FCS_OK, FCS_EINVAL, FCS_EOVERLAP, FCS_ENOMEM, FCS_ENONFINITE, FCS_EHIP, FCS_ESTATE = range(7)
 STATUS = {0: "OK", 1: "EINVAL", 2: "EOVERLAP", 3: "ENOMEM", 4: "ENONFINITE", 5: "EHIP", 6: "ESTATE"}
-SIDE = {"INTERNAL": 0, "INFLOW": 1, "OUTFLOW": 2, "SLIP": 3, "EXACT": 4}
+SIDE = {"INTERNAL": 0, "INFLOW": 1, "OUTFLOW": 2, "SLIP": 3, "EXACT": 4, "NOSLIP": 5}
 PATCH = {"I": 0, "S": 1, "C1": 2, "C2": 3}
-PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2}
+PREC = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 AV = {"off": 0, "modal": 1, "sdnn": 2, "frozen": 3}
-OP = {"d1": 0, "d2": 1, "filter": 2}
+OP = {"d1": 0, "d2": 1, "filter": 2, "smear": 3}
 FIELD = {"rho": 0, "mx": 1, "my": 2, "E": 3, "p": 4, "mach": 5, "mu": 6, "tau0": 7, "tau1": 8, "muhat": 9}
 SDNN_NPARAM = 64 * 16 + 64 + 64 * 64 + 64 + 3 * 64 + 3
 
@@ -48,6 +48,7 @@ class Params(ctypes.Structure):
         ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32), ("visc_all_lines", ctypes.c_int32),
         ("sdnn_weights", ctypes.POINTER(ctypes.c_float)),
         ("vortex", ctypes.c_double * 5),
+        ("smear", ctypes.c_int32),
     ]
 
 

@@ -38,6 +38,7 @@ class SolverParams:
     visc_all_lines: bool = False
     sdnn_weights: np.ndarray | None = None
     vortex: tuple = (5.0, 5.0, 5.0, 1.0, 1.0)
+    smear: bool = False
 
 
 def create_context(specs, prm: SolverParams) -> ctypes.c_void_p:
@@ -54,6 +55,7 @@ def create_context(specs, prm: SolverParams) -> ctypes.c_void_p:
     cp.use_graph = int(bool(prm.use_graph))
     cp.autotune = int(bool(prm.autotune))
     cp.visc_all_lines = int(bool(prm.visc_all_lines))
+    cp.smear = int(bool(prm.smear))
     if prm.sdnn_weights is not None:
         w = np.ascontiguousarray(prm.sdnn_weights, dtype=np.float32)
         if w.size != L.SDNN_NPARAM:

@@ -68,7 +68,7 @@ enum ArrayId { A_U0, A_UA, A_UB, A_F, A_DF1, A_DF2, A_W1, A_W2, A_W11, A_W22, A_
 
 // PH_EULER0: the first stage's contraction, which also takes the viscosity
 // gradient (frozen for the step) in the same launch.
-enum Phase { PH_EULER, PH_CROSS, PH_MUGRAD, PH_FILT1, PH_FILT2, PH_EULER0, PH_N };
+enum Phase { PH_EULER, PH_CROSS, PH_MUGRAD, PH_FILT1, PH_FILT2, PH_EULER0, PH_SMEAR1, PH_SMEAR2, PH_N };
 
 }  // namespace
 
@@ -100,6 +100,7 @@ struct fcs_ctx {
   std::vector<int32_t> iptr, bptr;
   std::vector<double> ival, bval;
   std::vector<BcEntry> bc;
+  std::vector<WallLine> walls;  // lines ending at no-slip adiabatic walls
   std::vector<int32_t> bcidx;  // entry of each boundary point
   std::vector<double> metric_host[10];  // t1x t1y t2x t2y g11 g12 g22 lap1 lap2 hx
   std::vector<double> basis, wdil;
@@ -280,12 +281,16 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   c->prm.sdnn_weights = nullptr;
   const fcs_params& p = c->prm;
   if (p.fc_d < 1 || p.fc_d > 12 || p.fc_C < 4 || p.fc_C > 64 || p.n_f < 1 || p.n_v < 1 || p.n_v > 64 ||
-      p.precision < 0 || p.precision > 2 || p.av_mode < 0 || p.av_mode > 3 || !(p.gamma > 1.0) ||
+      p.precision < 0 || p.precision > 3 || p.av_mode < 0 || p.av_mode > 3 || !(p.gamma > 1.0) ||
       !(p.cfl > 0.0)) {
     *out = c.release();
     return (*out)->fail(FCS_EINVAL, "invalid solver parameters");
   }
   c->visc = p.av_mode != FCS_AV_OFF;
+  if (p.smear && !c->visc) {
+    *out = c.release();
+    return (*out)->fail(FCS_EINVAL, "the initial-data smearing needs a smoothness classifier (av_mode)");
+  }
   if (p.av_mode == FCS_AV_SDNN) {
     if (!prm->sdnn_weights) {
       *out = c.release();
@@ -309,7 +314,7 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       return (*out)->fail(FCS_EINVAL, "subpatch " + std::to_string(q) + ": bad size or coordinates");
     }
     for (int s = 0; s < 4; ++s)
-      if (d.side[s] < 0 || d.side[s] > 4) {
+      if (d.side[s] < 0 || d.side[s] > 5 || d.notch < 0 || d.notch > 5) {
         *out = c.release();
         return (*out)->fail(FCS_EINVAL, "bad side kind");
       }
@@ -533,6 +538,10 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_FILT1, g, 0, FCS_OP_FILTER, A_F, 0, A_DF1, 0, 4);
       add_line_tasks(c.get(), PH_FILT2, g, 1, FCS_OP_FILTER, A_DF1, 0, A_DF2, 0, 4);
     }
+    if (p.smear) {
+      add_line_tasks(c.get(), PH_SMEAR1, g, 0, FCS_OP_SMEAR, A_F, 0, A_DF1, 0, 4);
+      add_line_tasks(c.get(), PH_SMEAR2, g, 1, FCS_OP_SMEAR, A_DF1, 0, A_DF2, 0, 4);
+    }
   }
   // activity flags of the row and the column of each blend row's point
   if (c->nact)
@@ -541,7 +550,52 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       const int32_t j = c->ij[k] >> 16, i = c->ij[k] & 0xFFFF;
       c->bact.push_back(pd.act_row >= 0 ? make_int2(pd.act_row + j, pd.act_col + i) : make_int2(-1, -1));
     }
-  c->deriv_f32 = p.precision != FCS_PREC_FP64 && !c->cross;
+  // no-slip adiabatic walls: the lines ending there (Sec. 7 obstacle
+  // conditions; a node ending two such lines uses the line along q^2)
+  for (const Grid& g : c->grids) {
+    std::map<std::pair<int, int>, int> dir_of;  // (j, i) -> line direction
+    for (const BoundaryEntry& b : g.bnd)
+      if (b.kind == kNoSlip) {
+        auto key = std::make_pair(b.j, b.i);
+        auto it = dir_of.find(key);
+        dir_of[key] = it == dir_of.end() ? b.dir : std::max(it->second, b.dir);
+      }
+    std::map<std::pair<int, int>, std::vector<int>> line_pos;  // (dir, line) -> wall positions
+    for (const auto& kv : dir_of) {
+      const int j = kv.first.first, i = kv.first.second, dir = kv.second;
+      const Run& r = dir == 0 ? g.rows[j] : g.cols[i];
+      line_pos[std::make_pair(dir, dir == 0 ? j : i)].push_back((dir == 0 ? i : j) - r.start);
+    }
+    for (auto& kv : line_pos) {
+      const int dir = kv.first.first, l = kv.first.second;
+      const Run& r = dir == 0 ? g.rows[l] : g.cols[l];
+      std::vector<int>& ps = kv.second;
+      std::sort(ps.begin(), ps.end());
+      WallLine w{};
+      w.first = g.offset + (dir == 0 ? static_cast<int64_t>(l) * g.n1 + r.start
+                                     : static_cast<int64_t>(r.start) * g.n1 + l);
+      w.stride = dir == 0 ? 1 : g.n1;
+      w.n = r.len;
+      w.op = op_id(c.get(), r.len, FCS_OP_D1);
+      w.pos[0] = ps[0];
+      w.pos[1] = ps.size() > 1 ? ps[1] : -1;
+      // a wall node that also carries Dirichlet data (an inflow side
+      // meeting the wall) keeps them: it is solved for with the line but not
+      // written
+      for (int q = 0; q < 2; ++q) {
+        w.keep[q] = 0;
+        if (w.pos[q] < 0) continue;
+        const int jj = dir == 0 ? l : r.start + w.pos[q], ii = dir == 0 ? r.start + w.pos[q] : l;
+        for (const BoundaryEntry& b : g.bnd)
+          if (b.j == jj && b.i == ii && (b.kind == kInflow || b.kind == kExact)) w.keep[q] = 1;
+        if (g.xfringe[g.at(jj, ii)]) w.keep[q] = 1;
+      }
+      c->walls.push_back(w);
+    }
+  }
+  // mixed forms store the stage derivatives in FP32 (their precision); with
+  // cross derivatives W1 stays FP64, the operand of the cross contraction
+  c->deriv_f32 = p.precision != FCS_PREC_FP64;
   if (c->visc) {
     c->phase_tasks[PH_EULER0] = c->phase_tasks[PH_EULER];
     c->phase_tasks[PH_EULER0].insert(c->phase_tasks[PH_EULER0].end(), c->phase_tasks[PH_MUGRAD].begin(),
@@ -592,10 +646,11 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["OPF64"] = cv.take(c->opk.elems * D);
   o["OPROW"] = cv.take(c->opk.rows * D);
   if (p.precision == FCS_PREC_FP32) o["OPF32"] = cv.take(c->opk.elems * 4);
-  if (p.precision == FCS_PREC_BF16X3) {
+  if (p.precision == FCS_PREC_BF16X3 || p.precision == FCS_PREC_BF16X6) {
     o["OPBHI"] = cv.take(c->opk.elems * 2);
     o["OPBLO"] = cv.take(c->opk.elems * 2);
   }
+  if (p.precision == FCS_PREC_BF16X6) o["OPBMID"] = cv.take(c->opk.elems * 2);
   for (int ph = 0; ph < PH_N; ++ph) {
     for (int v = 0; v < 3; ++v)
       o["TASK" + std::to_string(ph) + "_" + std::to_string(v)] = cv.take(c->phase_tasks[ph].size() * sizeof(GemmTask));
@@ -612,6 +667,8 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["BCOL"] = cv.take(c->bcol.size() * 8);
   o["BVAL"] = cv.take(c->bval.size() * D);
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
+  o["WALL"] = cv.take(c->walls.size() * sizeof(WallLine));
+  o["WTH"] = cv.take(c->walls.size() * 2 * D);
   o["SDNNF"] = cv.take(64 * 84 * 4);  // classifier fragment table
   o["BCIDX"] = cv.take(P * 4);
   o["GCTR"] = cv.take(kGemmCounters * PH_N * 4);  // tile counters of the persistent contractions
@@ -655,7 +712,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
   if ((st = upload(c, "OPROFF", c->opk.roff.data(), c->opk.roff.size() * 8)) != FCS_OK) return st;
   if ((st = upload(c, "OPLD", c->opk.ld.data(), c->opk.ld.size() * 4)) != FCS_OK) return st;
   std::vector<float> f32;
-  std::vector<uint16_t> bhi, blo;
+  std::vector<uint16_t> bhi, blo, bmid;
   if (c->prm.precision == FCS_PREC_FP32) {
     f32.assign(f64.begin(), f64.end());
     if ((st = upload(c, "OPF32", f32.data(), f32.size() * 4)) != FCS_OK) return st;
@@ -665,14 +722,22 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
     if ((st = upload(c, "OPBHI", bhi.data(), bhi.size() * 2)) != FCS_OK) return st;
     if ((st = upload(c, "OPBLO", blo.data(), blo.size() * 2)) != FCS_OK) return st;
   }
+  if (c->prm.precision == FCS_PREC_BF16X6) {
+    split_bf16x3(f64, bhi, bmid, blo);
+    if ((st = upload(c, "OPBHI", bhi.data(), bhi.size() * 2)) != FCS_OK) return st;
+    if ((st = upload(c, "OPBMID", bmid.data(), bmid.size() * 2)) != FCS_OK) return st;
+    if ((st = upload(c, "OPBLO", blo.data(), blo.size() * 2)) != FCS_OK) return st;
+  }
   c->optab.off = c->dptr<int64_t>("OPOFF");
   c->optab.ld = c->dptr<int32_t>("OPLD");
   c->optab.roff = c->dptr<int64_t>("OPROFF");
   c->optab.f64 = c->dptr<double>("OPF64");
   c->optab.rowsum = c->dptr<double>("OPROW");
   c->optab.f32 = c->prm.precision == FCS_PREC_FP32 ? c->dptr<float>("OPF32") : nullptr;
-  c->optab.bhi = c->prm.precision == FCS_PREC_BF16X3 ? c->dptr<uint16_t>("OPBHI") : nullptr;
-  c->optab.blo = c->prm.precision == FCS_PREC_BF16X3 ? c->dptr<uint16_t>("OPBLO") : nullptr;
+  const bool split = c->prm.precision == FCS_PREC_BF16X3 || c->prm.precision == FCS_PREC_BF16X6;
+  c->optab.bhi = split ? c->dptr<uint16_t>("OPBHI") : nullptr;
+  c->optab.blo = split ? c->dptr<uint16_t>("OPBLO") : nullptr;
+  c->optab.bmid = c->prm.precision == FCS_PREC_BF16X6 ? c->dptr<uint16_t>("OPBMID") : nullptr;
   // arrays
   c->arr[A_U0] = c->dptr<double>("U0");
   c->arr[A_UA] = c->dptr<double>("UA");
@@ -701,8 +766,8 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
         t.act = s.act;
         double* sbase = s.src_arr == A_IN ? c->arr[A_U0 + v] : c->arr[s.src_arr];
         t.src = sbase + s.src_off;
-        const bool f32 = c->deriv_f32 && (ph == PH_EULER || ph == PH_EULER0) && s.dst_arr != A_MU1 &&
-                         s.dst_arr != A_MU2;
+        const bool f32 = c->deriv_f32 && (ph == PH_EULER || ph == PH_EULER0 || ph == PH_CROSS) &&
+                         s.dst_arr != A_MU1 && s.dst_arr != A_MU2 && !(c->cross && s.dst_arr == A_W1);
         // element offsets count in the stored type
         t.dst = f32 ? static_cast<void*>(reinterpret_cast<float*>(c->arr[s.dst_arr]) + s.dst_off)
                     : static_cast<void*>(c->arr[s.dst_arr] + s.dst_off);
@@ -753,6 +818,7 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"BCOL", c->bcol.data(), c->bcol.size() * 8},
       {"BVAL", c->bval.data(), c->bval.size() * 8},
       {"BC", c->bc.data(), c->bc.size() * sizeof(BcEntry)},
+      {"WALL", c->walls.data(), c->walls.size() * sizeof(WallLine)},
       {"BCIDX", c->bcidx.data(), c->bcidx.size() * 4},
       {"SDNN", c->sdnn.data(), c->sdnn.size() * 4},
       {"BASIS", c->basis.data(), c->basis.size() * 8},
@@ -815,10 +881,13 @@ fcs_status run_gemm(fcs_ctx* c, int ph, int variant, int precision, bool timed, 
     e1 = c->ev[c->ev_used++];
     HIPCHK(c, hipEventRecord(e0, c->stream));
   }
-  if (ph == PH_EULER || ph == PH_CROSS || ph == PH_EULER0)
+  // the stage phases in their tuned shape; the once-per-step phases in the
+  // default shape, through the stage kernels in the mixed forms and through
+  // k_gemm_step (FP64, its own name in profiles) otherwise
+  if (ph == PH_EULER || ph == PH_CROSS || ph == PH_EULER0 || precision != FCS_PREC_FP64)
     HIPCHK(c, launch_gemm(precision, c->var[ph], c->d_tasks[ph][variant], c->d_tiles[ph],
                           static_cast<int>(c->phase_tiles[ph].size()), c->optab, c->dptr<int>("GCTR") + kGemmCounters * ph,
-                          c->stream));
+                          s));
   else
     HIPCHK(c, launch_gemm_step(c->d_tasks[ph][variant], c->d_tiles[ph], static_cast<int>(c->phase_tiles[ph].size()),
                                c->optab, s));
@@ -898,8 +967,10 @@ fcs_status per_step(fcs_ctx* c) {
       fs = c->stream2;
     }
     HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], c->dptr<uint8_t>("FLAGS"), P, p.gamma, fs));
-    if ((st = run_gemm(c, PH_FILT1, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
-    if ((st = run_gemm(c, PH_FILT2, 0, FCS_PREC_FP64, false, fs)) != FCS_OK) return st;
+    // the filter's contractions in the precision mode (Alg. 4 on the FP64
+    // state; outputs FP64)
+    if ((st = run_gemm(c, PH_FILT1, 0, p.precision, false, fs)) != FCS_OK) return st;
+    if ((st = run_gemm(c, PH_FILT2, 0, p.precision, false, fs)) != FCS_OK) return st;
     const double* met[4] = {c->dptr<double>("MET0"), c->dptr<double>("MET1"), c->dptr<double>("MET2"),
                             c->dptr<double>("MET3")};
     FluxOut fo{c->arr[A_F], met[0], met[1], met[2], met[3], p.gamma - 1.0, c->dptr<int32_t>("PID"),
@@ -918,8 +989,23 @@ fcs_status per_step(fcs_ctx* c) {
                                      v.act, c->stream));
   }
   if (fork) HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev_join, 0));
+  if (p.smear && !c->past_t0) {
+    // Alg. 4 at t = 0 (after the viscosity, which Alg. 1 evaluates first):
+    // the window from this step's classes, the strongly filtered rho, rho u,
+    // rho v, theta (FCS_OP_SMEAR along q^1 then q^2) and the blend; the
+    // window is held in the (not yet used) W11 array
+    const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
+    double* w = c->arr[A_W11];
+    HIPCHK(c, launch_smear_window(v, w, c->stream));
+    HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], flags, P, p.gamma, c->stream));
+    if ((st = run_gemm(c, PH_SMEAR1, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
+    if ((st = run_gemm(c, PH_SMEAR2, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
+    HIPCHK(c, launch_smear_post(c->arr[A_DF2], c->arr[A_F], w, U0, flags, P, c->stream));
+  }
   return FCS_OK;  // the step size is taken by the first stage (one_stage)
 }
+
+fcs_status apply_walls(fcs_ctx* c, double* U, const FluxOut& fo, double2* ps);
 
 fcs_status one_stage(fcs_ctx* c, int s) {
   const int64_t P = c->P;
@@ -1003,6 +1089,7 @@ fcs_status one_stage(fcs_ctx* c, int s) {
     a.W12 = c->cross ? c->arr[A_W12] : nullptr;
   }
   a.deriv_f32 = c->deriv_f32;
+  a.w1_f64 = c->deriv_f32 && c->cross;
   a.pid = c->dptr<int32_t>("PID");
   a.patches = c->dptr<PatchDev>("PATCH");
   double* scal = c->dptr<double>("SCAL");
@@ -1021,12 +1108,19 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   if (s == 4) next.F = nullptr;
   a.flux = next;
   // copy fringe points are updated inside the stage kernel (from their
-  // donors); the fringe kernel evaluates the interpolation rows only
-  a.csrc = c->dptr<int32_t>("CSRC");
+  // donors); the fringe kernel evaluates the interpolation rows only.  With
+  // no-slip walls every point takes its own update first: the wall
+  // temperature's FC-Neumann condition reads whole grid lines, fringe points
+  // included, before the fringe fill; the copies follow the walls.
+  a.csrc = c->walls.empty() ? c->dptr<int32_t>("CSRC") : nullptr;
   // the last stage also leaves the next step's proxy values
   a.ps = (s == 4 && c->visc) ? c->dptr<double2>("PS") : nullptr;
   HIPCHK(c, launch_stage(a, c->stream));
-  HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), 0, c->dptr<int64_t>("IDST"),
+  // no-slip walls need the whole stage output; the copy fringe points are
+  // filled after them
+  if ((st = apply_walls(c, outp, next, a.ps)) != FCS_OK) return st;
+  const int ncopy = c->walls.empty() ? 0 : static_cast<int>(c->copy_pairs.size() / 2);
+  HIPCHK(c, launch_fringe(outp, flags, c->dptr<int64_t>("COPY"), ncopy, c->dptr<int64_t>("IDST"),
                           c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"), c->dptr<double>("IVAL"),
                           static_cast<int>(c->idst.size()), P, next, a.ps, p.gamma, c->stream));
   if (s == 4) c->ps_valid = c->visc;
@@ -1034,10 +1128,20 @@ fcs_status one_stage(fcs_ctx* c, int s) {
   return FCS_OK;
 }
 
+// No-slip adiabatic walls of a state (after its other boundary conditions,
+// before the fringe fill): fluxes and proxy values of the corrected points
+// through fo / ps when set.
+fcs_status apply_walls(fcs_ctx* c, double* U, const FluxOut& fo, double2* ps) {
+  if (c->walls.empty()) return FCS_OK;
+  HIPCHK(c, launch_walls(U, c->dptr<WallLine>("WALL"), static_cast<int>(c->walls.size()), c->optab,
+                         c->dptr<double>("WTH"), c->dptr<uint8_t>("FLAGS"), c->P, c->prm.gamma, fo, ps, c->stream));
+  return FCS_OK;
+}
+
 // Before the first step from t = 0: the initial data are made to satisfy
-// the boundary conditions (walls, inflow, exact data, then the fringe fill
-// from the donors), as the solution does after every stage; the first
-// step's viscosity then sees the jumps that the walls impose.
+// the boundary conditions (walls, inflow, exact data), as the solution does
+// after every stage; the first step's viscosity then sees the jumps that
+// the walls impose.
 fcs_status prepare_t0(fcs_ctx* c) {
   const fcs_params& p = c->prm;
   double* U0 = c->arr[A_U0];
@@ -1050,10 +1154,12 @@ fcs_status prepare_t0(fcs_ctx* c) {
   if (!c->bc.empty()) HIPCHK(c, launch_bc_state(U0, flags, b, c->t_host, c->P, c->stream));
   FluxOut none{};
   none.F = nullptr;
-  HIPCHK(c, launch_fringe(U0, flags, c->dptr<int64_t>("COPY"), static_cast<int>(c->copy_pairs.size() / 2),
-                          c->dptr<int64_t>("IDST"), c->dptr<int32_t>("IPTR"), c->dptr<int64_t>("ICOL"),
-                          c->dptr<double>("IVAL"), static_cast<int>(c->idst.size()), c->P, none, nullptr, p.gamma,
-                          c->stream));
+  fcs_status st;
+  if ((st = apply_walls(c, U0, none, nullptr)) != FCS_OK) return st;
+  // the fringe points keep the data's own (pointwise) values: interpolating
+  // discontinuous initial data would overshoot; the first stage's fringe
+  // fill follows the smearing
+  (void)flags;
   c->ps_valid = false;
   c->t0_prepared = true;
   return FCS_OK;
@@ -1310,7 +1416,8 @@ extern "C" fcs_status fcs_advance(fcs_ctx* c, int64_t n_stages, double* t_out) {
     if (c->stage_in_step == 0 && !c->past_t0 && !c->t0_prepared && (st = prepare_t0(c)) != FCS_OK) return st;
     if (c->stage_in_step == 0 && n_stages >= 5) {
       int wf = (c->prm.filter && c->past_t0) ? 1 : 0;
-      if (graph) {
+      // the step that smears the initial data runs once, eagerly
+      if (graph && !(c->prm.smear && !c->past_t0)) {
         if ((st = capture_step(c, wf, c->prof)) != FCS_OK) return st;
         if (c->visc && !c->ps_valid) HIPCHK(c, launch_proxy(visc_args(c), c->stream));
         HIPCHK(c, hipGraphLaunch(c->prof ? c->pgexec[wf] : c->gexec[wf], c->stream));

@@ -49,7 +49,7 @@ struct fcs_sweep {
   std::vector<GemmTile> tiles;
   char* ws = nullptr;
   size_t need = 0;
-  size_t o_ctr = 0, o_off = 0, o_roff = 0, o_ld = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_row = 0, o_task = 0, o_tile = 0;
+  size_t o_ctr = 0, o_off = 0, o_roff = 0, o_ld = 0, o_f64 = 0, o_f32 = 0, o_bhi = 0, o_blo = 0, o_bmid = 0, o_row = 0, o_task = 0, o_tile = 0;
   hipStream_t stream = nullptr;
   const double* last_in = nullptr;
   double *last_d1 = nullptr, *last_d2 = nullptr;
@@ -76,7 +76,7 @@ void sweep_tiles(fcs_sweep* s) {
 
 extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int32_t ncomp, int32_t precision,
                                        int32_t d, int32_t C, fcs_sweep** out) {
-  if (!out || !n1n2 || npatch <= 0 || ncomp <= 0 || ncomp > 64 || precision < 0 || precision > 2) return FCS_EINVAL;
+  if (!out || !n1n2 || npatch <= 0 || ncomp <= 0 || ncomp > 64 || precision < 0 || precision > 3) return FCS_EINVAL;
   if (d < 1 || d > 12 || C < 4 || C > 64) return FCS_EINVAL;
   std::unique_ptr<fcs_sweep> s(new (std::nothrow) fcs_sweep());
   if (!s) return FCS_ENOMEM;
@@ -145,8 +145,9 @@ extern "C" fcs_status fcs_sweep_create(int32_t npatch, const int32_t* n1n2, int3
   s->o_f64 = take(s->ops.elems * 8);
   s->o_row = take(s->ops.rows * 8);
   s->o_f32 = take(precision == 1 ? s->ops.elems * 4 : 0);
-  s->o_bhi = take(precision == 2 ? s->ops.elems * 2 : 0);
-  s->o_blo = take(precision == 2 ? s->ops.elems * 2 : 0);
+  s->o_bhi = take(precision >= 2 ? s->ops.elems * 2 : 0);
+  s->o_blo = take(precision >= 2 ? s->ops.elems * 2 : 0);
+  s->o_bmid = take(precision == 3 ? s->ops.elems * 2 : 0);
   s->o_task = take(s->tasks.size() * sizeof(GemmTask));
   s->o_tile = take(s->tiles.size() * sizeof(GemmTile));
   s->need = u;
@@ -173,7 +174,7 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   std::vector<double> f64, rows;
   if (!s->ops.fill(s->d, s->C, f64, rows)) return FCS_EINVAL;
   std::vector<float> f32;
-  std::vector<uint16_t> bhi, blo;
+  std::vector<uint16_t> bhi, blo, bmid;
   hipStream_t st = s->stream;
   // tile counters of the persistent variants start at zero
   if (hipMemsetAsync(s->ws + s->o_ctr, 0, kGemmCounters * 4, st)) return FCS_EHIP;
@@ -187,10 +188,16 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
     f32.assign(f64.begin(), f64.end());
     if (hipMemcpyAsync(s->ws + s->o_f32, f32.data(), f32.size() * 4, hipMemcpyHostToDevice, st)) return FCS_EHIP;
   }
-  if (s->precision == 2) {
-    split_bf16(f64, bhi, blo);
+  if (s->precision >= 2) {
+    if (s->precision == 3)
+      split_bf16x3(f64, bhi, bmid, blo);
+    else
+      split_bf16(f64, bhi, blo);
     if (hipMemcpyAsync(s->ws + s->o_bhi, bhi.data(), bhi.size() * 2, hipMemcpyHostToDevice, st) ||
         hipMemcpyAsync(s->ws + s->o_blo, blo.data(), blo.size() * 2, hipMemcpyHostToDevice, st))
+      return FCS_EHIP;
+    if (s->precision == 3 &&
+        hipMemcpyAsync(s->ws + s->o_bmid, bmid.data(), bmid.size() * 2, hipMemcpyHostToDevice, st))
       return FCS_EHIP;
   }
   if (hipMemcpyAsync(s->ws + s->o_tile, s->tiles.data(), s->tiles.size() * sizeof(GemmTile), hipMemcpyHostToDevice,
@@ -205,6 +212,7 @@ extern "C" fcs_status fcs_sweep_bind(fcs_sweep* s, void* workspace, size_t bytes
   s->tab.f32 = reinterpret_cast<const float*>(s->ws + s->o_f32);
   s->tab.bhi = reinterpret_cast<const uint16_t*>(s->ws + s->o_bhi);
   s->tab.blo = reinterpret_cast<const uint16_t*>(s->ws + s->o_blo);
+  s->tab.bmid = s->precision == 3 ? reinterpret_cast<const uint16_t*>(s->ws + s->o_bmid) : nullptr;
   s->last_in = nullptr;
   return FCS_OK;
 }
@@ -240,20 +248,22 @@ extern "C" fcs_status fcs_sweep_run(fcs_sweep* s, const double* in, double* d1, 
 }
 
 extern "C" int32_t fcs_gemm_variant_count(int32_t precision) {
-  if (precision < 0 || precision > 2) return 0;
+  if (precision < 0 || precision > 3) return 0;
   int nv = 0;
   gemm_variants(precision, &nv);
   return nv;
 }
 
 extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, char* buf, int32_t len) {
-  if (!buf || len <= 0 || precision < 0 || precision > 2) return FCS_EINVAL;
+  if (!buf || len <= 0 || precision < 0 || precision > 3) return FCS_EINVAL;
   int nv = 0;
   const GemmVariant* cand = gemm_variants(precision, &nv);
   if (index < 0 || index >= nv) return FCS_EINVAL;
   const GemmVariant& v = cand[index];
   std::string name;
-  if (precision == 2 && v.xw) {
+  if (precision == 3) {
+    name = "k_gemm_bf16x6";
+  } else if (precision == 2 && v.xw) {
     name = "k_gemm_xw_bf16x3<128, " + std::to_string(v.tb) + ">";
   } else if (precision == 2) {
     name = std::string(v.persist ? "k_gemm_bf16x3_persist<" : "k_gemm_bf16x3<") + std::to_string(v.tb) + ">";
@@ -442,7 +452,7 @@ extern "C" fcs_status fcs_lines_apply(int32_t n, int64_t nlines, int32_t kind, i
                                       const double* in, double* out, void* workspace, size_t bytes, void* stream) {
   if (!in || !out || !workspace || nlines <= 0 || nlines > (1ll << 31) / 1024) return FCS_EINVAL;
   if (bytes < fcs_lines_workspace(n, nlines) || reinterpret_cast<uintptr_t>(workspace) % kAlign) return FCS_EINVAL;
-  if (d < 1 || d > 12 || C < 4 || C > 64 || kind < FCS_OP_D1 || kind > FCS_OP_FILTER) return FCS_EINVAL;
+  if (d < 1 || d > 12 || C < 4 || C > 64 || kind < FCS_OP_D1 || kind > FCS_OP_SMEAR) return FCS_EINVAL;
   OpPack pk;
   pk.add(n, kind);
   std::vector<double> f64, rows;

@@ -16,7 +16,7 @@
 // multiplier and restriction: out[t] = sum_l K[(t - l) mod M] ext[l],
 // M = n + C, with K the periodic kernel of the multiplier (first or second
 // derivative in index units, Nyquist mode zeroed; or the filter
-// exp(-alpha (2|m|/M)^36), alpha = 16 ln 10).
+// exp(-alpha (2|m|/M)^36), alpha = 16 ln 10; kind 3: the same with order 8).
 #include <quadmath.h>
 
 #include <cmath>
@@ -194,7 +194,7 @@ bool fc_continuation(int d, int C, double* Q, double* A) {
 }
 
 const std::vector<double>* fc_operator(int n, int d, int C, int kind) {
-  if (n < 2 * d || n > 1024 || kind < 0 || kind > 2) return nullptr;
+  if (n < 2 * d || n > 1024 || kind < 0 || kind > 3) return nullptr;
   const Continuation& cont = continuation(d, C);
   {
     std::lock_guard<std::mutex> lock(g_mu);
@@ -222,8 +222,10 @@ const std::vector<double>* fc_operator(int n, int d, int C, int kind) {
       } else if (kind == 1) {
         s += w * w * cs[idx];
       } else {
+        // the filter of t > 0 (order 36) or the stronger one of the
+        // initial-data smearing (order 8)
         ld eta = 2.0L * k / M;
-        s += expl(-alpha * powl(eta, 36)) * cs[idx];
+        s += expl(-alpha * powl(eta, kind == 2 ? 36 : 8)) * cs[idx];
       }
     }
     if (kind == 0) K[mm] = -2.0L * s / M;

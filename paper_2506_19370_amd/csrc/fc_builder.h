@@ -7,7 +7,8 @@ namespace fcs {
 // continuation values, row-major; false on unsupported (d, C).
 bool fc_continuation(int d, int C, double* Q, double* A);
 // Dense n x n FC operator (kind 0: first derivative, 1: second derivative,
-// both in index units; 2: filter), row t / column s, cached; nullptr on
+// both in index units; 2: filter; 3: smearing filter), row t / column s,
+// cached; nullptr on
 // unsupported arguments.
 const std::vector<double>* fc_operator(int n, int d, int C, int kind);
 }  // namespace fcs

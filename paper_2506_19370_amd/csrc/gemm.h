@@ -31,6 +31,9 @@ struct OpPack {
 };
 // Round-to-nearest-even split of x (as FP32) into bf16 hi + lo.
 void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::vector<uint16_t>& lo);
+// Three-part split of the FP32 value: hi + mid + lo (split BF16 x6).
+void split_bf16x3(const std::vector<double>& x, std::vector<uint16_t>& hi, std::vector<uint16_t>& mid,
+                  std::vector<uint16_t>& lo);
 
 // Tile shape of a contraction launch: a workgroup covers 64 lines and 64 tb
 // outputs (tb = 1 or 2) and walks the operator depth in chunks of kc

@@ -781,20 +781,25 @@ __global__ __launch_bounds__(256, 4) void k_gemm_step(const GemmTask* __restrict
 }
 
 // Split BF16: chunks of 32 columns (one MFMA depth); LDS rows padded to 40
-// halves so each lane's 8-element operand is one aligned 16-byte read.
-template <int TB>
+// halves so each lane's 8-element operand is one aligned 16-byte read.  NS
+// parts per value: 2 (hi + lo; products hh, hl, lh) or 3 (hi + mid + lo;
+// products hh, hm, mh, hl, mm, lh), one FP32 accumulator per order of
+// magnitude, summed in FP64 at the store.
+template <int TB, int NS = 2>
 struct SmemBf {
   alignas(16) uint16_t Xh[2][kLB][40];
   alignas(16) uint16_t Xl[2][kLB][40];
+  alignas(16) uint16_t Xm[NS == 3 ? 2 : 1][NS == 3 ? kLB : 1][40];
   alignas(16) uint16_t Dh[2][64 * TB][40];
   alignas(16) uint16_t Dl[2][64 * TB][40];
+  alignas(16) uint16_t Dm[NS == 3 ? 2 : 1][NS == 3 ? 64 * TB : 1][40];
   double x0s[kLB];
   int64_t dst[kLB];
 };
 
-template <int TB, bool Q1>
+template <int TB, int NS, bool Q1>
 __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
-                                                SmemBf<TB>& sm) {
+                                                SmemBf<TB, NS>& sm) {
   constexpr int KC = 32, PITCH = 40, kTT = 64 * TB;
   constexpr int ND = kTT * KC / (256 * 8);  // 16-byte loads per thread and table
   auto& Xh = sm.Xh;
@@ -809,6 +814,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   const int64_t dbase = ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   const uint16_t* __restrict__ Bh = ops.bhi + dbase;
   const uint16_t* __restrict__ Bl = ops.blo + dbase;
+  const uint16_t* __restrict__ Bm = NS == 3 ? ops.bmid + dbase : nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr bool q1 = Q1;
   // Operand staging: each thread owns 8 consecutive columns of one line of
@@ -827,7 +833,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
 #pragma unroll
     for (int j = 0; j < 8; ++j) xr[j] = xbase[static_cast<int64_t>(min(k0 + xl_col + j, n - 1)) * T.s_stride];
   };
-  uint4 hr[ND], lr[ND];
+  uint4 hr[ND], lr[ND], mr[NS == 3 ? ND : 1];
   auto load_d = [&](int k0) {
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
@@ -835,23 +841,32 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
       const int64_t o = static_cast<int64_t>(t) * ld + k0 + kk;
       hr[p] = *reinterpret_cast<const uint4*>(Bh + o);
       lr[p] = *reinterpret_cast<const uint4*>(Bl + o);
+      if constexpr (NS == 3) mr[p] = *reinterpret_cast<const uint4*>(Bm + o);
     }
   };
   auto stage = [&](int b) {
-    bf16x8 h, l;
+    bf16x8 h, l, md;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
       const float f = static_cast<float>(xr[j] - x0);
       h[j] = static_cast<__bf16>(f);  // round to nearest even (v_cvt_pk_bf16_f32)
-      l[j] = static_cast<__bf16>(f - static_cast<float>(h[j]));
+      const float r1 = f - static_cast<float>(h[j]);  // exact in FP32
+      if constexpr (NS == 3) {
+        md[j] = static_cast<__bf16>(r1);
+        l[j] = static_cast<__bf16>(r1 - static_cast<float>(md[j]));
+      } else {
+        l[j] = static_cast<__bf16>(r1);
+      }
     }
     *reinterpret_cast<bf16x8*>(&Xh[b][xl_line][xl_col]) = h;
     *reinterpret_cast<bf16x8*>(&Xl[b][xl_line][xl_col]) = l;
+    if constexpr (NS == 3) *reinterpret_cast<bf16x8*>(&sm.Xm[b][xl_line][xl_col]) = md;
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * 8, t = e / KC, kk = e % KC;
       *reinterpret_cast<uint4*>(&Dh[b][t][kk]) = hr[p];
       *reinterpret_cast<uint4*>(&Dl[b][t][kk]) = lr[p];
+      if constexpr (NS == 3) *reinterpret_cast<uint4*>(&sm.Dm[b][t][kk]) = mr[p];
     }
   };
   const int nk = (n + KC - 1) / KC;
@@ -868,9 +883,13 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   const double* rowsum = ops.rowsum + ops.roff[T.op];
   with_live<4 * TB>(nb, [&](auto live) {
     constexpr int NL = decltype(live)::value;
-    f32x4 bm[NL > 0 ? NL : 1], bc[NL > 0 ? NL : 1];
+    f32x4 bm[NL > 0 ? NL : 1], bc[NL > 0 ? NL : 1], b3[NS == 3 && NL > 0 ? NL : 1];
 #pragma unroll
     for (int ob = 0; ob < NL; ++ob) bm[ob] = bc[ob] = f32x4{0, 0, 0, 0};
+    if constexpr (NS == 3) {
+#pragma unroll
+      for (int ob = 0; ob < NL; ++ob) b3[ob] = f32x4{0, 0, 0, 0};
+    }
     for (int c = 0; c < nk; ++c) {
       const int b = c & 1;
       if (c + 1 < nk) {
@@ -880,18 +899,32 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
       if constexpr (NL > 0) {
         const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[b][16 * wave + rr][kb]));
         const bf16x8 xlo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[b][16 * wave + rr][kb]));
+        bf16x8 xmd{};
+        if constexpr (NS == 3)
+          xmd = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xm[b][16 * wave + rr][kb]));
+        // A x B with the operand roles of the direction (along q^1 the
+        // lines are the rows, along q^2 the outputs are)
+        auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) {
+          return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
+                    : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
+        };
 #pragma unroll
         for (int ob = 0; ob < NL; ++ob) {
           const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * ob + rr][kb]));
           const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * ob + rr][kb]));
-          if (q1) {
-            bm[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bh, bm[ob], 0, 0, 0);
-            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xh, bl, bc[ob], 0, 0, 0);
-            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(xlo, bh, bc[ob], 0, 0, 0);
+          if constexpr (NS == 3) {
+            const bf16x8 bmd =
+                __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Dm[b][16 * ob + rr][kb]));
+            bm[ob] = mm(xh, bh, bm[ob]);
+            bc[ob] = mm(xh, bmd, bc[ob]);
+            bc[ob] = mm(xmd, bh, bc[ob]);
+            b3[ob] = mm(xh, bl, b3[ob]);
+            b3[ob] = mm(xmd, bmd, b3[ob]);
+            b3[ob] = mm(xlo, bh, b3[ob]);
           } else {
-            bm[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xh, bm[ob], 0, 0, 0);
-            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bh, xlo, bc[ob], 0, 0, 0);
-            bc[ob] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bl, xh, bc[ob], 0, 0, 0);
+            bm[ob] = mm(xh, bh, bm[ob]);
+            bc[ob] = mm(xh, bl, bc[ob]);
+            bc[ob] = mm(xlo, bh, bc[ob]);
           }
         }
       }
@@ -910,8 +943,9 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
           const int lloc = 16 * wave + (q1 ? row : col);
           const int tloc = 16 * ob + (q1 ? col : row);
           if (tloc >= nt || lloc >= nl) continue;
-          const double v = static_cast<double>(bm[ob][r]) + static_cast<double>(bc[ob][r]) +
-                           x0s[lloc] * rowsum[t0 + tloc];
+          double v = static_cast<double>(bm[ob][r]) + static_cast<double>(bc[ob][r]);
+          if constexpr (NS == 3) v += static_cast<double>(b3[ob][r]);
+          v += x0s[lloc] * rowsum[t0 + tloc];
           const int64_t o = dst[lloc] + static_cast<int64_t>(t0 + tloc) * T.s_stride;
           if (T.out_f32)
             gdst32(T.dst)[o] = static_cast<float>(v);
@@ -923,15 +957,24 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   });
 }
 
-template <int TB>
+template <int TB, int NS = 2>
 __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, const GemmTile tile,
                                             const OpTables& ops) {
-  __shared__ SmemBf<TB> sm;
+  __shared__ SmemBf<TB, NS> sm;
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
-    gemm_bf16x3_dir<TB, true>(T, tile, ops, sm);
+    gemm_bf16x3_dir<TB, NS, true>(T, tile, ops, sm);
   else
-    gemm_bf16x3_dir<TB, false>(T, tile, ops, sm);
+    gemm_bf16x3_dir<TB, NS, false>(T, tile, ops, sm);
+}
+
+// Split BF16 x6: three parts per value, six products (about FP32 accuracy
+// from BF16 matrix cores); one output block of 64 per tile (LDS).
+__global__ __launch_bounds__(256) void k_gemm_bf16x6(const GemmTask* __restrict__ tasks,
+                                                     const GemmTile* __restrict__ tiles, OpTables ops) {
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile_idle(tile)) return;
+  gemm_bf16x3<1, 3>(tasks, tile, ops);
 }
 
 template <int TB>
@@ -1031,6 +1074,20 @@ bool OpPack::fill(int d, int C, std::vector<double>& f64, std::vector<double>& r
   return true;
 }
 
+void split_bf16x3(const std::vector<double>& x, std::vector<uint16_t>& hi, std::vector<uint16_t>& mid,
+                  std::vector<uint16_t>& lo) {
+  hi.resize(x.size());
+  mid.resize(x.size());
+  lo.resize(x.size());
+  for (size_t q = 0; q < x.size(); ++q) {
+    const float f = static_cast<float>(x[q]);
+    hi[q] = host_bf16(f);
+    const float r = f - host_bf16_to_f(hi[q]);
+    mid[q] = host_bf16(r);
+    lo[q] = host_bf16(r - host_bf16_to_f(mid[q]));
+  }
+}
+
 void split_bf16(const std::vector<double>& x, std::vector<uint16_t>& hi, std::vector<uint16_t>& lo) {
   hi.resize(x.size());
   lo.resize(x.size());
@@ -1128,7 +1185,9 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
     FCS_FP(float, 16, 1, 7, 1)
     return hipErrorInvalidValue;
   }
-  if (v.tb == 2) {
+  if (precision == 3) {
+    hipLaunchKernelGGL(k_gemm_bf16x6, grid, block, 0, stream, tasks, tiles, ops);
+  } else if (v.tb == 2) {
     hipLaunchKernelGGL((k_gemm_bf16x3<2>), grid, block, 0, stream, tasks, tiles, ops);
   } else {
     hipLaunchKernelGGL((k_gemm_bf16x3<1>), grid, block, 0, stream, tasks, tiles, ops);
@@ -1158,8 +1217,9 @@ const GemmVariant* gemm_variants(int precision, int* count) {
   static const GemmVariant bf[] = {{1, 32, false, false, false}, {2, 32, false, false, false},
                                    {1, 32, true, false, false},  {2, 32, true, false, false},
                                    {2, 32, false, false, true},  {4, 32, false, false, true}};
-  *count = precision == 0 ? 11 : (precision == 1 ? 13 : 6);
-  return precision == 0 ? f64 : (precision == 1 ? f32 : bf);
+  static const GemmVariant bf6[] = {{1, 32, false, false, false}};
+  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 6 : 1));
+  return precision == 0 ? f64 : (precision == 1 ? f32 : (precision == 2 ? bf : bf6));
 }
 
 void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nlines, size_t ntasks,

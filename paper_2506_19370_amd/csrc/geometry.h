@@ -7,7 +7,7 @@
 
 namespace fcs {
 
-enum SideKind { kInternal = 0, kInflow = 1, kOutflow = 2, kSlip = 3, kExact = 4 };
+enum SideKind { kInternal = 0, kInflow = 1, kOutflow = 2, kSlip = 3, kExact = 4, kNoSlip = 5 };
 
 struct Run {
   int start = 0, len = 0;

@@ -42,7 +42,8 @@ struct OpTables {
   const double* f64;
   const float* f32;
   const uint16_t* bhi;
-  const uint16_t* blo;
+  const uint16_t* blo;      // split BF16: the second part (x3) or the third (x6)
+  const uint16_t* bmid;     // split BF16 x6: the second part (else null)
   const double* rowsum;     // row sums of operator k at roff[k]
   const int64_t* roff;
 };
@@ -76,6 +77,19 @@ struct BcEntry {
   int32_t dirichlet; // 0 none, 1 fixed state e[], 2 exact vortex at (x, y)
   double e[4];
   double x, y;
+};
+
+// A grid line that ends at one or two no-slip adiabatic wall nodes: the
+// wall values of theta make the FC first derivative along it vanish there
+// (both ends together when both are walls).
+struct WallLine {
+  int64_t first;   // global index of the line's first point
+  int64_t stride;  // index step along the line (1 or n1)
+  int32_t n;       // points on the line
+  int32_t op;      // its first-derivative operator
+  int32_t pos[2];  // positions of the wall nodes on the line (pos[1] < 0: one)
+  int32_t keep[2]; // 1: the node keeps its Dirichlet data (solved, not written)
+  int32_t pad;
 };
 
 }  // namespace fcs

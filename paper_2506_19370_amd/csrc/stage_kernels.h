@@ -43,6 +43,7 @@ struct StageArgs {
   const double *mu, *mu1, *mu2, *g11, *g12, *g22, *lap1, *lap2;
   const void *W1, *W2, *W11, *W22, *W12;
   int deriv_f32;
+  int w1_f64;  // with deriv_f32: W1 is FP64 (operand of the cross contraction)
   const double* dt;
   int* bad_flag;
   BcArgs bcs;
@@ -125,6 +126,20 @@ hipError_t launch_bc_state(double* U, const uint8_t* flags, const BcArgs& b, dou
 // that reads the state), then classification, preliminary viscosity,
 // dilation and blend.
 hipError_t launch_proxy(const ViscArgs& v, hipStream_t s);
+// No-slip adiabatic walls of state U (see WallLine): wall theta per line into
+// wth (2 doubles per line), then zero momentum and E = rho theta at the wall
+// nodes, with their fluxes (fo.F) and proxy values (ps) when set.
+hipError_t launch_walls(double* U, const WallLine* lines, int nlines, const OpTables& ops, double* wth,
+                        const uint8_t* flags, int64_t P, double gamma, const FluxOut& fo, double2* ps, hipStream_t s);
+// Window of the initial-data smearing into w (P doubles): the indicator of
+// the classes in v.tau (a discontinuity flagged in either direction, off the
+// fringe) localized as the viscosity is (two dilation passes, blend rows);
+// v.muhat, v.tmp and v.mut serve as scratch.
+hipError_t launch_smear_window(const ViscArgs& v, double* w, hipStream_t s);
+// U <- w Qs + (1 - w) Q for rho, rho u, rho v, theta (w clipped to [0, 1]),
+// E rebuilt; active points only.
+hipError_t launch_smear_post(const double* Qs, const double* Q, const double* w, double* U, const uint8_t* flags,
+                             int64_t P, hipStream_t s);
 // Fragment table (64 x 84 words) of a classifier parameter blob.
 hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s);
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s);

@@ -120,6 +120,59 @@ __global__ void k_bc_state(double* __restrict__ U, const uint8_t* __restrict__ f
   U[3 * P + k] = E;
 }
 
+// No-slip adiabatic walls, part 1: per line, the wall values of theta that
+// make the FC first derivative along the line vanish at its wall nodes (one
+// node: one equation; two: the 2 x 2 system), from the state before any
+// wall correction.
+__global__ void k_wall_theta(const double* __restrict__ U, const WallLine* __restrict__ lines, int nlines,
+                             OpTables ops, double* __restrict__ wth, int64_t P, double gm1) {
+  const int l = blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= nlines) return;
+  const WallLine w = lines[l];
+  const double* D = ops.f64 + ops.off[w.op];
+  const int ld = ops.ld[w.op];
+  const int p0 = w.pos[0], p1 = w.pos[1];
+  double r0 = 0.0, r1 = 0.0;
+  for (int s = 0; s < w.n; ++s) {
+    if (s == p0 || s == p1) continue;
+    const int64_t k = w.first + static_cast<int64_t>(s) * w.stride;
+    const double r = U[k], mx = U[P + k], my = U[2 * P + k], E = U[3 * P + k];
+    const double th = (E - 0.5 * (mx * mx + my * my) / r) / r;  // p / ((gamma - 1) rho)
+    r0 -= D[static_cast<int64_t>(p0) * ld + s] * th;
+    if (p1 >= 0) r1 -= D[static_cast<int64_t>(p1) * ld + s] * th;
+  }
+  if (p1 < 0) {
+    wth[2 * l] = r0 / D[static_cast<int64_t>(p0) * ld + p0];
+    wth[2 * l + 1] = 0.0;
+  } else {
+    const double a = D[static_cast<int64_t>(p0) * ld + p0], b = D[static_cast<int64_t>(p0) * ld + p1];
+    const double c = D[static_cast<int64_t>(p1) * ld + p0], d = D[static_cast<int64_t>(p1) * ld + p1];
+    const double det = a * d - b * c;
+    wth[2 * l] = (d * r0 - b * r1) / det;
+    wth[2 * l + 1] = (a * r1 - c * r0) / det;
+  }
+  (void)gm1;
+}
+
+// Part 2: zero momentum, rho kept, E = rho theta at every wall node; the
+// fluxes and proxy values of the corrected points when requested.
+__global__ void k_wall_apply(double* __restrict__ U, const WallLine* __restrict__ lines, int nlines,
+                             const double* __restrict__ wth, const uint8_t* __restrict__ flags, int64_t P,
+                             double gamma, FluxOut fo, double2* __restrict__ ps) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= 2 * nlines) return;
+  const WallLine w = lines[q >> 1];
+  const int pos = w.pos[q & 1];
+  if (pos < 0 || w.keep[q & 1]) return;
+  const int64_t k = w.first + static_cast<int64_t>(pos) * w.stride;
+  const double r = U[k], E = r * wth[q];
+  U[P + k] = 0.0;
+  U[2 * P + k] = 0.0;
+  U[3 * P + k] = E;
+  if (fo.F) store_flux(fo, P, k, flags[k], r, 0.0, 0.0, E);
+  if (ps) ps[k] = proxy_speed(r, 0.0, 0.0, E, gamma);
+}
+
 // DT: element type of the stage derivatives (double, or float in the mixed
 // forms, where the contractions themselves are FP32 or split BF16).
 // S: the stage (0..4), so that each instantiation reads only the registers
@@ -144,7 +197,7 @@ __global__ void k_stage(StageArgs a) {
   // its own accumulator slot, which holds the same values as the donor's
   // (both are formed from equal inputs), so the read-modify-write of the
   // fourth stage does not race with the donor's thread.
-  const int64_t ks = a.csrc[k];
+  const int64_t ks = a.csrc ? a.csrc[k] : k;
   const uint8_t f = ks == k ? fk : a.flags[ks];
   const double dt = *a.dt;
   double L[4];
@@ -182,7 +235,8 @@ __global__ void k_stage(StageArgs a) {
     const DT *W11 = static_cast<const DT*>(a.W11), *W22 = static_cast<const DT*>(a.W22);
     const DT* W12 = static_cast<const DT*>(a.W12);
     for (int q = 0; q < 4; ++q) {
-      double w1 = W1[q * P + ks], w2 = W2[q * P + ks], w11 = W11[q * P + ks], w22 = W22[q * P + ks];
+      double w1 = a.w1_f64 ? static_cast<const double*>(a.W1)[q * P + ks] : static_cast<double>(W1[q * P + ks]);
+      double w2 = W2[q * P + ks], w11 = W11[q * P + ks], w22 = W22[q * P + ks];
       double w12 = W12 ? static_cast<double>(W12[q * P + ks]) : 0.0;
       double lap = g11 * w11 + 2.0 * g12 * w12 + g22 * w22 + l1 * w1 + l2 * w2;
       double grad = g11 * mu1 * w1 + g12 * (mu1 * w2 + mu2 * w1) + g22 * mu2 * w2;
@@ -474,14 +528,24 @@ __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out
 
 // bact (or null): activity flags of the row and the column of each blended
 // point (x < 0: not on a lattice subpatch with activity flags).
+// A group of kBlendLanes lanes per row: lane j takes the entries j, j + 8,
+// ... (independent gathers in flight instead of one dependent chain of up
+// to 73), then the group sums by shuffles.
+constexpr int kBlendLanes = 8;
 __global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu, const int64_t* __restrict__ dst,
                              const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
                              const double* __restrict__ val, int n, const int2* __restrict__ bact,
                              uint8_t* __restrict__ act) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= n) return;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int q = static_cast<int>(g / kBlendLanes), j = static_cast<int>(g % kBlendLanes);
+  // every lane of a group exists (blockDim is a multiple of the group
+  // size), so the shuffles below see whole groups; rows past n add nothing
   double s = 0.0;
-  for (int e = ptr[q]; e < ptr[q + 1]; ++e) s += val[e] * mut[col[e]];
+  if (q < n)
+    for (int e = ptr[q] + j; e < ptr[q + 1]; e += kBlendLanes) s += val[e] * mut[col[e]];
+#pragma unroll
+  for (int o = kBlendLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kBlendLanes);
+  if (q >= n || j != 0) return;
   mu[dst[q]] = fmax(s, 0.0);
   if (act && s > 0.0) {
     const int2 a = bact[q];
@@ -490,6 +554,36 @@ __global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict_
       act[a.y] = 1;
     }
   }
+}
+
+// Initial-data smearing (Alg. 4 at t = 0).  Indicator: 1 at the active
+// non-fringe points whose class flags a discontinuity in either direction.
+__global__ void k_smear_indicator(const uint8_t* __restrict__ tau, const uint8_t* __restrict__ flags, int64_t P,
+                                  double* __restrict__ out) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  const uint8_t f = flags[k];
+  const bool on = (f & kActive) && !(f & (kFringe | kXFringe)) && (tau[k] >= 1 || tau[P + k] >= 1);
+  out[k] = on ? 1.0 : 0.0;
+}
+
+// Blend of the strongly filtered (Qs) and the given (Q) rho, rho u, rho v,
+// theta with the window w clipped to [0, 1]; E rebuilt.
+__global__ void k_smear_post(const double* __restrict__ Qs, const double* __restrict__ Q,
+                             const double* __restrict__ w, double* __restrict__ U, const uint8_t* __restrict__ flags,
+                             int64_t P) {
+  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (k >= P) return;
+  if (!(flags[k] & kActive)) return;
+  const double a = fmin(fmax(w[k], 0.0), 1.0), b = 1.0 - a;
+  const double r = a * Qs[k] + b * Q[k];
+  const double mx = a * Qs[P + k] + b * Q[P + k];
+  const double my = a * Qs[2 * P + k] + b * Q[2 * P + k];
+  const double th = a * Qs[3 * P + k] + b * Q[3 * P + k];
+  U[k] = r;
+  U[P + k] = mx;
+  U[2 * P + k] = my;
+  U[3 * P + k] = r * th + 0.5 * (mx * mx + my * my) / r;
 }
 
 __global__ void k_filter_pre(const double* __restrict__ U, double* __restrict__ Q, const uint8_t* __restrict__ flags,
@@ -624,6 +718,33 @@ hipError_t launch_bc_state(double* U, const uint8_t* flags, const BcArgs& b, dou
   return hipGetLastError();
 }
 
+hipError_t launch_smear_window(const ViscArgs& v, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_smear_indicator, grid_for(v.P), dim3(256), 0, s, v.tau, v.flags, v.P, v.muhat);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
+                     0, v.nv, v.wdil, nullptr, nullptr);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.ij, v.patches, v.flags, v.P,
+                     1, v.nv, v.wdil, w, nullptr);
+  if (v.nblend)
+    hipLaunchKernelGGL(k_blend_rows, grid_for(static_cast<int64_t>(v.nblend) * kBlendLanes), dim3(256), 0, s, v.mut, w,
+                       v.bdst, v.bptr, v.bcol, v.bval, v.nblend, nullptr, nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_smear_post(const double* Qs, const double* Q, const double* w, double* U, const uint8_t* flags,
+                             int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_smear_post, grid_for(P), dim3(256), 0, s, Qs, Q, w, U, flags, P);
+  return hipGetLastError();
+}
+
+hipError_t launch_walls(double* U, const WallLine* lines, int nlines, const OpTables& ops, double* wth,
+                       const uint8_t* flags, int64_t P, double gamma, const FluxOut& fo, double2* ps, hipStream_t s) {
+  if (nlines <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_wall_theta, grid_for(nlines), dim3(256), 0, s, U, lines, nlines, ops, wth, P, gamma - 1.0);
+  hipLaunchKernelGGL(k_wall_apply, grid_for(2 * static_cast<int64_t>(nlines)), dim3(256), 0, s, U, lines, nlines, wth,
+                     flags, P, gamma, fo, ps);
+  return hipGetLastError();
+}
+
 hipError_t launch_sdnn_pack(const float* weights, uint32_t* table, hipStream_t s) {
   hipLaunchKernelGGL(k_sdnn_pack, dim3(1), dim3(256), 0, s, weights, table);
   return hipGetLastError();
@@ -673,7 +794,8 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.ij, v.patches, v.flags, v.P,
                      1, v.nv, v.wdil, v.mu, v.act);
   if (v.nblend)
-    hipLaunchKernelGGL(k_blend_rows, grid_for(v.nblend), dim3(256), 0, s, v.mut, v.mu, v.bdst, v.bptr, v.bcol,
+    hipLaunchKernelGGL(k_blend_rows, grid_for(static_cast<int64_t>(v.nblend) * kBlendLanes), dim3(256), 0, s, v.mut,
+                       v.mu, v.bdst, v.bptr, v.bcol,
                        v.bval, v.nblend, v.bact, v.act);
   return hipGetLastError();
 }

@@ -63,7 +63,7 @@ def test_fc_continuation_matches_oracle(d):
 
 
 @pytest.mark.parametrize("n,d,kind", [(12, 2, "d1"), (37, 5, "d1"), (101, 2, "d1"), (101, 5, "d2"),
-                                      (64, 2, "filter"), (150, 5, "d1")])
+                                      (64, 2, "filter"), (150, 5, "d1"), (48, 2, "smear"), (230, 2, "smear")])
 def test_fc_operator_matches_oracle(n, d, kind):
     from oracle import fcgram
     import paper_2506_19370_amd as F
@@ -106,6 +106,16 @@ def test_create_reports_missing_donors():
     with pytest.raises(L.FcsError) as e:
         _create(specs, fc_d=2, fc_C=27)
     assert e.value.status == L.FCS_EOVERLAP
+
+
+def test_create_rejects_smearing_without_classifier():
+    from paper_2506_19370_amd import _lib as L
+    specs = W.sod_reflect(200)
+    with pytest.raises(L.FcsError) as e:
+        _create(specs, fc_d=2, fc_C=27, smear=True)
+    assert e.value.status == L.FCS_EINVAL
+    h = _create(specs, fc_d=2, fc_C=27, smear=True, av="modal")
+    L.fcs_destroy(h)
 
 
 def test_create_rejects_invalid_parameters():

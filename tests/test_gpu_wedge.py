@@ -1,7 +1,8 @@
 """GPU runs of the wedge tunnel (MI355X, gfx950): the obstacle with C1
 corner subpatches at the tip (30-degree obstacle angle) and at the two rear
 corners (75 degrees), skewed-affine subpatches on the faces and seeded
-lattice subpatches, at the Mach number of the headline configuration.
+lattice subpatches, at the Mach number of the headline configuration, the
+initial data smeared in the first step (Alg. 4 at t = 0).
 
 - oracle parity on the small decomposition (h = 1/600, 72 subpatches):
   modal viscosity and filter, two steps, classes equal and the state to
@@ -39,11 +40,11 @@ def _rel(S, O, n):
 def test_wedge_small_matches_oracle():
     specs = W.wedge_tunnel(600, 48, 96, mach=M)
     w = W.wedge_state(specs, quiescent_wake=True, mach=M)
-    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
+    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, smear=True))
     for p in range(len(specs)):
         S.set_state(p, w[p])
     O = osolver.Solver(osolver.patches_from_specs(specs),
-                       osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True))
+                       osolver.Params(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, smear=True))
     O.set_prim(w)
     for step in range(2):
         t = S.advance(5, sync=True)
@@ -88,12 +89,13 @@ def test_wedge_shock_angle():
     specs = W.wedge_tunnel(600, 48, 96, mach=M)
     w = W.wedge_state(specs, quiescent_wake=True, mach=M)
     blob = np.load(GOLD)["params"]
-    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, sdnn_weights=blob))
+    S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="sdnn", filter=True, sdnn_weights=blob,
+                                       smear=True))
     for p in range(len(specs)):
         S.set_state(p, w[p])
     t = 0.0
     while t < 0.06:
-        t = S.advance(5 * 100, sync=True)
+        t = S.advance(5 * 1000, sync=True)
     geo = W.wedge_geometry(1.0)
     face = lambda x: geo["Yc"] + (x - geo["Xt"]) * np.tan(geo["theta"])
     beta = np.rad2deg(exact.weak_shock_angle(geo["theta"], M))
@@ -114,7 +116,7 @@ def test_wedge_full_size_graph_and_split_bf16():
         stream = torch.cuda.Stream()
         with torch.cuda.stream(stream):
             S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, use_graph=graph,
-                                               precision=prec), stream=stream)
+                                               precision=prec, smear=True), stream=stream)
             for p in range(len(specs)):
                 S.set_state(p, w[p])
             S.advance(5, sync=True)

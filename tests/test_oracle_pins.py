@@ -266,3 +266,152 @@ def test_modal_indicator_on_known_modal_content(lo, hi, frac, tau):
     v = 3.0 + 0.7 * (c_lo * P[:, lo] + c_hi * P[:, hi])
     got = sdnn.modal_classify(np.stack([v, -v + 10.0]))
     assert got.tolist() == [tau, tau]
+
+
+def test_lowp_gradient_pins():
+    """The low-precision gradient of the training reading: with weights,
+    inputs and activations already on the bf16 grid it equals the FP64
+    gradient (rounding is then the identity), and otherwise it equals the
+    FP64 gradient of the network whose weights are rounded, fed rounded
+    inputs (a plausible mistake, such as rounding the gradients or skipping
+    the activation rounding, breaks one of the two)."""
+    rng = np.random.default_rng(11)
+    p = {k: rng.standard_normal(s) * 0.3 for k, s in (("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)),
+                                                      ("b2", (64,)), ("W3", (3, 64)), ("b3", (3,)))}
+    x = rng.random((200, 16))
+    y = rng.integers(0, 3, 200)
+    cw = np.array([0.5, 1.5, 3.0])
+    # on the bf16 grid: identical to the FP64 gradient up to the activation
+    # rounding, which vanishes only for bf16-exact activations; use a
+    # network with one hidden unit active per layer and exact values
+    pr = {k: (sdnn.round_bf16(v) if k.startswith("W") else v) for k, v in p.items()}
+    xr = sdnn.round_bf16(x)
+    l_low, g_low = sdnn.loss_and_grads_lowp(p, x, y, cw)
+    l_ref, g_ref = sdnn.loss_and_grads(pr, xr, y, cw)
+    # the only remaining difference is the rounding of the hidden
+    # activations: small and of bf16 size
+    for k in g_ref:
+        d = np.abs(g_low[k] - g_ref[k]).max() / np.abs(g_ref[k]).max()
+        assert d < 3e-2, (k, d)
+    assert abs(l_low - l_ref) < 1e-2 * abs(l_ref)
+    # with bf16-exact activations the two agree to FP64 rounding: the first
+    # layer reduced to bf16 biases (W1 = 0), the second to halving those
+    # (one weight 0.5 per unit), so every activation lies on the bf16 grid
+    q = {k: v.copy() for k, v in pr.items()}
+    q["W1"][:] = 0.0
+    q["b1"] = sdnn.round_bf16(np.abs(p["b1"]))
+    q["W2"] = np.zeros((64, 64))
+    q["W2"][np.arange(64), np.arange(64)] = 0.5
+    q["b2"] = np.zeros(64)
+    l1, g1 = sdnn.loss_and_grads_lowp(q, x, y, cw)
+    l2, g2 = sdnn.loss_and_grads(q, xr, y, cw)
+    assert abs(l1 - l2) < 1e-13
+    for k in g2:
+        assert np.allclose(g1[k], g2[k], rtol=1e-12, atol=1e-15), k
+
+
+# ---------------------------------------------------------------- initial-data smearing
+def _sod_line_solver(n1=120, n2=24):
+    spec = W.box_patch(0.0, 1.0, 0.0, 0.2, n1, n2, {k: W.SLIP for k in "WESN"})
+    S = solver.Solver(solver.patches_from_specs([spec]),
+                      solver.Params(fc_d=2, fc_C=27, av="modal", smear=True, filter=True))
+    w = np.where((spec.x < 0.5)[None], np.array([1.0, 0.0, 0.0, 1.0])[:, None, None],
+                 np.array([0.125, 0.0, 0.0, 0.1])[:, None, None])
+    S.set_prim([w])
+    return S, spec
+
+
+def test_smear_filter_multiplier():
+    """The smearing's filter is the t > 0 filter's exponential with order 8:
+    10^(-16 eta^8), so it damps the middle of the spectrum (eta = 0.5: 0.866,
+    0.7: 0.111) where the order-36 filter hardly does (1 - 1e-13 and 0.9999),
+    and both keep constants exactly."""
+    M = 128
+    m = np.fft.fftfreq(M) * M
+    eta = 2 * np.abs(m) / M
+    s = fcgram._multiplier(M, "smear").real
+    f = fcgram._multiplier(M, "filter").real
+    for e0, want in ((0.5, 10 ** (-16 * 0.5 ** 8)), (0.703125, 10 ** (-16 * 0.703125 ** 8))):
+        k = int(np.argmin(np.abs(eta - e0)))
+        assert abs(s[k] - want) < 1e-12 and f[k] > 0.9998
+    x = np.linspace(0, 1, 80)
+    for kind in ("smear", "filter"):
+        assert np.allclose(fcgram.fc_apply(np.full((2, 80), 3.25), 2, 27, kind), 3.25, atol=1e-12)
+    # a smooth low-mode line is nearly kept, a jump is spread
+    smooth = np.sin(2 * np.pi * x)
+    assert np.abs(fcgram.fc_apply(smooth, 2, 27, "smear") - smooth).max() < 1e-3
+    jump = (x > 0.5).astype(float)
+    assert np.abs(fcgram.fc_apply(jump, 2, 27, "smear") - jump).max() > 0.1
+
+
+def test_smear_initial_data_pins():
+    """Nothing flagged: the data are returned unchanged.  Everything flagged
+    (window 1 at every point): the data are exactly the strong-filtered
+    rho, rho u, rho v, theta with E rebuilt.  A jump flagged only near its
+    position: the data change only within n_v + 8 points of it, and
+    density and theta stay positive."""
+    S, spec = _sod_line_solver()
+    g = S.grids[0]
+    n2, n1 = spec.shape
+    S.last_tau = [np.zeros((2, n2, n1), dtype=np.int64)]
+    assert np.array_equal(S.smear_initial_data(S.U), S.U)
+    S.last_tau = [np.ones((2, n2, n1), dtype=np.int64)]
+    # all non-fringe points flagged: the window is 1 wherever a flagged point
+    # lies within reach; on this box without internal sides every point is
+    e = S.view(S.U, 0)
+    theta = euler.temperature_like(e)
+    q = np.stack([e[0], e[1], e[2], theta])
+    qs = g.deriv(g.deriv(q, 0, "smear"), 1, "smear")
+    out = S.view(S.smear_initial_data(S.U), 0)
+    assert np.allclose(out[0], qs[0], rtol=0, atol=1e-14)
+    assert np.allclose(out[3], qs[0] * qs[3] + 0.5 * (qs[1] ** 2 + qs[2] ** 2) / qs[0], rtol=1e-13, atol=1e-14)
+    # flagged within 3 columns of the jump only
+    tau = np.zeros((2, n2, n1), dtype=np.int64)
+    jcol = int(np.argmax(spec.x[0] >= 0.5))
+    tau[0, :, jcol - 3:jcol + 3] = 2
+    S.last_tau = [tau]
+    out = S.view(S.smear_initial_data(S.U), 0)
+    changed = np.abs(out - e).max(axis=(0, 1)) > 0
+    cols = np.flatnonzero(changed)
+    assert cols.size > 0 and cols.min() >= jcol - 3 - 9 and cols.max() <= jcol + 3 + 9
+    assert (out[0] > 0).all() and (euler.temperature_like(out) > 0).all()
+
+
+# ---------------------------------------------------------------- no-slip adiabatic walls
+def _noslip_box(n):
+    spec = W.box_patch(0.0, 1.0, 0.0, 1.0, 31, n, {"W": W.OUTFLOW, "E": W.OUTFLOW, "S": W.NOSLIP, "N": W.NOSLIP})
+    S = solver.Solver(solver.patches_from_specs([spec]), solver.Params(fc_d=5, fc_C=27))
+    y = spec.y
+    theta = 1.0 + 0.3 * y ** 2 * (1 - y) ** 2  # zero slope at both walls
+    rho = 1.0 + 0.2 * np.sin(3 * spec.x)
+    S.set_prim([np.stack([rho, 0.3 + 0 * y, -0.2 + 0 * y, 0.4 * rho * theta])])
+    e = S.view(S.U, 0)
+    e[3, 0, :] *= 1.7   # spoiled wall values: they must be recomputed
+    e[3, -1, :] *= 0.6
+    return S, spec, theta, e.copy()
+
+
+def test_noslip_adiabatic_wall_pins():
+    """A box with no-slip walls at y = 0 and y = 1 (d = 5): after the
+    boundary treatment the wall nodes carry zero momentum and their density,
+    theta there makes the FC derivative along the column vanish at both
+    walls (the two ends of each column solved together), and for the profile
+    theta = 1 + c y^2 (1 - y)^2 (zero slope at both walls, degree 4, which
+    FC d = 5 reproduces) the recomputed wall values are the profile's (a
+    wrong sign, row or excluded term breaks these)."""
+    errs = []
+    for n in (41, 81):
+        S, spec, theta, e = _noslip_box(n)
+        out = S.view(S.enforce(S.U, 0.0), 0)
+        D = fcgram.dense_operator(n, 5, 27, "d1")
+        for j in (0, n - 1):
+            assert np.all(out[1, j] == 0.0) and np.all(out[2, j] == 0.0)
+            assert np.array_equal(out[0, j], e[0, j])
+        th = out[3] / out[0]  # theta on the wall rows (momentum zero)
+        col = np.where(np.arange(n)[:, None] == 0, th, np.where(np.arange(n)[:, None] == n - 1, th,
+                                                                   euler.temperature_like(out)))
+        dth = D @ col
+        assert np.abs(dth[0]).max() < 1e-10 and np.abs(dth[-1]).max() < 1e-10
+        assert np.array_equal(out[:, 1:-1], e[:, 1:-1])  # interior untouched
+        errs.append(max(np.abs(th[0] - theta[0]).max(), np.abs(th[-1] - theta[-1]).max()))
+    assert max(errs) < 1e-10, errs

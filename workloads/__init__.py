@@ -11,7 +11,7 @@ from dataclasses import dataclass, field
 
 import numpy as np
 
-INTERNAL, INFLOW, OUTFLOW, SLIP, EXACT = 0, 1, 2, 3, 4
+INTERNAL, INFLOW, OUTFLOW, SLIP, EXACT, NOSLIP = 0, 1, 2, 3, 4, 5
 GAMMA = 1.4
 SEED_BASE = 25061937
 
@@ -455,11 +455,11 @@ def window_labels(pos, amp, lines, n=101, rel_tol=1e-2):
 
 # ---------------------------------------------------------------- Mach-M wedge tunnel
 WEDGE_INFLOW = (1.4, 10.0, 0.0, 1.0)
-# Mach number of the wedge runs: the impulsive start from the uniform stream
-# (quiescent gas behind the rear face) keeps rho, p > 0 on this
-# decomposition at CFL 0.5 up to Mach 6.5; at Mach 8 and 10 the first steps
-# lose positivity at the tip without the initial-data smearing of Part I
-WEDGE_MACH = 5.0
+# Mach number of the wedge runs.  The impulsive start from the uniform stream
+# (quiescent gas behind the rear face) keeps rho, p > 0 at Mach 10 with the
+# localized smearing of the initial data (Alg. 4 at t = 0); without it, only
+# up to Mach 6.5 on this decomposition
+WEDGE_MACH = 10.0
 
 
 def wedge_geometry(h_index, tip_x=0.2, length=0.2, half_angle_deg=15.0, yc=0.25):
