@@ -10,6 +10,11 @@ import ctypes
 import os
 
 import numpy as np
+# PyTorch first: its HIP runtime (the same soname as ROCm's) is then the one
+# the library binds to, so that both share one runtime, its devices and
+# streams.  Loaded the other way round, PyTorch runs on the system runtime,
+# which it was not built against.
+import torch  # noqa: F401,E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIBPATH = os.path.join(HERE, "libfcsdnn.so")

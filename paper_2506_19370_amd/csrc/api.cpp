@@ -992,11 +992,17 @@ fcs_status per_step(fcs_ctx* c) {
   if (p.smear && !c->past_t0) {
     // Alg. 4 at t = 0 (after the viscosity, which Alg. 1 evaluates first):
     // the window from this step's classes, the strongly filtered rho, rho u,
-    // rho v, theta (FCS_OP_SMEAR along q^1 then q^2) and the blend; the
-    // window is held in the (not yet used) W11 array
+    // rho v, theta (FCS_OP_SMEAR along q^1 then q^2) and the blend.  The
+    // indicator and the window are held in the first stage's output buffer,
+    // not yet written in this step: mu-hat stays this step's, and the
+    // viscous derivative arrays hold nothing but derivatives (the stage
+    // kernel multiplies their values on skipped lines by exact zeros, so
+    // they must stay finite: FP64 window values read as FP32 pairs in the
+    // mixed forms are not)
     const uint8_t* flags = c->dptr<uint8_t>("FLAGS");
-    double* w = c->arr[A_W11];
-    HIPCHK(c, launch_smear_window(v, w, c->stream));
+    double* ind = c->arr[A_UA];
+    double* w = c->arr[A_UA] + P;
+    HIPCHK(c, launch_smear_window(v, ind, w, c->stream));
     HIPCHK(c, launch_filter_pre(U0, c->arr[A_F], flags, P, p.gamma, c->stream));
     if ((st = run_gemm(c, PH_SMEAR1, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;
     if ((st = run_gemm(c, PH_SMEAR2, 0, FCS_PREC_FP64, false)) != FCS_OK) return st;

@@ -133,9 +133,9 @@ hipError_t launch_walls(double* U, const WallLine* lines, int nlines, const OpTa
                         const uint8_t* flags, int64_t P, double gamma, const FluxOut& fo, double2* ps, hipStream_t s);
 // Window of the initial-data smearing into w (P doubles): the indicator of
 // the classes in v.tau (a discontinuity flagged in either direction, off the
-// fringe) localized as the viscosity is (two dilation passes, blend rows);
-// v.muhat, v.tmp and v.mut serve as scratch.
-hipError_t launch_smear_window(const ViscArgs& v, double* w, hipStream_t s);
+// fringe; into ind, P doubles) localized as the viscosity is (two dilation
+// passes, blend rows); v.tmp and v.mut serve as scratch.
+hipError_t launch_smear_window(const ViscArgs& v, double* ind, double* w, hipStream_t s);
 // U <- w Qs + (1 - w) Q for rho, rho u, rho v, theta (w clipped to [0, 1]),
 // E rebuilt; active points only.
 hipError_t launch_smear_post(const double* Qs, const double* Q, const double* w, double* U, const uint8_t* flags,

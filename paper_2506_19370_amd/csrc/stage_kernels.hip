@@ -718,9 +718,9 @@ hipError_t launch_bc_state(double* U, const uint8_t* flags, const BcArgs& b, dou
   return hipGetLastError();
 }
 
-hipError_t launch_smear_window(const ViscArgs& v, double* w, hipStream_t s) {
-  hipLaunchKernelGGL(k_smear_indicator, grid_for(v.P), dim3(256), 0, s, v.tau, v.flags, v.P, v.muhat);
-  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
+hipError_t launch_smear_window(const ViscArgs& v, double* ind, double* w, hipStream_t s) {
+  hipLaunchKernelGGL(k_smear_indicator, grid_for(v.P), dim3(256), 0, s, v.tau, v.flags, v.P, ind);
+  hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, ind, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
                      0, v.nv, v.wdil, nullptr, nullptr);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.tmp, v.mut, v.pid, v.ij, v.patches, v.flags, v.P,
                      1, v.nv, v.wdil, w, nullptr);

@@ -64,3 +64,29 @@ def test_smeared_wedge_start_matches_oracle():
         assert np.array_equal(S.field(p, "tau0"), O.last_tau[p][0]), p
         assert np.array_equal(S.field(p, "tau1"), O.last_tau[p][1]), p
     assert _rel(S, O, len(specs)) < 1e-11
+
+
+@pytest.mark.parametrize("prec,tol", [("fp32", 2e-6), ("bf16x6", 2e-6), ("bf16x3", 1e-4)])
+def test_smeared_wedge_start_mixed_forms(prec, tol):
+    """The smeared first step in the mixed forms (FP32 or split-BF16 stage
+    contractions, FP32 stage derivatives) against the FP64 form on the small
+    wedge: the classes of the first step come from the same initial data,
+    the smearing runs in FP64 in every form, so the states differ by the
+    contraction's bound only (the sweep tolerance, relative to max|U|).  The
+    smearing window must not pass through the derivative arrays that the
+    stage kernel reads in FP32 (a window value read as an FP32 pair can be
+    a NaN)."""
+    specs = W.wedge_tunnel(600, 48, 96)
+    w = W.wedge_state(specs)
+    res = {}
+    for form in ("fp64", prec):
+        S = F.Solver(specs, F.SolverParams(fc_d=2, fc_C=27, cfl=0.5, av="modal", filter=True, smear=True,
+                                           precision=form))
+        for p in range(len(specs)):
+            S.set_state(p, w[p])
+        S.advance(5, sync=True)
+        res[form] = [S.cons(p) for p in range(len(specs))]
+        del S
+    scale = max(np.abs(r).max() for r in res["fp64"])
+    err = max(np.abs(a - b).max() for a, b in zip(res[prec], res["fp64"])) / scale
+    assert np.isfinite(err) and err < tol, (prec, err)
