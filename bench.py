@@ -53,7 +53,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the step channel, derivative-sweep and classifier measurements")
-    ap.add_argument("--forms", default="bf16x3,fp64,fp32",
+    ap.add_argument("--forms", default="bf16x3,fp64,fp32,bf16x6",
                     help="contraction precisions to run on the wedge (the first is the headline value)")
     ap.add_argument("--eager", action="store_true", help="launch kernels one by one instead of replaying step graphs "
                                                            "(for per-dispatch counter runs)")
@@ -139,7 +139,7 @@ def sweep_bench(F, W, torch):
     d1, d2 = torch.empty_like(x), torch.empty_like(x)
     out = {"workload": "2000 patches, sides U{64..256}, 4 fields, d/dq1 and d/dq2, FC d=5 C=27, one launch",
            "points": int(sum(int(a) * int(b) for a, b in sizes))}
-    for prec in ("fp64", "fp32", "bf16x3"):
+    for prec in ("fp64", "fp32", "bf16x3", "bf16x6"):
         sw = F.DerivSweep(sizes, 4, prec, d=5, C=27)
         sw.autotune(x, d1, d2)
         sw.profile(1)
@@ -147,9 +147,10 @@ def sweep_bench(F, W, torch):
             sw.run(x, d1, d2)
         r = sw.profile(-1)
         rate = r["flops"] / (r["avg_ms"] * 1e-3)
-        own = PEAK["fp32"] if prec == "bf16x3" else PEAK[prec]
+        split = prec.startswith("bf16")
+        own = PEAK["fp32"] if split else PEAK[prec]
         out[prec] = {"ms": r["avg_ms"], "tflops": rate / 1e12, "frac_of_fp32_peak": rate / PEAK["fp32"],
-                     "frac_of_own_peak": rate / own if prec != "bf16x3" else None,
+                     "frac_of_own_peak": rate / own if not split else None,
                      "algorithmic_GBps": r["bytes"] / (r["avg_ms"] * 1e-3) / 1e9}
         del sw
     return out
@@ -261,12 +262,12 @@ def roofline_of(prof, precision, kernel):
     """Roofline entries of a stage contraction timed alone: achieved
     algorithmic HBM bytes per second against HBM, and dense MFMA flops
     (2n per point per line operation) against the precision's MFMA peak
-    (split BF16: the BF16 peak, three products per product)."""
+    (split BF16: the BF16 peak, three or six products per product)."""
     sec = prof["avg_ms"] * 1e-3
     gbps = prof["bytes"] / sec
     flops = prof["flops"] / sec
-    mfma_peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"]}[precision]
-    mfma_rate = flops * (3.0 if precision == "bf16x3" else 1.0)
+    mfma_peak = {"fp64": PEAK["fp64"], "fp32": PEAK["fp32"], "bf16x3": PEAK["bf16"], "bf16x6": PEAK["bf16"]}[precision]
+    mfma_rate = flops * {"bf16x3": 3.0, "bf16x6": 6.0}.get(precision, 1.0)
     return {"kernel": kernel, "avg_launch_ms": prof["avg_ms"], "launches_timed": prof["launches"],
             "algorithmic_bytes_per_launch": prof["bytes"], "dense_flops_per_launch": prof["flops"],
             "hbm": {"achieved_GBps": gbps / 1e9, "peak_GBps": HBM_PEAK / 1e9, "frac": gbps / HBM_PEAK},
@@ -432,7 +433,7 @@ def main():
     wedge = wedge_run(F, W, torch, weights, forms, a.steps, a.warmup, eager=a.eager, stage_variant=a.stage_variant)
     head = forms[0]
     rf = wedge[head]["stage_contraction"]
-    dtype = {"bf16x3": "bf16x3+f64", "fp32": "f32+f64", "fp64": "f64"}[head]
+    dtype = {"bf16x3": "bf16x3+f64", "bf16x6": "bf16x6+f64", "fp32": "f32+f64", "fp64": "f64"}[head]
     out = {
         "metric": "point-stage updates/s, plain FP64 vs mixed-precision batched form at stated error",
         "value": wedge[head]["value"], "unit": "point-stage updates/s", "n_gpus": 1, "steps": a.steps,

@@ -266,7 +266,9 @@ extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, ch
   } else if (precision == 2 && v.xw) {
     name = "k_gemm_xw_bf16x3<128, " + std::to_string(v.tb) + ">";
   } else if (precision == 2) {
-    name = std::string(v.persist ? "k_gemm_bf16x3_persist<" : "k_gemm_bf16x3<") + std::to_string(v.tb) + ">";
+    name = std::string(v.persist ? "k_gemm_bf16x3_persist<" : "k_gemm_bf16x3<") + std::to_string(v.tb);
+    if (!v.persist) name += ", " + std::to_string(v.kc) + ", " + std::to_string(v.pf);
+    name += ">";
   } else if (v.xw) {
     name = std::string("k_gemm_xw<") + (precision == 0 ? "double, 64, " : "float, 128, ") + std::to_string(v.tb) +
            ">";

@@ -11,11 +11,11 @@ namespace fcs {
 // Operator tables are stored zero-padded: operator k occupies
 // op_rows(n) x op_ld(n) elements (row-major, leading dimension op_ld), so a
 // contraction tile never tests operator bounds.  The padding is sized for the
-// largest tile (256 outputs) and the deepest chunk (32 columns).
+// largest tile (256 outputs) and the deepest chunk (64 columns, split BF16).
 constexpr int kOpRowPad = 256;
 // Device counters (ints) that one persistent contraction launch uses.
 constexpr int kGemmCounters = 16;
-constexpr int kOpColPad = 32;
+constexpr int kOpColPad = 64;
 inline int op_ld(int n) { return (n + kOpColPad - 1) / kOpColPad * kOpColPad; }
 inline int op_rows(int n) { return (n + kOpRowPad - 1) / kOpRowPad * kOpRowPad; }
 

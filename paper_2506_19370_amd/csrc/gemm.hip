@@ -177,6 +177,15 @@ __device__ __forceinline__ void with_live(int nb, F&& f) {
   }
 }
 
+// Calls f(std::integral_constant<int, u>{}) for u = 0 .. N - 1 in order.
+template <int N, int U = 0, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (U < N) {
+    f(std::integral_constant<int, U>{});
+    static_for<N, U + 1>(f);
+  }
+}
+
 // FP64 or FP32 operands on the 16x16x4 MFMA of that type.
 template <typename Elem, int KC, int TB>
 struct SmemFp {
@@ -780,28 +789,42 @@ __global__ __launch_bounds__(256, 4) void k_gemm_step(const GemmTask* __restrict
   gemm_fp<double, 16, 1>(tasks, tile, ops);
 }
 
-// Split BF16: chunks of 32 columns (one MFMA depth); LDS rows padded to 40
-// halves so each lane's 8-element operand is one aligned 16-byte read.  NS
-// parts per value: 2 (hi + lo; products hh, hl, lh) or 3 (hi + mid + lo;
-// products hh, hm, mh, hl, mm, lh), one FP32 accumulator per order of
-// magnitude, summed in FP64 at the store.
-template <int TB, int NS = 2>
+// Split BF16: chunks of KC columns (one or two MFMA depths of 32); LDS rows
+// padded by 8 halves so each lane's 8-element operand is one aligned 16-byte
+// read.  NS parts per value: 2 (hi + lo; products hh, hl, lh) or 3 (hi +
+// mid + lo; products hh, hm, mh, hl, mm, lh), one FP32 accumulator per
+// order of magnitude, summed in FP64 at the store.
+template <int TB, int NS = 2, int KC = 32>
 struct SmemBf {
-  alignas(16) uint16_t Xh[2][kLB][40];
-  alignas(16) uint16_t Xl[2][kLB][40];
-  alignas(16) uint16_t Xm[NS == 3 ? 2 : 1][NS == 3 ? kLB : 1][40];
-  alignas(16) uint16_t Dh[2][64 * TB][40];
-  alignas(16) uint16_t Dl[2][64 * TB][40];
-  alignas(16) uint16_t Dm[NS == 3 ? 2 : 1][NS == 3 ? 64 * TB : 1][40];
+  static constexpr int PITCH = KC + 8;
+  alignas(16) uint16_t Xh[2][kLB][PITCH];
+  alignas(16) uint16_t Xl[2][kLB][PITCH];
+  alignas(16) uint16_t Xm[NS == 3 ? 2 : 1][NS == 3 ? kLB : 1][PITCH];
+  alignas(16) uint16_t Dh[2][64 * TB][PITCH];
+  alignas(16) uint16_t Dl[2][64 * TB][PITCH];
+  alignas(16) uint16_t Dm[NS == 3 ? 2 : 1][NS == 3 ? 64 * TB : 1][PITCH];
   double x0s[kLB];
   int64_t dst[kLB];
 };
 
-template <int TB, int NS, bool Q1>
+// Registers of one chunk's global loads (operand lines and operator rows).
+template <int NXG, int ND, int NS>
+struct BfChunk {
+  double xr[8 * NXG];
+  uint4 hr[ND], lr[ND], mr[NS == 3 ? ND : 1];
+};
+
+// One tile of the split-BF16 contraction.  The chunk loop keeps PF chunks'
+// global loads in flight: A holds chunk c + 1 while the products of chunk c
+// run, and is staged into the free LDS buffer after them; with PF = 2, B
+// holds chunk c + 2, moves into A, and is refilled with chunk c + 3 (plain
+// register moves: no slot is indexed at run time).
+template <int TB, int NS, int KC, int PF, bool Q1>
 __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
-                                                SmemBf<TB, NS>& sm) {
-  constexpr int KC = 32, PITCH = 40, kTT = 64 * TB;
+                                                SmemBf<TB, NS, KC>& sm) {
+  constexpr int kTT = 64 * TB;
   constexpr int ND = kTT * KC / (256 * 8);  // 16-byte loads per thread and table
+  constexpr int NXG = KC / 32;              // groups of 8 columns per thread
   auto& Xh = sm.Xh;
   auto& Xl = sm.Xl;
   auto& Dh = sm.Dh;
@@ -817,63 +840,122 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   const uint16_t* __restrict__ Bm = NS == 3 ? ops.bmid + dbase : nullptr;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr bool q1 = Q1;
-  // Operand staging: each thread owns 8 consecutive columns of one line of
-  // the chunk (along q^1 four threads share a line, along q^2 neighbouring
-  // threads hold neighbouring lines), splits them with packed conversions and
-  // stores 16 bytes per table.
-  const int xl_line = q1 ? tid >> 2 : tid & 63, xl_col = 8 * (q1 ? tid & 3 : tid >> 6);
-  const gdouble* __restrict__ xbase = gsrc(T.src) + line_base(T, min(tile.line0 + xl_line, nlines - 1));
-  const double x0 = xbase[0];  // line offset (first point of the line)
+  // Operand staging.  Along q^2 (lines adjacent in memory) thread t owns
+  // line t % 64 and NXG groups of 8 consecutive columns: each load reads 64
+  // neighbouring lines at one column, and each group is split with packed
+  // conversions and stored as 16 bytes per table.  Along q^1 (columns
+  // contiguous) thread t owns column pair 2 (t % 16), +1 (and +32 per
+  // further group) of the four lines t / 16 + 16 i: sixteen lanes read one
+  // line's chunk, and each pair is stored as 4 bytes per table.
+  const int pc = 2 * (tid & 15), qs = tid >> 4;              // q^1 mapping
+  const int xl_line = tid & 63, xl_col = 8 * (tid >> 6);    // q^2 mapping
+  const gdouble* xb[q1 ? 4 : 1];
+  double x0v[q1 ? 4 : 1];
+#pragma unroll
+  for (int i = 0; i < (q1 ? 4 : 1); ++i) {
+    xb[i] = gsrc(T.src) + line_base(T, min(tile.line0 + (q1 ? qs + 16 * i : xl_line), nlines - 1));
+    x0v[i] = xb[i][0];  // line offset (first point of the line)
+  }
   if (tid < kLB) {
     dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
     x0s[tid] = gsrc(T.src)[dst[tid]];
   }
-  double xr[8];
-  auto load_x = [&](int k0) {
+  using Chunk = BfChunk<NXG, ND, NS>;
+  Chunk A, B;
+  auto load = [&](Chunk& r, int k0) __attribute__((always_inline)) {
+    if constexpr (q1) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) xr[j] = xbase[static_cast<int64_t>(min(k0 + xl_col + j, n - 1)) * T.s_stride];
-  };
-  uint4 hr[ND], lr[ND], mr[NS == 3 ? ND : 1];
-  auto load_d = [&](int k0) {
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < NXG; ++g)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+            r.xr[8 * g + 2 * i + h] = xb[i][min(k0 + 32 * g + pc + h, n - 1)];
+    } else {
+#pragma unroll
+      for (int g = 0; g < NXG; ++g)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          r.xr[8 * g + j] = xb[0][static_cast<int64_t>(min(k0 + 32 * g + xl_col + j, n - 1)) * T.s_stride];
+    }
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * 8, t = e / KC, kk = e % KC;
       const int64_t o = static_cast<int64_t>(t) * ld + k0 + kk;
-      hr[p] = *reinterpret_cast<const uint4*>(Bh + o);
-      lr[p] = *reinterpret_cast<const uint4*>(Bl + o);
-      if constexpr (NS == 3) mr[p] = *reinterpret_cast<const uint4*>(Bm + o);
+      r.hr[p] = *reinterpret_cast<const uint4*>(Bh + o);
+      r.lr[p] = *reinterpret_cast<const uint4*>(Bl + o);
+      if constexpr (NS == 3) r.mr[p] = *reinterpret_cast<const uint4*>(Bm + o);
     }
   };
-  auto stage = [&](int b) {
-    bf16x8 h, l, md;
+  // hi (+ mid) + lo parts of x - x0 (FP32 difference, parts rounded to
+  // nearest even by v_cvt_pk_bf16_f32; each remainder is exact in FP32)
+  struct Parts {
+    __bf16 h, md, l;
+  };
+  auto split = [&](double v, double x0) __attribute__((always_inline)) {
+    Parts o;
+    const float f = static_cast<float>(v - x0);
+    o.h = static_cast<__bf16>(f);
+    const float r1 = f - static_cast<float>(o.h);
+    if constexpr (NS == 3) {
+      o.md = static_cast<__bf16>(r1);
+      o.l = static_cast<__bf16>(r1 - static_cast<float>(o.md));
+    } else {
+      o.md = o.h;
+      o.l = static_cast<__bf16>(r1);
+    }
+    return o;
+  };
+  auto stage = [&](const Chunk& r, int b) __attribute__((always_inline)) {
+    if constexpr (q1) {
+      typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const float f = static_cast<float>(xr[j] - x0);
-      h[j] = static_cast<__bf16>(f);  // round to nearest even (v_cvt_pk_bf16_f32)
-      const float r1 = f - static_cast<float>(h[j]);  // exact in FP32
-      if constexpr (NS == 3) {
-        md[j] = static_cast<__bf16>(r1);
-        l[j] = static_cast<__bf16>(r1 - static_cast<float>(md[j]));
-      } else {
-        l[j] = static_cast<__bf16>(r1);
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int g = 0; g < NXG; ++g) {
+          bf16x2 h, l, md;
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const Parts o = split(r.xr[8 * g + 2 * i + q], x0v[i]);
+            h[q] = o.h;
+            md[q] = o.md;
+            l[q] = o.l;
+          }
+          const int line = qs + 16 * i, col = 32 * g + pc;
+          *reinterpret_cast<bf16x2*>(&Xh[b][line][col]) = h;
+          *reinterpret_cast<bf16x2*>(&Xl[b][line][col]) = l;
+          if constexpr (NS == 3) *reinterpret_cast<bf16x2*>(&sm.Xm[b][line][col]) = md;
+        }
+    } else {
+#pragma unroll
+      for (int g = 0; g < NXG; ++g) {
+        bf16x8 h, l, md;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const Parts o = split(r.xr[8 * g + j], x0v[0]);
+          h[j] = o.h;
+          md[j] = o.md;
+          l[j] = o.l;
+        }
+        *reinterpret_cast<bf16x8*>(&Xh[b][xl_line][xl_col + 32 * g]) = h;
+        *reinterpret_cast<bf16x8*>(&Xl[b][xl_line][xl_col + 32 * g]) = l;
+        if constexpr (NS == 3) *reinterpret_cast<bf16x8*>(&sm.Xm[b][xl_line][xl_col + 32 * g]) = md;
       }
     }
-    *reinterpret_cast<bf16x8*>(&Xh[b][xl_line][xl_col]) = h;
-    *reinterpret_cast<bf16x8*>(&Xl[b][xl_line][xl_col]) = l;
-    if constexpr (NS == 3) *reinterpret_cast<bf16x8*>(&sm.Xm[b][xl_line][xl_col]) = md;
 #pragma unroll
     for (int p = 0; p < ND; ++p) {
       const int e = (tid + 256 * p) * 8, t = e / KC, kk = e % KC;
-      *reinterpret_cast<uint4*>(&Dh[b][t][kk]) = hr[p];
-      *reinterpret_cast<uint4*>(&Dl[b][t][kk]) = lr[p];
-      if constexpr (NS == 3) *reinterpret_cast<uint4*>(&sm.Dm[b][t][kk]) = mr[p];
+      *reinterpret_cast<uint4*>(&Dh[b][t][kk]) = r.hr[p];
+      *reinterpret_cast<uint4*>(&Dl[b][t][kk]) = r.lr[p];
+      if constexpr (NS == 3) *reinterpret_cast<uint4*>(&sm.Dm[b][t][kk]) = r.mr[p];
     }
   };
   const int nk = (n + KC - 1) / KC;
-  load_x(0);
-  load_d(0);
-  stage(0);
+  load(A, 0);
+  stage(A, 0);
   __syncthreads();
+  if (1 < nk) load(A, KC);
+  if (PF == 2 && 2 < nk) load(B, 2 * KC);
   const int rr = lane & 15, kb = 8 * (lane >> 4);
   // Wave w owns the 16 lines 16 w .. 16 w + 15 and every output block of the
   // tile; blocks past the line end are skipped by all waves alike (the chunk
@@ -881,7 +963,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   // kernel).
   const int nb = 16 * wave < nl && !((tile.skip >> wave) & 1) ? (nt + 15) >> 4 : 0;
   const double* rowsum = ops.rowsum + ops.roff[T.op];
-  with_live<4 * TB>(nb, [&](auto live) {
+  with_live<4 * TB>(nb, [&](auto live) __attribute__((always_inline)) {
     constexpr int NL = decltype(live)::value;
     f32x4 bm[NL > 0 ? NL : 1], bc[NL > 0 ? NL : 1], b3[NS == 3 && NL > 0 ? NL : 1];
 #pragma unroll
@@ -890,49 +972,59 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
 #pragma unroll
       for (int ob = 0; ob < NL; ++ob) b3[ob] = f32x4{0, 0, 0, 0};
     }
-    for (int c = 0; c < nk; ++c) {
-      const int b = c & 1;
-      if (c + 1 < nk) {
-        load_x((c + 1) * KC);
-        load_d((c + 1) * KC);
-      }
+    // A x B with the operand roles of the direction (along q^1 the lines are
+    // the rows, along q^2 the outputs are)
+    auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) __attribute__((always_inline)) {
+      return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
+                : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
+    };
+    auto products = [&](int b) __attribute__((always_inline)) {
       if constexpr (NL > 0) {
-        const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[b][16 * wave + rr][kb]));
-        const bf16x8 xlo = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[b][16 * wave + rr][kb]));
-        bf16x8 xmd{};
-        if constexpr (NS == 3)
-          xmd = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xm[b][16 * wave + rr][kb]));
-        // A x B with the operand roles of the direction (along q^1 the
-        // lines are the rows, along q^2 the outputs are)
-        auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) {
-          return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
-                    : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
-        };
 #pragma unroll
-        for (int ob = 0; ob < NL; ++ob) {
-          const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * ob + rr][kb]));
-          const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * ob + rr][kb]));
-          if constexpr (NS == 3) {
-            const bf16x8 bmd =
-                __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Dm[b][16 * ob + rr][kb]));
-            bm[ob] = mm(xh, bh, bm[ob]);
-            bc[ob] = mm(xh, bmd, bc[ob]);
-            bc[ob] = mm(xmd, bh, bc[ob]);
-            b3[ob] = mm(xh, bl, b3[ob]);
-            b3[ob] = mm(xmd, bmd, b3[ob]);
-            b3[ob] = mm(xlo, bh, b3[ob]);
-          } else {
-            bm[ob] = mm(xh, bh, bm[ob]);
-            bc[ob] = mm(xh, bl, bc[ob]);
-            bc[ob] = mm(xlo, bh, bc[ob]);
+        for (int ks = 0; ks < NXG; ++ks) {
+          const int kc = kb + 32 * ks;
+          const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xh[b][16 * wave + rr][kc]));
+          const bf16x8 xlo =
+              __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Xl[b][16 * wave + rr][kc]));
+          bf16x8 xmd{};
+          if constexpr (NS == 3)
+            xmd = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xm[b][16 * wave + rr][kc]));
+#pragma unroll
+          for (int ob = 0; ob < NL; ++ob) {
+            const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dh[b][16 * ob + rr][kc]));
+            const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&Dl[b][16 * ob + rr][kc]));
+            if constexpr (NS == 3) {
+              const bf16x8 bmd =
+                  __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Dm[b][16 * ob + rr][kc]));
+              bm[ob] = mm(xh, bh, bm[ob]);
+              bc[ob] = mm(xh, bmd, bc[ob]);
+              bc[ob] = mm(xmd, bh, bc[ob]);
+              b3[ob] = mm(xh, bl, b3[ob]);
+              b3[ob] = mm(xmd, bmd, b3[ob]);
+              b3[ob] = mm(xlo, bh, b3[ob]);
+            } else {
+              bm[ob] = mm(xh, bh, bm[ob]);
+              bc[ob] = mm(xh, bl, bc[ob]);
+              bc[ob] = mm(xlo, bh, bc[ob]);
+            }
           }
         }
       }
-      if (c + 1 < nk) stage(b ^ 1);
+    };
+#pragma unroll 1
+    for (int c = 0; c < nk; ++c) {
+      products(c & 1);
+      if (c + 1 < nk) stage(A, (c + 1) & 1);
       __syncthreads();
+      if constexpr (PF == 2) {
+        A = B;
+        if (c + 3 < nk) load(B, (c + 3) * KC);
+      } else {
+        if (c + 2 < nk) load(A, (c + 2) * KC);
+      }
     }
-    // the two FP32 accumulations are added in FP64 at the store, with the
-    // exact offset term x0 * rowsum
+    // the FP32 accumulations are added in FP64 at the store, with the exact
+    // offset term x0 * rowsum
     if constexpr (NL > 0) {
 #pragma unroll
       for (int ob = 0; ob < NL; ++ob) {
@@ -957,15 +1049,15 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   });
 }
 
-template <int TB, int NS = 2>
+template <int TB, int NS = 2, int KC = 32, int PF = 1>
 __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, const GemmTile tile,
                                             const OpTables& ops) {
-  __shared__ SmemBf<TB, NS> sm;
+  __shared__ SmemBf<TB, NS, KC> sm;
   const GemmTask T = tasks[tile.task];
   if (T.s_stride == 1)
-    gemm_bf16x3_dir<TB, NS, true>(T, tile, ops, sm);
+    gemm_bf16x3_dir<TB, NS, KC, PF, true>(T, tile, ops, sm);
   else
-    gemm_bf16x3_dir<TB, NS, false>(T, tile, ops, sm);
+    gemm_bf16x3_dir<TB, NS, KC, PF, false>(T, tile, ops, sm);
 }
 
 // Split BF16 x6: three parts per value, six products (about FP32 accuracy
@@ -977,12 +1069,12 @@ __global__ __launch_bounds__(256) void k_gemm_bf16x6(const GemmTask* __restrict_
   gemm_bf16x3<1, 3>(tasks, tile, ops);
 }
 
-template <int TB>
+template <int TB, int KC = 32, int PF = 1>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3(const GemmTask* __restrict__ tasks,
                                                      const GemmTile* __restrict__ tiles, OpTables ops) {
   const GemmTile tile = tiles[blockIdx.x];
   if (tile_idle(tile)) return;
-  gemm_bf16x3<TB>(tasks, tile, ops);
+  gemm_bf16x3<TB, 2, KC, PF>(tasks, tile, ops);
 }
 
 template <int TB>
@@ -1187,10 +1279,18 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
   }
   if (precision == 3) {
     hipLaunchKernelGGL(k_gemm_bf16x6, grid, block, 0, stream, tasks, tiles, ops);
+  } else if (v.kc == 64) {
+    hipLaunchKernelGGL((k_gemm_bf16x3<1, 64, 1>), grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.tb == 2) {
-    hipLaunchKernelGGL((k_gemm_bf16x3<2>), grid, block, 0, stream, tasks, tiles, ops);
+    if (v.pf == 2)
+      hipLaunchKernelGGL((k_gemm_bf16x3<2, 32, 2>), grid, block, 0, stream, tasks, tiles, ops);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16x3<2>), grid, block, 0, stream, tasks, tiles, ops);
   } else {
-    hipLaunchKernelGGL((k_gemm_bf16x3<1>), grid, block, 0, stream, tasks, tiles, ops);
+    if (v.pf == 2)
+      hipLaunchKernelGGL((k_gemm_bf16x3<1, 32, 2>), grid, block, 0, stream, tasks, tiles, ops);
+    else
+      hipLaunchKernelGGL((k_gemm_bf16x3<1>), grid, block, 0, stream, tasks, tiles, ops);
   }
 #undef FCS_FP
   return hipGetLastError();
@@ -1216,9 +1316,11 @@ const GemmVariant* gemm_variants(int precision, int* count) {
                                     {1, 16, false, false, false, 1, 7}};
   static const GemmVariant bf[] = {{1, 32, false, false, false}, {2, 32, false, false, false},
                                    {1, 32, true, false, false},  {2, 32, true, false, false},
-                                   {2, 32, false, false, true},  {4, 32, false, false, true}};
+                                   {2, 32, false, false, true},  {4, 32, false, false, true},
+                                   {1, 32, false, false, false, 2}, {1, 64, false, false, false},
+                                   {2, 32, false, false, false, 2}};
   static const GemmVariant bf6[] = {{1, 32, false, false, false}};
-  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 6 : 1));
+  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 9 : 1));
   return precision == 0 ? f64 : (precision == 1 ? f32 : (precision == 2 ? bf : bf6));
 }
 

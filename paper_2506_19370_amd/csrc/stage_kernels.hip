@@ -396,72 +396,90 @@ __global__ void k_window_geo(ClassifyArgs a, int4* __restrict__ out) {
 // Alg. 3 with the SDNN: each wave classifies the two windows of 64 points
 // in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  Round
 // 2 pg + dir covers direction dir of the points 16 pg .. 16 pg + 15 of the
-// wave; the window geometry comes from the per-point table, is handed to the
-// rounds by lane shuffles, and each round's window values are fetched while
-// the previous round is on the matrix cores.  Lanes 0..15 write the classes
-// and the preliminary viscosity of the points of their rounds.
+// chunk; the window geometry comes from the per-point table, is handed to
+// the rounds by lane shuffles, and each round's window values are fetched
+// while the previous round is on the matrix cores.  Lanes 0..15 write the
+// classes and the preliminary viscosity of the points of their rounds.
+//
+// Persistent: the grid holds a fixed number of waves (a multiple of the 8
+// XCDs), each loads its weight fragments once and walks chunks of 64
+// points.  Workgroup b runs on XCD b % 8 and takes the chunks of the XCD's
+// contiguous share, so the grid rows that the column windows of
+// neighbouring chunks share stay in one XCD's L2.
+constexpr int kClassifyBlocks = 768;  // 3 workgroups of 4 waves per CU (occupancy 3)
+
 __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
   SdnnFrag F;
   load_sdnn_frag(a.sdnn_table, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
-  const int64_t kw = static_cast<int64_t>(blockIdx.x) * 256 + (threadIdx.x >> 6) * 64;
-  const int64_t kl = kw + lane;
-  const uint8_t fl = kl < a.P ? a.flags[kl] : 0;
-  const int4 geo = kl < a.P ? a.wgeo[kl] : int4{-1, 0, -1, 0};
-  // values (proxy, wave speed) of this lane's 4 window points in round (pg, dir)
-  auto fetch = [&](int pg, int dir, double2 (&q)[4]) -> bool {
-    const int src = 16 * pg + c;
-    const int base = __shfl(dir == 0 ? geo.x : geo.z, src);
-    const int stride = __shfl(dir == 0 ? geo.y : geo.w, src);
-    const bool valid = base >= 0;
-#pragma unroll
-    for (int j = 0; j < 4; ++j)
-      q[j] = valid ? a.ps[static_cast<int64_t>(base) + static_cast<int64_t>(4 * g + j) * stride] : double2{0.0, 0.0};
-    return valid;
-  };
-  double2 qc[4];
-  bool vc = fetch(0, 0, qc);
+  const int64_t nchunk = (a.P + 63) / 64;
+  const int xcd = static_cast<int>(blockIdx.x & 7);
+  const int64_t per_xcd = static_cast<int64_t>(gridDim.x >> 3) * 4;  // waves per XCD
+  const int64_t share = (nchunk + 7) / 8;
+  const int64_t c_end = min(nchunk, share * (xcd + 1));
 #pragma unroll 1
-  for (int pg = 0; pg < 4; ++pg) {
-    const int src = 16 * pg + c;  // lane that owns this round's point
-    int tau[2] = {0, 0};
-    double smax = 0.0;
+  for (int64_t ch = share * xcd + static_cast<int64_t>(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); ch < c_end;
+       ch += per_xcd) {
+    const int64_t kw = ch * 64;
+    const int64_t kl = kw + lane;
+    const uint8_t fl = kl < a.P ? a.flags[kl] : 0;
+    const int4 geo = kl < a.P ? a.wgeo[kl] : int4{-1, 0, -1, 0};
+    // values (proxy, wave speed) of this lane's 4 window points in round (pg, dir)
+    auto fetch = [&](int pg, int dir, double2 (&q)[4]) -> bool {
+      const int src = 16 * pg + c;
+      const int base = __shfl(dir == 0 ? geo.x : geo.z, src);
+      const int stride = __shfl(dir == 0 ? geo.y : geo.w, src);
+      const bool valid = base >= 0;
 #pragma unroll
-    for (int dir = 0; dir < 2; ++dir) {
-      double2 qn[4] = {};
-      bool vn = false;
-      if (dir == 0)
-        vn = fetch(pg, 1, qn);
-      else if (pg + 1 < 4)
-        vn = fetch(pg + 1, 0, qn);
-      double v[4], sp = 0.0;
+      for (int j = 0; j < 4; ++j)
+        q[j] = valid ? a.ps[static_cast<int64_t>(base) + static_cast<int64_t>(4 * g + j) * stride]
+                     : double2{0.0, 0.0};
+      return valid;
+    };
+    double2 qc[4];
+    bool vc = fetch(0, 0, qc);
+#pragma unroll 1
+    for (int pg = 0; pg < 4; ++pg) {
+      const int src = 16 * pg + c;  // lane that owns this round's point
+      int tau[2] = {0, 0};
+      double smax = 0.0;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        v[j] = qc[j].x;
-        sp = fmax(sp, qc[j].y);
+      for (int dir = 0; dir < 2; ++dir) {
+        double2 qn[4] = {};
+        bool vn = false;
+        if (dir == 0)
+          vn = fetch(pg, 1, qn);
+        else if (pg + 1 < 4)
+          vn = fetch(pg + 1, 0, qn);
+        double v[4], sp = 0.0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          v[j] = qc[j].x;
+          sp = fmax(sp, qc[j].y);
+        }
+        sp = fmax(sp, __shfl_xor(sp, 16));
+        sp = fmax(sp, __shfl_xor(sp, 32));
+        float x[4], z[3] = {0.0f, 0.0f, 0.0f};
+        const bool live = sdnn_features(v, x);
+        // a flat window is smooth without the network: a round of 16 flat
+        // windows skips it (the branch is uniform over the wave, and when
+        // taken all 64 lanes run the matrix instructions)
+        if (__ballot(live) != 0) sdnn_mfma(F, x, z);
+        if (vc) {
+          smax = fmax(smax, sp);
+          tau[dir] = live ? sdnn_argmax(z) : 0;
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) qc[j] = qn[j];
+        vc = vn;
       }
-      sp = fmax(sp, __shfl_xor(sp, 16));
-      sp = fmax(sp, __shfl_xor(sp, 32));
-      float x[4], z[3] = {0.0f, 0.0f, 0.0f};
-      const bool live = sdnn_features(v, x);
-      // a flat window is smooth without the network: a round of 16 flat
-      // windows skips it (the branch is uniform over the wave, and when taken
-      // all 64 lanes run the matrix instructions)
-      if (__ballot(live) != 0) sdnn_mfma(F, x, z);
-      if (vc) {
-        smax = fmax(smax, sp);
-        tau[dir] = live ? sdnn_argmax(z) : 0;
+      const int64_t k = kw + src;
+      const uint8_t f = __shfl(static_cast<int>(fl), src);
+      if (g == 0 && k < a.P) {
+        a.tau[k] = static_cast<uint8_t>(tau[0]);
+        a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
+        a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
       }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) qc[j] = qn[j];
-      vc = vn;
-    }
-    const int64_t k = kw + src;
-    const uint8_t f = __shfl(static_cast<int>(fl), src);
-    if (g == 0 && k < a.P) {
-      a.tau[k] = static_cast<uint8_t>(tau[0]);
-      a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
-      a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
     }
   }
 }
@@ -786,7 +804,7 @@ hipError_t launch_window_geo(const ViscArgs& v, hipStream_t s) {
 hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
   const ClassifyArgs c = classify_args(v);
   if (c.mode == 2)
-    hipLaunchKernelGGL(k_classify_sdnn, grid_for(v.P), dim3(256), 0, s, c);
+    hipLaunchKernelGGL(k_classify_sdnn, dim3(kClassifyBlocks), dim3(256), 0, s, c);
   else
     hipLaunchKernelGGL(k_classify, grid_for(v.P), dim3(256), 0, s, c);
   hipLaunchKernelGGL(k_dilate, grid_for(v.P), dim3(256), 0, s, v.muhat, v.tmp, v.pid, v.ij, v.patches, v.flags, v.P,
