@@ -614,6 +614,14 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       }
       c->var[ph] = GemmVariant{};
     }
+    if ((ph == PH_FILT1 || ph == PH_FILT2) && p.precision == FCS_PREC_BF16X3) {
+      // the split-BF16 filter in the line-stationary shape (one tile per 64
+      // lines, fewer than the default shape's tiles)
+      GemmVariant v;
+      v.kc = 32;
+      v.line = true;
+      c->var[ph] = v;
+    }
     build_tiles(c.get(), ph);
     c->tile_cap[ph] = std::max(cap, c->phase_tiles[ph].size());
   }

@@ -1060,6 +1060,222 @@ __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, 
     gemm_bf16x3_dir<TB, NS, KC, PF, false>(T, tile, ops, sm);
 }
 
+// Line-stationary split BF16 (lines of at most kLineMax points): one
+// workgroup stages the hi and lo parts of its 64 lines over their whole
+// length into LDS once, and then forms every output of those lines: wave w
+// takes the 16-output blocks w, w + 4, ... and, for each, runs the chunks of
+// 32 columns with the operator rows read from L2 straight into MFMA
+// operands (the next chunk's rows are loaded during the current chunk's
+// products).  Operand lines are read from memory once per line tile instead
+// of once per output tile, and the chunk loop needs no barrier.  Tasks with
+// longer lines run the staged shape above, output tile by output tile.
+constexpr int kLineMax = 304;
+struct SmemLine {
+  static constexpr int PITCH = kLineMax + 8;  // halves; 624-byte rows
+  alignas(16) uint16_t Xh[kLB][PITCH];
+  alignas(16) uint16_t Xl[kLB][PITCH];
+  double x0s[kLB];
+  int64_t dst[kLB];
+};
+
+template <bool Q1>
+__device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
+                                                     SmemLine& sm) {
+  const int n = T.n, nlines = T.nrow * T.ncomp;
+  const int nl = min(kLB, nlines - tile.line0);
+  const int ld = ops.ld[T.op];
+  const int nk = (n + 31) / 32;
+  const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  constexpr bool q1 = Q1;
+  if (tid < kLB) {
+    sm.dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
+    sm.x0s[tid] = gsrc(T.src)[sm.dst[tid]];
+  }
+  // Staging, as in the staged shape: along q^1 sixteen lanes per line (a
+  // column pair each), along q^2 one line per lane (8 consecutive columns).
+  // Only the 8-column groups that meet the line are stored (columns past its
+  // end repeat its last value); a product's group past the line end reads
+  // group 0 instead, whose values meet zero operator columns there.
+  const int n8 = (n + 7) & ~7;
+  auto split2 = [&](double v, double x0, __bf16& h, __bf16& l) __attribute__((always_inline)) {
+    const float f = static_cast<float>(v - x0);
+    const __bf16 hh = static_cast<__bf16>(f);
+    h = hh;
+    l = static_cast<__bf16>(f - static_cast<float>(hh));
+  };
+  // loads of kCG chunks are issued together (many loads in flight per
+  // thread), then split and stored
+  constexpr int kCG = 4;
+  if constexpr (q1) {
+    typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+    const int pc = 2 * (tid & 15), qs = tid >> 4;
+    const gdouble* xb[4];
+    double x0[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      xb[i] = gsrc(T.src) + line_base(T, min(tile.line0 + qs + 16 * i, nlines - 1));
+      x0[i] = xb[i][0];
+    }
+#pragma unroll 1
+    for (int c0 = 0; c0 < nk; c0 += kCG) {
+      double v[kCG][4][2];
+#pragma unroll
+      for (int cc = 0; cc < kCG; ++cc)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int h = 0; h < 2; ++h) v[cc][i][h] = xb[i][min(32 * (c0 + cc) + pc + h, n - 1)];
+#pragma unroll
+      for (int cc = 0; cc < kCG; ++cc) {
+        const int col = 32 * (c0 + cc) + pc;
+        if (col >= n8) continue;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          __bf16 h0, l0, h1, l1;
+          split2(v[cc][i][0], x0[i], h0, l0);
+          split2(v[cc][i][1], x0[i], h1, l1);
+          bf16x2 h, l;
+          h[0] = h0;
+          h[1] = h1;
+          l[0] = l0;
+          l[1] = l1;
+          *reinterpret_cast<bf16x2*>(&sm.Xh[qs + 16 * i][col]) = h;
+          *reinterpret_cast<bf16x2*>(&sm.Xl[qs + 16 * i][col]) = l;
+        }
+      }
+    }
+  } else {
+    const int line = tid & 63, col0 = 8 * (tid >> 6);
+    const gdouble* __restrict__ xb = gsrc(T.src) + line_base(T, min(tile.line0 + line, nlines - 1));
+    const double x0 = xb[0];
+#pragma unroll 1
+    for (int c0 = 0; c0 < nk; c0 += kCG) {
+      double v[kCG][8];
+#pragma unroll
+      for (int cc = 0; cc < kCG; ++cc)
+#pragma unroll
+        for (int j = 0; j < 8; ++j)
+          v[cc][j] = xb[static_cast<int64_t>(min(32 * (c0 + cc) + col0 + j, n - 1)) * T.s_stride];
+#pragma unroll
+      for (int cc = 0; cc < kCG; ++cc) {
+        const int col = 32 * (c0 + cc) + col0;
+        if (col >= n8) continue;
+        bf16x8 h, l;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          __bf16 hj, lj;
+          split2(v[cc][j], x0, hj, lj);
+          h[j] = hj;
+          l[j] = lj;
+        }
+        *reinterpret_cast<bf16x8*>(&sm.Xh[line][col]) = h;
+        *reinterpret_cast<bf16x8*>(&sm.Xl[line][col]) = l;
+      }
+    }
+  }
+  __syncthreads();
+  const int rr = lane & 15, kb = 8 * (lane >> 4);
+  const double* rowsum = ops.rowsum + ops.roff[T.op];
+  const int nob = (n + 15) / 16;
+  // line blocks with work (16 lines each; the skip bits mark blocks of lines
+  // on inactive grid lines)
+  int lbmask = 0;
+#pragma unroll
+  for (int lb = 0; lb < 4; ++lb)
+    if (16 * lb < nl && !((tile.skip >> lb) & 1)) lbmask |= 1 << lb;
+  auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) __attribute__((always_inline)) {
+    return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
+              : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
+  };
+#pragma unroll 1
+  for (int ob = wave; ob < nob; ob += 4) {
+    // operator row of this lane (zero-padded tables: rows past n are zero)
+    const int64_t rbase = ops.off[T.op] + static_cast<int64_t>(16 * ob + rr) * ld + kb;
+    const uint16_t* __restrict__ Bh = ops.bhi + rbase;
+    const uint16_t* __restrict__ Bl = ops.blo + rbase;
+    f32x4 bm[4], bc[4];
+#pragma unroll
+    for (int lb = 0; lb < 4; ++lb) bm[lb] = bc[lb] = f32x4{0, 0, 0, 0};
+    // operator rows of the next kPD chunks in flight (a register queue
+    // shifted by one each chunk)
+    constexpr int kPD = 1;
+    uint4 dh[kPD], dl[kPD];
+#pragma unroll
+    for (int q = 0; q < kPD; ++q)
+      if (q < nk) {
+        dh[q] = *reinterpret_cast<const uint4*>(Bh + 32 * q);
+        dl[q] = *reinterpret_cast<const uint4*>(Bl + 32 * q);
+      }
+#pragma unroll 1
+    for (int c = 0; c < nk; ++c) {
+      const bf16x8 bh = __builtin_bit_cast(bf16x8, dh[0]), bl = __builtin_bit_cast(bf16x8, dl[0]);
+#pragma unroll
+      for (int q = 0; q + 1 < kPD; ++q) {
+        dh[q] = dh[q + 1];
+        dl[q] = dl[q + 1];
+      }
+      if (c + kPD < nk) {
+        dh[kPD - 1] = *reinterpret_cast<const uint4*>(Bh + 32 * (c + kPD));
+        dl[kPD - 1] = *reinterpret_cast<const uint4*>(Bl + 32 * (c + kPD));
+      }
+      const int kx = 32 * c + kb < n ? 32 * c + kb : 0;
+#pragma unroll
+      for (int lb = 0; lb < 4; ++lb) {
+        if (!((lbmask >> lb) & 1)) continue;
+        const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xh[16 * lb + rr][kx]));
+        const bf16x8 xl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xl[16 * lb + rr][kx]));
+        bm[lb] = mm(xh, bh, bm[lb]);
+        bc[lb] = mm(xh, bl, bc[lb]);
+        bc[lb] = mm(xl, bh, bc[lb]);
+      }
+    }
+#pragma unroll
+    for (int lb = 0; lb < 4; ++lb) {
+      if (!((lbmask >> lb) & 1)) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * (lane >> 4) + r, col = lane & 15;
+        const int lloc = 16 * lb + (q1 ? row : col);
+        const int t = 16 * ob + (q1 ? col : row);
+        if (t >= n || lloc >= nl) continue;
+        const double v = static_cast<double>(bm[lb][r]) + static_cast<double>(bc[lb][r]) + sm.x0s[lloc] * rowsum[t];
+        const int64_t o = sm.dst[lloc] + static_cast<int64_t>(t) * T.s_stride;
+        if (T.out_f32)
+          gdst32(T.dst)[o] = static_cast<float>(v);
+        else
+          gdst64(T.dst)[o] = v;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gemm_bf16x3_line(const GemmTask* __restrict__ tasks,
+                                                          const GemmTile* __restrict__ tiles, OpTables ops) {
+  constexpr size_t kBytes = sizeof(SmemLine) > sizeof(SmemBf<1, 2, 32>) ? sizeof(SmemLine) : sizeof(SmemBf<1, 2, 32>);
+  __shared__ __attribute__((aligned(16))) char smem[kBytes];
+  const GemmTile tile = tiles[blockIdx.x];
+  if (tile_idle(tile)) return;
+  const GemmTask T = tasks[tile.task];
+  if (T.n <= kLineMax) {
+    SmemLine& sm = *reinterpret_cast<SmemLine*>(smem);
+    if (T.s_stride == 1)
+      gemm_bf16x3_line_dir<true>(T, tile, ops, sm);
+    else
+      gemm_bf16x3_line_dir<false>(T, tile, ops, sm);
+    return;
+  }
+  SmemBf<1, 2, 32>& sm = *reinterpret_cast<SmemBf<1, 2, 32>*>(smem);
+  for (int t0 = 0; t0 < T.n; t0 += 64) {
+    GemmTile t = tile;
+    t.t0 = t0;
+    if (T.s_stride == 1)
+      gemm_bf16x3_dir<1, 2, 32, 1, true>(T, t, ops, sm);
+    else
+      gemm_bf16x3_dir<1, 2, 32, 1, false>(T, t, ops, sm);
+    __syncthreads();  // the next output tile restages the LDS buffers
+  }
+}
+
 // Split BF16 x6: three parts per value, six products (about FP32 accuracy
 // from BF16 matrix cores); one output block of 64 per tile (LDS).
 __global__ __launch_bounds__(256) void k_gemm_bf16x6(const GemmTask* __restrict__ tasks,
@@ -1279,6 +1495,8 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
   }
   if (precision == 3) {
     hipLaunchKernelGGL(k_gemm_bf16x6, grid, block, 0, stream, tasks, tiles, ops);
+  } else if (v.line) {
+    hipLaunchKernelGGL(k_gemm_bf16x3_line, grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.kc == 64) {
     hipLaunchKernelGGL((k_gemm_bf16x3<1, 64, 1>), grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.tb == 2) {
@@ -1297,7 +1515,10 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
 }
 
 int gemm_lines_per_tile() { return kLB; }
-int gemm_outputs_per_tile(const GemmVariant& v) { return 64 * (v.tb == 4 ? 4 : (v.tb == 2 ? 2 : 1)); }
+int gemm_outputs_per_tile(const GemmVariant& v) {
+  // the line-stationary shape covers every output of its lines in one tile
+  return v.line ? (1 << 24) : 64 * (v.tb == 4 ? 4 : (v.tb == 2 ? 2 : 1));
+}
 
 const GemmVariant* gemm_variants(int precision, int* count) {
   // {tb, kc, persist, xs, xw, pf, minb}
@@ -1318,9 +1539,9 @@ const GemmVariant* gemm_variants(int precision, int* count) {
                                    {1, 32, true, false, false},  {2, 32, true, false, false},
                                    {2, 32, false, false, true},  {4, 32, false, false, true},
                                    {1, 32, false, false, false, 2}, {1, 64, false, false, false},
-                                   {2, 32, false, false, false, 2}};
+                                   {2, 32, false, false, false, 2}, {1, 32, false, false, false, 1, 4, true}};
   static const GemmVariant bf6[] = {{1, 32, false, false, false}};
-  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 9 : 1));
+  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 10 : 1));
   return precision == 0 ? f64 : (precision == 1 ? f32 : (precision == 2 ? bf : bf6));
 }
 
