@@ -530,7 +530,12 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       add_line_tasks(c.get(), PH_EULER, g, 0, FCS_OP_D2, A_IN, 0, A_W11, 0, 4, rs);
       add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D1, A_IN, 0, A_W2, 0, 4, cs);
       add_line_tasks(c.get(), PH_EULER, g, 1, FCS_OP_D2, A_IN, 0, A_W22, 0, 4, cs);
-      if (c->cross) add_line_tasks(c.get(), PH_CROSS, g, 1, FCS_OP_D1, A_W1, 0, A_W12, 0, 4);
+      // the mixed derivative of w enters only through g^12: subpatches where
+      // g^12 vanishes at every active point need none (their W12 entries
+      // keep the workspace's zeros, multiplied by g^12 = 0)
+      bool has12 = false;
+      for (size_t k = 0; k < g.np() && !has12; ++k) has12 = g.mask[k] && g.g12[k] != 0.0;
+      if (c->cross && has12) add_line_tasks(c.get(), PH_CROSS, g, 1, FCS_OP_D1, A_W1, 0, A_W12, 0, 4);
       add_line_tasks(c.get(), PH_MUGRAD, g, 0, FCS_OP_D1, A_MU, 0, A_MU1, 0, 1);
       add_line_tasks(c.get(), PH_MUGRAD, g, 1, FCS_OP_D1, A_MU, 0, A_MU2, 0, 1);
     }
