@@ -64,7 +64,7 @@ def parse():
                          "instead of tuning it (for counter runs, whose dispatch serialization skews the tuner)")
     ap.add_argument("--tiled", action="store_true",
                     help="also run the tiled step channel at 1.17e7 points (FP64 and split-BF16)")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--classifier-lines", type=int, default=100_000,
                     help="synthetic lines for training the classifier (10 %% held out)")
     return ap.parse_args()
@@ -258,6 +258,29 @@ def contraction_profile(S, torch, nsteps=20, reps=50):
     return alone, graph
 
 
+def measured_traffic(kernel, points):
+    """HBM bytes of one stage-contraction launch from the counter summary in
+    profiles/ (FETCH_SIZE and WRITE_SIZE scaled by a plain copy's reading),
+    if it was taken on this kernel, this workload and the current kernel
+    source; None otherwise."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "wedge_stage_contraction_traffic.json")
+    try:
+        with open(path) as f:
+            m = json.load(f)
+        with open(os.path.join(ROOT, m["source"]), "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except (OSError, ValueError, KeyError):
+        return None
+    if m.get("kernel") != kernel or m.get("points") != points or m.get("source_sha256") != sha:
+        return None
+    return {"bytes_per_launch": m["hbm_bytes_per_launch"], "read_bytes": m["hbm_read_bytes_per_launch"],
+            "write_bytes": m["hbm_write_bytes_per_launch"],
+            "vs_algorithmic": m["hbm_bytes_per_launch"] / m["algorithmic_bytes_per_launch"],
+            "from": "profiles/wedge_stage_contraction_traffic.md (rocprofv3 FETCH_SIZE x %.3f, WRITE_SIZE x %.3f)"
+                    % (m["calibration"]["fetch_factor"], m["calibration"]["write_factor"])}
+
+
 def roofline_of(prof, precision, kernel):
     """Roofline entries of a stage contraction timed alone: achieved
     algorithmic HBM bytes per second against HBM, and dense MFMA flops
@@ -444,6 +467,7 @@ def main():
         "roofline": {"bound": "hbm", "kernel": rf["kernel"] + " (grouped FC stage contraction, autotuned tile)",
                      "achieved": rf["hbm"]["achieved_GBps"], "peak": rf["hbm"]["peak_GBps"], "unit": "GB/s",
                      "frac": rf["hbm"]["frac"], "traffic": None,
+                     "traffic_detail": None,
                      "achieved_from": "algorithmic bytes of one launch (FP64 operand lines read once, derivatives "
                                       "written once, the lines that step needs) / average launch time",
                      "avg_launch_ms": rf["avg_launch_ms"], "mfma": rf["mfma"],
@@ -451,6 +475,10 @@ def main():
         "wedge": wedge,
         "classifier_training": train_info,
     }
+    tr = measured_traffic(rf["kernel"], wedge["points"])
+    if tr is not None:
+        out["roofline"]["traffic"] = tr["bytes_per_launch"]
+        out["roofline"]["traffic_detail"] = tr
     if not a.no_extras:
         out["step_channel"] = channel_run(F, W, torch, weights, min(a.steps, 2000), a.warmup)
         log("step channel done")
@@ -464,8 +492,14 @@ def main():
         out["cpu_baseline"] = cpu_baseline(W, weights, a.cpu_steps)
         log("cpu baseline done")
     if a.calibration_copy:
+        # a 256 MiB source written first, then 512 MiB of other writes (so
+        # that the source is read from HBM, not from the caches), then three
+        # plain copies
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        other = torch.zeros(64 * 1024 * 1024, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        del other
         for _ in range(3):
             dst.copy_(src)
         torch.cuda.synchronize()
