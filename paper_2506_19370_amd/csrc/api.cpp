@@ -95,10 +95,12 @@ struct fcs_ctx {
   std::vector<int32_t> ij;  // (j << 16) | i of every point
   std::vector<PatchDev> pdev;
   std::vector<int2> rowrun, colrun;
-  std::vector<int64_t> copy_pairs, idst, icol, bdst, bcol;
+  std::vector<int64_t> copy_pairs, idst, icol;
   std::vector<int32_t> csrc;  // per point: copy donor of a lattice fringe point, else the point itself
-  std::vector<int32_t> iptr, bptr;
-  std::vector<double> ival, bval;
+  std::vector<int32_t> iptr;
+  std::vector<double> ival;
+  std::vector<BlendRowDev> brow;    // viscosity blend rows (factored)
+  std::vector<BlendTermDev> bterm;
   std::vector<BcEntry> bc;
   std::vector<WallLine> walls;  // lines ending at no-slip adiabatic walls
   std::vector<int32_t> bcidx;  // entry of each boundary point
@@ -473,17 +475,29 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
       c->iptr.push_back(static_cast<int32_t>(c->icol.size()));
     }
   }
-  c->bptr.push_back(0);
   if (c->visc && npatch > 1) {
-    std::vector<InterpRow> brows;
-    build_blend_rows(c->grids, p.n_v, brows);
-    for (const InterpRow& r : brows) {
-      c->bdst.push_back(r.dst);
-      for (const auto& e : r.ent) {
-        c->bcol.push_back(e.first);
-        c->bval.push_back(e.second);
+    std::vector<BlendRow> brows;
+    build_blend_terms(c->grids, p.n_v, brows);
+    for (const BlendRow& r : brows) {
+      BlendRowDev d{};
+      d.dst = r.dst;
+      d.wself = r.wself;
+      d.t0 = static_cast<int32_t>(c->bterm.size());
+      for (const BlendTerm& t : r.terms) {
+        BlendTermDev e{};
+        e.base = t.base;
+        e.stride = t.stride;
+        e.ni = t.ni;
+        e.nj = t.nj;
+        e.scale = t.scale;
+        for (int a = 0; a < 6; ++a) {
+          e.wi[a] = t.wi[a];
+          e.wj[a] = t.wj[a];
+        }
+        c->bterm.push_back(e);
       }
-      c->bptr.push_back(static_cast<int32_t>(c->bcol.size()));
+      d.t1 = static_cast<int32_t>(c->bterm.size());
+      c->brow.push_back(d);
     }
   }
   // viscosity tables: dilation weights, modal basis
@@ -550,7 +564,8 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   }
   // activity flags of the row and the column of each blend row's point
   if (c->nact)
-    for (int64_t k : c->bdst) {
+    for (const BlendRowDev& br : c->brow) {
+      const int64_t k = br.dst;
       const PatchDev& pd = c->pdev[c->pid[k]];
       const int32_t j = c->ij[k] >> 16, i = c->ij[k] & 0xFFFF;
       c->bact.push_back(pd.act_row >= 0 ? make_int2(pd.act_row + j, pd.act_col + i) : make_int2(-1, -1));
@@ -675,10 +690,8 @@ extern "C" fcs_status fcs_create(const fcs_params* prm, int32_t npatch, const fc
   o["IPTR"] = cv.take(c->iptr.size() * 4);
   o["ICOL"] = cv.take(c->icol.size() * 8);
   o["IVAL"] = cv.take(c->ival.size() * D);
-  o["BDST"] = cv.take(c->bdst.size() * 8);
-  o["BPTR"] = cv.take(c->bptr.size() * 4);
-  o["BCOL"] = cv.take(c->bcol.size() * 8);
-  o["BVAL"] = cv.take(c->bval.size() * D);
+  o["BROW"] = cv.take(c->brow.size() * sizeof(BlendRowDev));
+  o["BTERM"] = cv.take(c->bterm.size() * sizeof(BlendTermDev));
   o["BC"] = cv.take(c->bc.size() * sizeof(BcEntry));
   o["WALL"] = cv.take(c->walls.size() * sizeof(WallLine));
   o["WTH"] = cv.take(c->walls.size() * 2 * D);
@@ -826,10 +839,8 @@ extern "C" fcs_status fcs_bind(fcs_ctx* c, void* workspace, size_t bytes, void* 
       {"IPTR", c->iptr.data(), c->iptr.size() * 4},
       {"ICOL", c->icol.data(), c->icol.size() * 8},
       {"IVAL", c->ival.data(), c->ival.size() * 8},
-      {"BDST", c->bdst.data(), c->bdst.size() * 8},
-      {"BPTR", c->bptr.data(), c->bptr.size() * 4},
-      {"BCOL", c->bcol.data(), c->bcol.size() * 8},
-      {"BVAL", c->bval.data(), c->bval.size() * 8},
+      {"BROW", c->brow.data(), c->brow.size() * sizeof(BlendRowDev)},
+      {"BTERM", c->bterm.data(), c->bterm.size() * sizeof(BlendTermDev)},
       {"BC", c->bc.data(), c->bc.size() * sizeof(BcEntry)},
       {"WALL", c->walls.data(), c->walls.size() * sizeof(WallLine)},
       {"BCIDX", c->bcidx.data(), c->bcidx.size() * 4},
@@ -942,11 +953,9 @@ ViscArgs visc_args(fcs_ctx* c) {
   v.gamma = p.gamma;
   v.nv = p.n_v;
   v.wdil = c->dptr<double>("WDIL");
-  v.nblend = static_cast<int>(c->bdst.size());
-  v.bdst = c->dptr<int64_t>("BDST");
-  v.bptr = c->dptr<int32_t>("BPTR");
-  v.bcol = c->dptr<int64_t>("BCOL");
-  v.bval = c->dptr<double>("BVAL");
+  v.nblend = static_cast<int>(c->brow.size());
+  v.brow = c->dptr<BlendRowDev>("BROW");
+  v.bterm = c->dptr<BlendTermDev>("BTERM");
   v.act = c->nact ? c->dptr<uint8_t>("LACT") : nullptr;
   v.bact = c->nact ? c->dptr<int2>("BACT") : nullptr;
   v.wgeo = c->dptr<int4>("WGEO");

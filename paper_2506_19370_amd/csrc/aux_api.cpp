@@ -264,7 +264,7 @@ extern "C" fcs_status fcs_gemm_variant_name(int32_t precision, int32_t index, ch
   if (precision == 3) {
     name = "k_gemm_bf16x6";
   } else if (precision == 2 && v.line) {
-    name = "k_gemm_bf16x3_line";
+    name = "k_gemm_bf16x3_line<" + std::to_string(v.lines) + ">";
   } else if (precision == 2 && v.xw) {
     name = "k_gemm_xw_bf16x3<128, " + std::to_string(v.tb) + ">";
   } else if (precision == 2) {

@@ -56,6 +56,7 @@ struct GemmVariant {
   int pf = 1;    // staged kernel: chunks whose loads are in flight (1 or 2)
   int minb = 4;  // staged kernel: workgroups per CU of its launch bound
   bool line = false;  // split BF16: line-stationary (all outputs of a line tile)
+  int lines = 64;     // lines per tile (the line-stationary shape: 64 or 32)
 };
 hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* tasks, const GemmTile* tiles,
                        int ntiles, const OpTables& ops, int* counters, hipStream_t stream);

@@ -821,7 +821,7 @@ struct BfChunk {
 // register moves: no slot is indexed at run time).
 template <int TB, int NS, int KC, int PF, bool Q1>
 __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
-                                                SmemBf<TB, NS, KC>& sm) {
+                                                SmemBf<TB, NS, KC>& sm, int maxl = kLB) {
   constexpr int kTT = 64 * TB;
   constexpr int ND = kTT * KC / (256 * 8);  // 16-byte loads per thread and table
   constexpr int NXG = KC / 32;              // groups of 8 columns per thread
@@ -832,7 +832,7 @@ __device__ __forceinline__ void gemm_bf16x3_dir(const GemmTask& T, const GemmTil
   double* x0s = sm.x0s;
   int64_t* dst = sm.dst;
   const int n = T.n, nlines = T.nrow * T.ncomp, t0 = tile.t0, nt = min(kTT, n - t0);
-  const int nl = min(kLB, nlines - tile.line0);
+  const int nl = min(maxl, nlines - tile.line0);
   const int ld = ops.ld[T.op];
   const int64_t dbase = ops.off[T.op] + static_cast<int64_t>(t0) * ld;
   const uint16_t* __restrict__ Bh = ops.bhi + dbase;
@@ -1060,36 +1060,110 @@ __device__ __forceinline__ void gemm_bf16x3(const GemmTask* __restrict__ tasks, 
     gemm_bf16x3_dir<TB, NS, KC, PF, false>(T, tile, ops, sm);
 }
 
-// Line-stationary split BF16 (lines of at most kLineMax points): one
+// Line-stationary split BF16 (lines of at most line_max<LINES>() points): one
 // workgroup stages the hi and lo parts of its 64 lines over their whole
 // length into LDS once, and then forms every output of those lines: wave w
 // takes the 16-output blocks w, w + 4, ... and, for each, runs the chunks of
 // 32 columns with the operator rows read from L2 straight into MFMA
 // operands (the next chunk's rows are loaded during the current chunk's
 // products).  Operand lines are read from memory once per line tile instead
-// of once per output tile, and the chunk loop needs no barrier.  Tasks with
-// longer lines run the staged shape above, output tile by output tile.
-constexpr int kLineMax = 304;
+// of once per output tile, and the chunk loop needs no barrier.  Lines
+// longer than the LDS rows take the staged shape (64-line tiles) or a
+// register path (32-line tiles: operands read from memory per product).
+// Longest line whose hi and lo parts fit the LDS rows (78 KB for 64 lines:
+// two workgroups per CU; 39 KB for 32 lines: four).
+template <int LINES>
+constexpr int line_max() {
+  return 304;
+}
+template <int LINES>
 struct SmemLine {
-  static constexpr int PITCH = kLineMax + 8;  // halves; 624-byte rows
-  alignas(16) uint16_t Xh[kLB][PITCH];
-  alignas(16) uint16_t Xl[kLB][PITCH];
-  double x0s[kLB];
-  int64_t dst[kLB];
+  static constexpr int PITCH = line_max<LINES>() + 8;  // halves
+  alignas(16) uint16_t Xh[LINES][PITCH];
+  alignas(16) uint16_t Xl[LINES][PITCH];
+  double x0s[LINES];
+  int64_t dst[LINES];
 };
 
-template <bool Q1>
+// LINES lines per tile (64, or 32: half the LDS, more workgroups per CU).
+template <int LINES, bool Q1>
 __device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const GemmTile tile, const OpTables& ops,
-                                                     SmemLine& sm) {
+                                                     SmemLine<LINES>& sm) {
+  constexpr int NLB = LINES / 16;      // 16-line blocks
+  constexpr int GPP = 256 / LINES;     // q^2 staging: 8-column groups per pass
   const int n = T.n, nlines = T.nrow * T.ncomp;
-  const int nl = min(kLB, nlines - tile.line0);
+  const int nl = min(LINES, nlines - tile.line0);
   const int ld = ops.ld[T.op];
   const int nk = (n + 31) / 32;
   const int tid = threadIdx.x, lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr bool q1 = Q1;
-  if (tid < kLB) {
+  if (tid < LINES) {
     sm.dst[tid] = line_base(T, min(tile.line0 + tid, nlines - 1));
     sm.x0s[tid] = gsrc(T.src)[sm.dst[tid]];
+  }
+  auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) __attribute__((always_inline)) {
+    return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
+              : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
+  };
+  const int rr = lane & 15, kb = 8 * (lane >> 4);
+  const double* rowsum = ops.rowsum + ops.roff[T.op];
+  const int nob = (n + 15) / 16;
+  // line blocks with work (16 lines each; the skip bits mark blocks of lines
+  // on inactive grid lines)
+  int lbmask = 0;
+#pragma unroll
+  for (int lb = 0; lb < NLB; ++lb)
+    if (16 * lb < nl && !((tile.skip >> lb) & 1)) lbmask |= 1 << lb;
+  auto store = [&](int ob, int lb, const f32x4& am, const f32x4& ac) __attribute__((always_inline)) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = 4 * (lane >> 4) + r, col = lane & 15;
+      const int lloc = 16 * lb + (q1 ? row : col);
+      const int t = 16 * ob + (q1 ? col : row);
+      if (t >= n || lloc >= nl) continue;
+      const double v = static_cast<double>(am[r]) + static_cast<double>(ac[r]) + sm.x0s[lloc] * rowsum[t];
+      const int64_t o = sm.dst[lloc] + static_cast<int64_t>(t) * T.s_stride;
+      if (T.out_f32)
+        gdst32(T.dst)[o] = static_cast<float>(v);
+      else
+        gdst64(T.dst)[o] = v;
+    }
+  };
+  if (n > line_max<LINES>()) {
+    // Lines longer than the LDS rows: each product reads its 8 operand
+    // values straight from memory and splits them in registers (operand
+    // lines re-read from L2 once per output block; such lines are rare).
+    __syncthreads();
+#pragma unroll 1
+    for (int ob = wave; ob < nob; ob += 4) {
+      const int64_t rbase = ops.off[T.op] + static_cast<int64_t>(16 * ob + rr) * ld + kb;
+#pragma unroll 1
+      for (int lb = 0; lb < NLB; ++lb) {
+        if (!((lbmask >> lb) & 1)) continue;
+        const int ll = 16 * lb + rr;
+        const gdouble* __restrict__ xb = gsrc(T.src) + sm.dst[ll];
+        const double x0 = sm.x0s[ll];
+        f32x4 am = {0, 0, 0, 0}, ac = {0, 0, 0, 0};
+#pragma unroll 1
+        for (int c = 0; c < nk; ++c) {
+          const bf16x8 bh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ops.bhi + rbase + 32 * c));
+          const bf16x8 bl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(ops.blo + rbase + 32 * c));
+          bf16x8 xh, xl;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            const double v = xb[static_cast<int64_t>(min(32 * c + kb + j, n - 1)) * T.s_stride];
+            const float f = static_cast<float>(v - x0);
+            xh[j] = static_cast<__bf16>(f);
+            xl[j] = static_cast<__bf16>(f - static_cast<float>(xh[j]));
+          }
+          am = mm(xh, bh, am);
+          ac = mm(xh, bl, ac);
+          ac = mm(xl, bh, ac);
+        }
+        store(ob, lb, am, ac);
+      }
+    }
+    return;
   }
   // Staging, as in the staged shape: along q^1 sixteen lanes per line (a
   // column pair each), along q^2 one line per lane (8 consecutive columns).
@@ -1103,26 +1177,26 @@ __device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const Ge
     h = hh;
     l = static_cast<__bf16>(f - static_cast<float>(hh));
   };
-  // loads of kCG chunks are issued together (many loads in flight per
-  // thread), then split and stored
+  // loads of kCG chunks (groups) are issued together (many loads in flight
+  // per thread), then split and stored
   constexpr int kCG = 4;
   if constexpr (q1) {
     typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
     const int pc = 2 * (tid & 15), qs = tid >> 4;
-    const gdouble* xb[4];
-    double x0[4];
+    const gdouble* xb[NLB];
+    double x0[NLB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
+    for (int i = 0; i < NLB; ++i) {
       xb[i] = gsrc(T.src) + line_base(T, min(tile.line0 + qs + 16 * i, nlines - 1));
       x0[i] = xb[i][0];
     }
 #pragma unroll 1
     for (int c0 = 0; c0 < nk; c0 += kCG) {
-      double v[kCG][4][2];
+      double v[kCG][NLB][2];
 #pragma unroll
       for (int cc = 0; cc < kCG; ++cc)
 #pragma unroll
-        for (int i = 0; i < 4; ++i)
+        for (int i = 0; i < NLB; ++i)
 #pragma unroll
           for (int h = 0; h < 2; ++h) v[cc][i][h] = xb[i][min(32 * (c0 + cc) + pc + h, n - 1)];
 #pragma unroll
@@ -1130,7 +1204,7 @@ __device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const Ge
         const int col = 32 * (c0 + cc) + pc;
         if (col >= n8) continue;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < NLB; ++i) {
           __bf16 h0, l0, h1, l1;
           split2(v[cc][i][0], x0[i], h0, l0);
           split2(v[cc][i][1], x0[i], h1, l1);
@@ -1145,26 +1219,27 @@ __device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const Ge
       }
     }
   } else {
-    const int line = tid & 63, col0 = 8 * (tid >> 6);
+    const int line = tid % LINES, g0 = tid / LINES;
     const gdouble* __restrict__ xb = gsrc(T.src) + line_base(T, min(tile.line0 + line, nlines - 1));
     const double x0 = xb[0];
+    const int ng = n8 / 8;
 #pragma unroll 1
-    for (int c0 = 0; c0 < nk; c0 += kCG) {
+    for (int m0 = 0; m0 * GPP < ng; m0 += kCG) {
       double v[kCG][8];
 #pragma unroll
-      for (int cc = 0; cc < kCG; ++cc)
+      for (int mm = 0; mm < kCG; ++mm)
 #pragma unroll
         for (int j = 0; j < 8; ++j)
-          v[cc][j] = xb[static_cast<int64_t>(min(32 * (c0 + cc) + col0 + j, n - 1)) * T.s_stride];
+          v[mm][j] = xb[static_cast<int64_t>(min(8 * (g0 + GPP * (m0 + mm)) + j, n - 1)) * T.s_stride];
 #pragma unroll
-      for (int cc = 0; cc < kCG; ++cc) {
-        const int col = 32 * (c0 + cc) + col0;
+      for (int mm = 0; mm < kCG; ++mm) {
+        const int col = 8 * (g0 + GPP * (m0 + mm));
         if (col >= n8) continue;
         bf16x8 h, l;
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
           __bf16 hj, lj;
-          split2(v[cc][j], x0, hj, lj);
+          split2(v[mm][j], x0, hj, lj);
           h[j] = hj;
           l[j] = lj;
         }
@@ -1174,106 +1249,118 @@ __device__ __forceinline__ void gemm_bf16x3_line_dir(const GemmTask& T, const Ge
     }
   }
   __syncthreads();
-  const int rr = lane & 15, kb = 8 * (lane >> 4);
-  const double* rowsum = ops.rowsum + ops.roff[T.op];
-  const int nob = (n + 15) / 16;
-  // line blocks with work (16 lines each; the skip bits mark blocks of lines
-  // on inactive grid lines)
-  int lbmask = 0;
+  // NB output blocks at a time (blocks ob, ob + 4, ...: the operand reads
+  // from LDS serve NB x 3 products)
+  auto blocks = [&](auto nb_c, int ob0) __attribute__((always_inline)) {
+    constexpr int NB = decltype(nb_c)::value;
+    const uint16_t* Bh[NB];
+    const uint16_t* Bl[NB];
 #pragma unroll
-  for (int lb = 0; lb < 4; ++lb)
-    if (16 * lb < nl && !((tile.skip >> lb) & 1)) lbmask |= 1 << lb;
-  auto mm = [&](const bf16x8& x, const bf16x8& d, f32x4 acc) __attribute__((always_inline)) {
-    return q1 ? __builtin_amdgcn_mfma_f32_16x16x32_bf16(x, d, acc, 0, 0, 0)
-              : __builtin_amdgcn_mfma_f32_16x16x32_bf16(d, x, acc, 0, 0, 0);
-  };
-#pragma unroll 1
-  for (int ob = wave; ob < nob; ob += 4) {
-    // operator row of this lane (zero-padded tables: rows past n are zero)
-    const int64_t rbase = ops.off[T.op] + static_cast<int64_t>(16 * ob + rr) * ld + kb;
-    const uint16_t* __restrict__ Bh = ops.bhi + rbase;
-    const uint16_t* __restrict__ Bl = ops.blo + rbase;
-    f32x4 bm[4], bc[4];
+    for (int i = 0; i < NB; ++i) {
+      // operator row of this lane (zero-padded tables: rows past n are zero)
+      const int64_t rbase = ops.off[T.op] + static_cast<int64_t>(16 * (ob0 + 4 * i) + rr) * ld + kb;
+      Bh[i] = ops.bhi + rbase;
+      Bl[i] = ops.blo + rbase;
+    }
+    f32x4 bm[NB][NLB], bc[NB][NLB];
 #pragma unroll
-    for (int lb = 0; lb < 4; ++lb) bm[lb] = bc[lb] = f32x4{0, 0, 0, 0};
+    for (int i = 0; i < NB; ++i)
+#pragma unroll
+      for (int lb = 0; lb < NLB; ++lb) bm[i][lb] = bc[i][lb] = f32x4{0, 0, 0, 0};
     // operator rows of the next kPD chunks in flight (a register queue
-    // shifted by one each chunk)
-    constexpr int kPD = 1;
-    uint4 dh[kPD], dl[kPD];
+    // shifted by one each chunk); every line block is multiplied (the
+    // staged lines are valid data; skipped blocks are only not stored),
+    // which keeps the chunk loop free of branches
+    constexpr int kPD = 2;
+    uint4 dh[kPD][NB], dl[kPD][NB];
 #pragma unroll
     for (int q = 0; q < kPD; ++q)
-      if (q < nk) {
-        dh[q] = *reinterpret_cast<const uint4*>(Bh + 32 * q);
-        dl[q] = *reinterpret_cast<const uint4*>(Bl + 32 * q);
-      }
+      if (q < nk)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          dh[q][i] = *reinterpret_cast<const uint4*>(Bh[i] + 32 * q);
+          dl[q][i] = *reinterpret_cast<const uint4*>(Bl[i] + 32 * q);
+        }
 #pragma unroll 1
     for (int c = 0; c < nk; ++c) {
-      const bf16x8 bh = __builtin_bit_cast(bf16x8, dh[0]), bl = __builtin_bit_cast(bf16x8, dl[0]);
+      bf16x8 bh[NB], bl[NB];
 #pragma unroll
-      for (int q = 0; q + 1 < kPD; ++q) {
-        dh[q] = dh[q + 1];
-        dl[q] = dl[q + 1];
+      for (int i = 0; i < NB; ++i) {
+        bh[i] = __builtin_bit_cast(bf16x8, dh[0][i]);
+        bl[i] = __builtin_bit_cast(bf16x8, dl[0][i]);
       }
-      if (c + kPD < nk) {
-        dh[kPD - 1] = *reinterpret_cast<const uint4*>(Bh + 32 * (c + kPD));
-        dl[kPD - 1] = *reinterpret_cast<const uint4*>(Bl + 32 * (c + kPD));
-      }
+#pragma unroll
+      for (int q = 0; q + 1 < kPD; ++q)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          dh[q][i] = dh[q + 1][i];
+          dl[q][i] = dl[q + 1][i];
+        }
+      if (c + kPD < nk)
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          dh[kPD - 1][i] = *reinterpret_cast<const uint4*>(Bh[i] + 32 * (c + kPD));
+          dl[kPD - 1][i] = *reinterpret_cast<const uint4*>(Bl[i] + 32 * (c + kPD));
+        }
       const int kx = 32 * c + kb < n ? 32 * c + kb : 0;
 #pragma unroll
-      for (int lb = 0; lb < 4; ++lb) {
-        if (!((lbmask >> lb) & 1)) continue;
+      for (int lb = 0; lb < NLB; ++lb) {
         const bf16x8 xh = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xh[16 * lb + rr][kx]));
         const bf16x8 xl = __builtin_bit_cast(bf16x8, *reinterpret_cast<const uint4*>(&sm.Xl[16 * lb + rr][kx]));
-        bm[lb] = mm(xh, bh, bm[lb]);
-        bc[lb] = mm(xh, bl, bc[lb]);
-        bc[lb] = mm(xl, bh, bc[lb]);
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          bm[i][lb] = mm(xh, bh[i], bm[i][lb]);
+          bc[i][lb] = mm(xh, bl[i], bc[i][lb]);
+          bc[i][lb] = mm(xl, bh[i], bc[i][lb]);
+        }
       }
     }
 #pragma unroll
-    for (int lb = 0; lb < 4; ++lb) {
-      if (!((lbmask >> lb) & 1)) continue;
+    for (int i = 0; i < NB; ++i)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = 4 * (lane >> 4) + r, col = lane & 15;
-        const int lloc = 16 * lb + (q1 ? row : col);
-        const int t = 16 * ob + (q1 ? col : row);
-        if (t >= n || lloc >= nl) continue;
-        const double v = static_cast<double>(bm[lb][r]) + static_cast<double>(bc[lb][r]) + sm.x0s[lloc] * rowsum[t];
-        const int64_t o = sm.dst[lloc] + static_cast<int64_t>(t) * T.s_stride;
-        if (T.out_f32)
-          gdst32(T.dst)[o] = static_cast<float>(v);
-        else
-          gdst64(T.dst)[o] = v;
-      }
-    }
-  }
+      for (int lb = 0; lb < NLB; ++lb)
+        if ((lbmask >> lb) & 1) store(ob0 + 4 * i, lb, bm[i][lb], bc[i][lb]);
+  };
+  int ob = wave;
+#pragma unroll 1
+  for (; ob + 4 < nob; ob += 8) blocks(std::integral_constant<int, 2>{}, ob);
+  if (ob < nob) blocks(std::integral_constant<int, 1>{}, ob);
 }
 
+template <int LINES>
 __global__ __launch_bounds__(256) void k_gemm_bf16x3_line(const GemmTask* __restrict__ tasks,
                                                           const GemmTile* __restrict__ tiles, OpTables ops) {
-  constexpr size_t kBytes = sizeof(SmemLine) > sizeof(SmemBf<1, 2, 32>) ? sizeof(SmemLine) : sizeof(SmemBf<1, 2, 32>);
+  constexpr size_t kBytes = LINES == 64 && sizeof(SmemBf<1, 2, 32>) > sizeof(SmemLine<LINES>)
+                                ? sizeof(SmemBf<1, 2, 32>)
+                                : sizeof(SmemLine<LINES>);
   __shared__ __attribute__((aligned(16))) char smem[kBytes];
   const GemmTile tile = tiles[blockIdx.x];
-  if (tile_idle(tile)) return;
+  constexpr int kAll = (1 << (LINES / 16)) - 1;  // skip bits of this tile's line blocks
+  if (tile.task < 0 || (tile.skip & kAll) == kAll) return;
   const GemmTask T = tasks[tile.task];
-  if (T.n <= kLineMax) {
-    SmemLine& sm = *reinterpret_cast<SmemLine*>(smem);
-    if (T.s_stride == 1)
-      gemm_bf16x3_line_dir<true>(T, tile, ops, sm);
-    else
-      gemm_bf16x3_line_dir<false>(T, tile, ops, sm);
-    return;
+  if constexpr (LINES == 64) {
+    // with two workgroups per CU (set by the LDS) the staged shape's
+    // registers cost no occupancy: longer lines run it, output tile by
+    // output tile (faster than the register path on lines of 300-330)
+    if (T.n > line_max<LINES>()) {
+      SmemBf<1, 2, 32>& sb = *reinterpret_cast<SmemBf<1, 2, 32>*>(smem);
+      for (int t0 = 0; t0 < T.n; t0 += 64) {
+        GemmTile t = tile;
+        t.t0 = t0;
+        if (T.s_stride == 1)
+          gemm_bf16x3_dir<1, 2, 32, 1, true>(T, t, ops, sb);
+        else
+          gemm_bf16x3_dir<1, 2, 32, 1, false>(T, t, ops, sb);
+        __syncthreads();  // the next output tile restages the LDS buffers
+      }
+      return;
+    }
   }
-  SmemBf<1, 2, 32>& sm = *reinterpret_cast<SmemBf<1, 2, 32>*>(smem);
-  for (int t0 = 0; t0 < T.n; t0 += 64) {
-    GemmTile t = tile;
-    t.t0 = t0;
-    if (T.s_stride == 1)
-      gemm_bf16x3_dir<1, 2, 32, 1, true>(T, t, ops, sm);
-    else
-      gemm_bf16x3_dir<1, 2, 32, 1, false>(T, t, ops, sm);
-    __syncthreads();  // the next output tile restages the LDS buffers
-  }
+  SmemLine<LINES>& sm = *reinterpret_cast<SmemLine<LINES>*>(smem);
+  if (T.s_stride == 1)
+    gemm_bf16x3_line_dir<LINES, true>(T, tile, ops, sm);
+  else
+    gemm_bf16x3_line_dir<LINES, false>(T, tile, ops, sm);
 }
 
 // Split BF16 x6: three parts per value, six products (about FP32 accuracy
@@ -1496,7 +1583,10 @@ hipError_t launch_gemm(int precision, const GemmVariant& v, const GemmTask* task
   if (precision == 3) {
     hipLaunchKernelGGL(k_gemm_bf16x6, grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.line) {
-    hipLaunchKernelGGL(k_gemm_bf16x3_line, grid, block, 0, stream, tasks, tiles, ops);
+    if (v.lines == 32)
+      hipLaunchKernelGGL(k_gemm_bf16x3_line<32>, grid, block, 0, stream, tasks, tiles, ops);
+    else
+      hipLaunchKernelGGL(k_gemm_bf16x3_line<64>, grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.kc == 64) {
     hipLaunchKernelGGL((k_gemm_bf16x3<1, 64, 1>), grid, block, 0, stream, tasks, tiles, ops);
   } else if (v.tb == 2) {
@@ -1539,9 +1629,10 @@ const GemmVariant* gemm_variants(int precision, int* count) {
                                    {1, 32, true, false, false},  {2, 32, true, false, false},
                                    {2, 32, false, false, true},  {4, 32, false, false, true},
                                    {1, 32, false, false, false, 2}, {1, 64, false, false, false},
-                                   {2, 32, false, false, false, 2}, {1, 32, false, false, false, 1, 4, true}};
+                                   {2, 32, false, false, false, 2}, {1, 32, false, false, false, 1, 4, true},
+                                   {1, 32, false, false, false, 1, 4, true, 32}};
   static const GemmVariant bf6[] = {{1, 32, false, false, false}};
-  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 10 : 1));
+  *count = precision == 0 ? 11 : (precision == 1 ? 13 : (precision == 2 ? 11 : 1));
   return precision == 0 ? f64 : (precision == 1 ? f32 : (precision == 2 ? bf : bf6));
 }
 
@@ -1549,6 +1640,7 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
                       std::vector<GemmTile>& tiles, const uint8_t* late) {
   tiles.clear();
   const int step = gemm_outputs_per_tile(v);
+  const int lpt = v.lines;  // lines per tile
   // Workgroups are dispatched round-robin over the 8 XCDs, each with its own
   // L2.  Every task (one operator) is given to one XCD, balancing the work,
   // and the per-XCD queues are interleaved so that tile i runs on XCD i mod 8:
@@ -1575,11 +1667,11 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
   // the queues will be sorted, in task order otherwise); each queue keeps
   // its tasks in task order
   constexpr size_t kSortedQueue = 2 * 8 * kCusPerXcd;
-  auto task_load = [&](size_t q) { return static_cast<double>((nlines[q] + kLB - 1) / kLB) * n[q] * n[q]; };
+  auto task_load = [&](size_t q) { return static_cast<double>((nlines[q] + lpt - 1) / lpt) * n[q] * n[q]; };
   auto cls = [&](size_t q) { return late && late[q] ? 1 : 0; };
   size_t total = 0;
   for (size_t q = 0; q < ntasks; ++q)
-    total += static_cast<size_t>((nlines[q] + kLB - 1) / kLB) * ((n[q] + step - 1) / step);
+    total += static_cast<size_t>((nlines[q] + lpt - 1) / lpt) * ((n[q] + step - 1) / step);
   std::vector<size_t> order(ntasks);
   for (size_t q = 0; q < ntasks; ++q) order[q] = q;
   if (total <= kXcd * kSortedQueue)
@@ -1592,10 +1684,10 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
     ld[x] += task_load(q);
   }
   for (size_t q = 0; q < ntasks; ++q) {
-    const int nblk = (nlines[q] + kLB - 1) / kLB;
+    const int nblk = (nlines[q] + lpt - 1) / lpt;
     for (int b = 0; b < nblk; ++b)
       for (int t0 = 0; t0 < n[q]; t0 += step)
-        queue[cls(q)][task_queue[q]].push_back({static_cast<int32_t>(q), b * kLB, t0, 0});
+        queue[cls(q)][task_queue[q]].push_back({static_cast<int32_t>(q), b * lpt, t0, 0});
   }
   auto cost = [&](const GemmTile& t) { return n[t.task] * std::min(step, n[t.task] - t.t0); };
   size_t len = 0;
@@ -1604,7 +1696,9 @@ void gemm_build_tiles(const GemmVariant& v, const int32_t* n, const int32_t* nli
     const size_t qlen = queue[0][x].size() + queue[1][x].size();
     for (auto& part : queue) {
       std::vector<GemmTile>& qx = part[x];
-      if (v.persist || qlen <= kSortedQueue) {
+      // (the line-stationary shape has one tile per line block and shares
+      // nothing but operator rows between a task's tiles: always sorted)
+      if (v.persist || v.line || qlen <= kSortedQueue) {
         std::stable_sort(qx.begin(), qx.end(),
                          [&](const GemmTile& a, const GemmTile& b) { return cost(a) > cost(b); });
         // snake order: every other band of one tile per CU reversed, so that

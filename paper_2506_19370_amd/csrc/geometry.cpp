@@ -242,8 +242,15 @@ int stencil_starts(double xi, int n, int* out) {
 // directions, then by the rank along q^1 (where the centred stencil would
 // reach a masked or fringe node, e.g. beside the obstacle quadrant of a
 // corner subpatch, the interpolation becomes one-sided).  false if none.
+// The stencil in factored form: first nodes (j0, i0), sizes ni x nj and the
+// weights of the two directions (the entry weights are wj[b] * wi[a]).
+struct Stencil {
+  int i0, j0, ni, nj;
+  double wi[kOrder], wj[kOrder];
+};
+
 template <class Pred>
-bool stencil(const Grid& g, double xi, double eta, Pred ok, std::vector<Entry>& out) {
+bool stencil_factored(const Grid& g, double xi, double eta, Pred ok, Stencil& st) {
   int si[5], sj[5];
   const int ni_c = stencil_starts(xi, g.n1, si), nj_c = stencil_starts(eta, g.n2, sj);
   for (int total = 0; total <= ni_c + nj_c - 2; ++total)
@@ -273,12 +280,25 @@ bool stencil(const Grid& g, double xi, double eta, Pred ok, std::vector<Entry>& 
       for (int b = 0; b < nj && good; ++b)
         for (int a = 0; a < ni && good; ++a) good = ok(g.at(jj[b], ii[a]));
       if (!good) continue;
-      out.clear();
-      for (int b = 0; b < nj; ++b)
-        for (int a = 0; a < ni; ++a) out.push_back({jj[b], ii[a], wj[b] * wi[a]});
+      st.i0 = ii[0];
+      st.j0 = jj[0];
+      st.ni = ni;
+      st.nj = nj;
+      for (int a = 0; a < ni; ++a) st.wi[a] = wi[a];
+      for (int b = 0; b < nj; ++b) st.wj[b] = wj[b];
       return true;
     }
   return false;
+}
+
+template <class Pred>
+bool stencil(const Grid& g, double xi, double eta, Pred ok, std::vector<Entry>& out) {
+  Stencil st;
+  if (!stencil_factored(g, xi, eta, ok, st)) return false;
+  out.clear();
+  for (int b = 0; b < st.nj; ++b)
+    for (int a = 0; a < st.ni; ++a) out.push_back({st.j0 + b, st.i0 + a, st.wj[b] * st.wi[a]});
+  return true;
 }
 
 bool bbox_candidate(const Grid& s, double px, double py) {
@@ -586,58 +606,55 @@ static void fringe_rows_of(const std::vector<Grid>& grids, size_t p, std::vector
   }
 }
 
-static void blend_rows_of(const std::vector<Grid>& grids, size_t p, int n_v, std::vector<InterpRow>& rows);
-
-void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<InterpRow>& rows) {
-  rows.clear();
-  std::vector<std::vector<InterpRow>> per(grids.size());
-  for_each_patch(grids.size(), [&](size_t p) { blend_rows_of(grids, p, n_v, per[p]); });
-  for (auto& v : per)
-    for (auto& r : v) rows.push_back(std::move(r));
+static void blend_terms_of(const std::vector<Grid>& grids, size_t p, int n_v, std::vector<BlendRow>& rows) {
+  const Grid& gp = grids[p];
+  const std::vector<size_t> nb = box_neighbours(grids, p);
+  std::vector<std::pair<double, BlendTerm>> lst;
+  for (int j = 0; j < gp.n2; ++j)
+    for (int i = 0; i < gp.n1; ++i) {
+      size_t k = gp.at(j, i);
+      if (!gp.mask[k]) continue;
+      double px = gp.x[k], py = gp.y[k];
+      lst.clear();
+      for (size_t s : nb) {
+        const Grid& gs = grids[s];
+        if (!bbox_candidate(gs, px, py)) continue;
+        double xi, eta;
+        if (!invert(gs, px, py, xi, eta) || !inside(gs, xi, eta)) continue;
+        double w = smooth_step(depth_at(gs, xi, eta) / (2.0 * n_v));
+        if (!(w > 0.0)) continue;
+        Stencil st;
+        if (!stencil_factored(gs, xi, eta, [&](size_t kk) { return gs.mask[kk] != 0; }, st)) continue;
+        BlendTerm t{};
+        t.base = gs.offset + static_cast<int64_t>(gs.at(st.j0, st.i0));
+        t.stride = gs.n1;
+        t.ni = st.ni;
+        t.nj = st.nj;
+        for (int a = 0; a < st.ni; ++a) t.wi[a] = st.wi[a];
+        for (int b = 0; b < st.nj; ++b) t.wj[b] = st.wj[b];
+        lst.push_back({w, t});
+      }
+      if (lst.empty()) continue;
+      double wp = smooth_step(gp.depth[k] / (2.0 * n_v));
+      double total = wp;
+      for (const auto& c : lst) total += c.first;
+      BlendRow row;
+      row.dst = gp.offset + static_cast<int64_t>(k);
+      row.wself = wp > 0 ? wp / total : 0.0;
+      for (auto& c : lst) {
+        c.second.scale = c.first / total;
+        row.terms.push_back(c.second);
+      }
+      rows.push_back(std::move(row));
+    }
 }
 
-static void blend_rows_of(const std::vector<Grid>& grids, size_t p, int n_v, std::vector<InterpRow>& rows) {
-  std::vector<Entry> ent;
-  struct Contrib {
-    int s;
-    double w;
-    std::vector<Entry> e;
-  };
-  std::vector<Contrib> lst;
-  {
-    const Grid& gp = grids[p];
-    const std::vector<size_t> nb = box_neighbours(grids, p);
-    for (int j = 0; j < gp.n2; ++j)
-      for (int i = 0; i < gp.n1; ++i) {
-        size_t k = gp.at(j, i);
-        if (!gp.mask[k]) continue;
-        double px = gp.x[k], py = gp.y[k];
-        lst.clear();
-        for (size_t s : nb) {
-          const Grid& gs = grids[s];
-          if (!bbox_candidate(gs, px, py)) continue;
-          double xi, eta;
-          if (!invert(gs, px, py, xi, eta) || !inside(gs, xi, eta)) continue;
-          double w = smooth_step(depth_at(gs, xi, eta) / (2.0 * n_v));
-          if (!(w > 0.0)) continue;
-          if (!stencil(gs, xi, eta, [&](size_t kk) { return gs.mask[kk] != 0; }, ent)) continue;
-          lst.push_back({static_cast<int>(s), w, ent});
-        }
-        if (lst.empty()) continue;
-        double wp = smooth_step(gp.depth[k] / (2.0 * n_v));
-        double total = wp;
-        for (const Contrib& c : lst) total += c.w;
-        InterpRow row;
-        row.dst = gp.offset + static_cast<int64_t>(k);
-        if (wp > 0) row.ent.push_back({gp.offset + static_cast<int64_t>(k), wp / total});
-        for (const Contrib& c : lst) {
-          const Grid& gs = grids[c.s];
-          for (const Entry& e : c.e)
-            row.ent.push_back({gs.offset + static_cast<int64_t>(gs.at(e.j, e.i)), c.w * e.w / total});
-        }
-        rows.push_back(std::move(row));
-      }
-  }
+void build_blend_terms(const std::vector<Grid>& grids, int n_v, std::vector<BlendRow>& rows) {
+  rows.clear();
+  std::vector<std::vector<BlendRow>> per(grids.size());
+  for_each_patch(grids.size(), [&](size_t p) { blend_terms_of(grids, p, n_v, per[p]); });
+  for (auto& v : per)
+    for (auto& r : v) rows.push_back(std::move(r));
 }
 
 }  // namespace fcs

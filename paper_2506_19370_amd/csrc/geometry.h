@@ -64,8 +64,24 @@ struct InterpRow {
 // when a fringe point has no eligible donor.
 bool build_fringe_rows(const std::vector<Grid>& grids, std::vector<InterpRow>& rows, std::string& err);
 
-// Rows of the multi-patch viscosity blend; points without a row keep their
-// own smoothed value.
-void build_blend_rows(const std::vector<Grid>& grids, int n_v, std::vector<InterpRow>& rows);
+// Rows of the multi-patch viscosity blend (points without a row keep their
+// own smoothed value), each in factored form: the point's own value with weight wself,
+// plus per overlapping subpatch scale * sum_b wj[b] sum_a wi[a] u(j0 + b,
+// i0 + a) over its ni x nj interpolation stencil (ni, nj = 6, or 1 on a
+// grid line), the tensor product of the two directions' Lagrange weights.
+struct BlendTerm {
+  int64_t base;    // global index of node (j0, i0)
+  int32_t stride;  // row length n1 of the donor subpatch
+  int32_t ni, nj;
+  int32_t pad;
+  double scale;
+  double wi[6], wj[6];
+};
+struct BlendRow {
+  int64_t dst;
+  double wself;
+  std::vector<BlendTerm> terms;
+};
+void build_blend_terms(const std::vector<Grid>& grids, int n_v, std::vector<BlendRow>& rows);
 
 }  // namespace fcs

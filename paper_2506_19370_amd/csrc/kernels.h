@@ -79,6 +79,21 @@ struct BcEntry {
   double x, y;
 };
 
+// Viscosity blend rows in factored form (see BlendTerm on the host): row q
+// is wself * u(dst) + sum over its terms [t0, t1) of
+// scale * sum_b wj[b] sum_a wi[a] u(base + b * stride + a).
+struct BlendRowDev {
+  int64_t dst;
+  double wself;
+  int32_t t0, t1;
+};
+struct BlendTermDev {
+  int64_t base;
+  int32_t stride, ni, nj, pad;
+  double scale;
+  double wi[6], wj[6];
+};
+
 // A grid line that ends at one or two no-slip adiabatic wall nodes: the
 // wall values of theta make the FC first derivative along it vanish there
 // (both ends together when both are walls).

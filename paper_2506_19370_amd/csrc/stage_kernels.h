@@ -94,10 +94,8 @@ struct ViscArgs {
   int nv;
   const double* wdil;
   int nblend;
-  const int64_t* bdst;
-  const int32_t* bptr;
-  const int64_t* bcol;
-  const double* bval;
+  const BlendRowDev* brow;
+  const BlendTermDev* bterm;
   // (or null) line activity flags of lattice subpatches, one per row and
   // column: 1 where the final mu is nonzero somewhere on the line; bact:
   // the flags of the row and the column of each blend row's point

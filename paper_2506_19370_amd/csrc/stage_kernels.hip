@@ -546,25 +546,36 @@ __global__ void k_dilate(const double* __restrict__ in, double* __restrict__ out
 
 // bact (or null): activity flags of the row and the column of each blended
 // point (x < 0: not on a lattice subpatch with activity flags).
-// A group of kBlendLanes lanes per row: lane j takes the entries j, j + 8,
-// ... (independent gathers in flight instead of one dependent chain of up
-// to 73), then the group sums by shuffles.
+// A group of kBlendLanes lanes per row: lane j evaluates stencil row b = j of
+// each of the row's terms (six contiguous values, gathers in flight
+// together), then the group sums by shuffles.
 constexpr int kBlendLanes = 8;
-__global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu, const int64_t* __restrict__ dst,
-                             const int32_t* __restrict__ ptr, const int64_t* __restrict__ col,
-                             const double* __restrict__ val, int n, const int2* __restrict__ bact,
-                             uint8_t* __restrict__ act) {
+__global__ void k_blend_rows(const double* __restrict__ mut, double* __restrict__ mu,
+                             const BlendRowDev* __restrict__ rows, const BlendTermDev* __restrict__ terms, int n,
+                             const int2* __restrict__ bact, uint8_t* __restrict__ act) {
   const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int q = static_cast<int>(g / kBlendLanes), j = static_cast<int>(g % kBlendLanes);
   // every lane of a group exists (blockDim is a multiple of the group
   // size), so the shuffles below see whole groups; rows past n add nothing
   double s = 0.0;
-  if (q < n)
-    for (int e = ptr[q] + j; e < ptr[q + 1]; e += kBlendLanes) s += val[e] * mut[col[e]];
+  BlendRowDev r{};
+  if (q < n) {
+    r = rows[q];
+    if (j == 0) s = r.wself * mut[r.dst];
+    for (int t = r.t0; t < r.t1; ++t) {
+      const BlendTermDev& T = terms[t];
+      if (j < T.nj) {
+        const double* u = mut + T.base + static_cast<int64_t>(j) * T.stride;
+        double acc = 0.0;
+        for (int a = 0; a < T.ni; ++a) acc += T.wi[a] * u[a];
+        s += T.scale * T.wj[j] * acc;
+      }
+    }
+  }
 #pragma unroll
   for (int o = kBlendLanes / 2; o > 0; o >>= 1) s += __shfl_xor(s, o, kBlendLanes);
   if (q >= n || j != 0) return;
-  mu[dst[q]] = fmax(s, 0.0);
+  mu[r.dst] = fmax(s, 0.0);
   if (act && s > 0.0) {
     const int2 a = bact[q];
     if (a.x >= 0) {
@@ -744,7 +755,7 @@ hipError_t launch_smear_window(const ViscArgs& v, double* ind, double* w, hipStr
                      1, v.nv, v.wdil, w, nullptr);
   if (v.nblend)
     hipLaunchKernelGGL(k_blend_rows, grid_for(static_cast<int64_t>(v.nblend) * kBlendLanes), dim3(256), 0, s, v.mut, w,
-                       v.bdst, v.bptr, v.bcol, v.bval, v.nblend, nullptr, nullptr);
+                       v.brow, v.bterm, v.nblend, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -813,8 +824,7 @@ hipError_t launch_viscosity(const ViscArgs& v, hipStream_t s) {
                      1, v.nv, v.wdil, v.mu, v.act);
   if (v.nblend)
     hipLaunchKernelGGL(k_blend_rows, grid_for(static_cast<int64_t>(v.nblend) * kBlendLanes), dim3(256), 0, s, v.mut,
-                       v.mu, v.bdst, v.bptr, v.bcol,
-                       v.bval, v.nblend, v.bact, v.act);
+                       v.mu, v.brow, v.bterm, v.nblend, v.bact, v.act);
   return hipGetLastError();
 }
 
