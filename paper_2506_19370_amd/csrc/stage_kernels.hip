@@ -394,12 +394,13 @@ __global__ void k_window_geo(ClassifyArgs a, int4* __restrict__ out) {
 }
 
 // Alg. 3 with the SDNN: each wave classifies the two windows of 64 points
-// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  Round
-// 2 pg + dir covers direction dir of the points 16 pg .. 16 pg + 15 of the
-// chunk; the window geometry comes from the per-point table, is handed to
-// the rounds by lane shuffles, and each round's window values are fetched
-// while the previous round is on the matrix cores.  Lanes 0..15 write the
-// classes and the preliminary viscosity of the points of their rounds.
+// in 8 rounds of 16 windows on the matrix cores (see sdnn_mfma).  Per
+// direction, lane l first gathers the whole window of point l of the chunk
+// (16 independent loads in flight, coalesced across the lanes: neighbouring
+// points' windows are neighbouring addresses) into its row of an LDS block,
+// keeping the window's largest wave speed; round pg then hands window
+// 16 pg + c to lanes c, c + 16, c + 32, c + 48, four values each, read from
+// LDS.  Lane l writes the classes and the preliminary viscosity of its point.
 //
 // Persistent: the grid holds a fixed number of waves (a multiple of the 8
 // XCDs), each loads its weight fragments once and walks chunks of 64
@@ -407,11 +408,14 @@ __global__ void k_window_geo(ClassifyArgs a, int4* __restrict__ out) {
 // contiguous share, so the grid rows that the column windows of
 // neighbouring chunks share stay in one XCD's L2.
 constexpr int kClassifyBlocks = 768;  // 3 workgroups of 4 waves per CU (occupancy 3)
+constexpr int kWinPitch = 18;         // doubles per LDS window row (16 + 2: bank spread)
 
 __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
+  __shared__ __attribute__((aligned(16))) double win[4][64 * kWinPitch];
   SdnnFrag F;
   load_sdnn_frag(a.sdnn_table, F);
   const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  double* W = win[threadIdx.x >> 6];
   const int64_t nchunk = (a.P + 63) / 64;
   const int xcd = static_cast<int>(blockIdx.x & 7);
   const int64_t per_xcd = static_cast<int64_t>(gridDim.x >> 3) * 4;  // waves per XCD
@@ -420,66 +424,72 @@ __global__ __launch_bounds__(256) void k_classify_sdnn(ClassifyArgs a) {
 #pragma unroll 1
   for (int64_t ch = share * xcd + static_cast<int64_t>(blockIdx.x >> 3) * 4 + (threadIdx.x >> 6); ch < c_end;
        ch += per_xcd) {
-    const int64_t kw = ch * 64;
-    const int64_t kl = kw + lane;
-    const uint8_t fl = kl < a.P ? a.flags[kl] : 0;
-    const int4 geo = kl < a.P ? a.wgeo[kl] : int4{-1, 0, -1, 0};
-    // values (proxy, wave speed) of this lane's 4 window points in round (pg, dir)
-    auto fetch = [&](int pg, int dir, double2 (&q)[4]) -> bool {
-      const int src = 16 * pg + c;
-      const int base = __shfl(dir == 0 ? geo.x : geo.z, src);
-      const int stride = __shfl(dir == 0 ? geo.y : geo.w, src);
-      const bool valid = base >= 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        q[j] = valid ? a.ps[static_cast<int64_t>(base) + static_cast<int64_t>(4 * g + j) * stride]
-                     : double2{0.0, 0.0};
-      return valid;
-    };
-    double2 qc[4];
-    bool vc = fetch(0, 0, qc);
+    const int64_t kl = ch * 64 + lane;  // this lane's point
+    const bool in = kl < a.P;
+    const uint8_t fl = in ? a.flags[kl] : 0;
+    const int4 geo = in ? a.wgeo[kl] : int4{-1, 0, -1, 0};
+    int tau_own[2] = {0, 0};
+    double smax = 0.0;
 #pragma unroll 1
-    for (int pg = 0; pg < 4; ++pg) {
-      const int src = 16 * pg + c;  // lane that owns this round's point
-      int tau[2] = {0, 0};
-      double smax = 0.0;
+    for (int dir = 0; dir < 2; ++dir) {
+      const int base = dir == 0 ? geo.x : geo.z, stride = dir == 0 ? geo.y : geo.w;
+      const bool valid = base >= 0;
+      // gather this lane's window: 16 loads in flight (a lane without a
+      // window reads point 0 and stores zeros), proxy values to LDS, the
+      // largest wave speed kept, and whether the window is flat (the test of
+      // sdnn_features on the same values: a round of 16 flat windows gives
+      // class 0 without the network)
+      const double2* __restrict__ src = a.ps + (valid ? static_cast<int64_t>(base) : 0);
+      const int64_t st = valid ? stride : 0;
+      double sp = 0.0, lo = 0.0, hi = 0.0;
 #pragma unroll
-      for (int dir = 0; dir < 2; ++dir) {
-        double2 qn[4] = {};
-        bool vn = false;
-        if (dir == 0)
-          vn = fetch(pg, 1, qn);
-        else if (pg + 1 < 4)
-          vn = fetch(pg + 1, 0, qn);
-        double v[4], sp = 0.0;
+      for (int h = 0; h < 2; ++h) {
+        double2 q[8];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          v[j] = qc[j].x;
-          sp = fmax(sp, qc[j].y);
+        for (int m = 0; m < 8; ++m) q[m] = src[(8 * h + m) * st];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+          if (!valid) q[m] = double2{0.0, 0.0};
+          lo = (h == 0 && m == 0) ? q[m].x : fmin(lo, q[m].x);
+          hi = (h == 0 && m == 0) ? q[m].x : fmax(hi, q[m].x);
+          sp = fmax(sp, q[m].y);
         }
-        sp = fmax(sp, __shfl_xor(sp, 16));
-        sp = fmax(sp, __shfl_xor(sp, 32));
+#pragma unroll
+        for (int m = 0; m < 8; m += 2)
+          *reinterpret_cast<double2*>(&W[lane * kWinPitch + 8 * h + m]) = double2{q[m].x, q[m + 1].x};
+      }
+      if (valid) smax = fmax(smax, sp);
+      const double am = fmax(fabs(lo), fabs(hi));
+      const uint64_t livemask = __ballot(valid && !(hi - lo < 1e-3 * fmax(am, 1.0)));
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      int tv = 0;  // class of window 16 pg + c along dir, kept by lane (pg, c) of the rounds
+#pragma unroll 1
+      for (int pg = 0; pg < 4; ++pg) {
+        if (((livemask >> (16 * pg)) & 0xFFFFull) == 0) continue;  // 16 flat windows: class 0
+        const double2 v01 = *reinterpret_cast<const double2*>(&W[(16 * pg + c) * kWinPitch + 4 * g]);
+        const double2 v23 = *reinterpret_cast<const double2*>(&W[(16 * pg + c) * kWinPitch + 4 * g + 2]);
+        const double v[4] = {v01.x, v01.y, v23.x, v23.y};
         float x[4], z[3] = {0.0f, 0.0f, 0.0f};
         const bool live = sdnn_features(v, x);
         // a flat window is smooth without the network: a round of 16 flat
         // windows skips it (the branch is uniform over the wave, and when
         // taken all 64 lanes run the matrix instructions)
         if (__ballot(live) != 0) sdnn_mfma(F, x, z);
-        if (vc) {
-          smax = fmax(smax, sp);
-          tau[dir] = live ? sdnn_argmax(z) : 0;
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) qc[j] = qn[j];
-        vc = vn;
+        const int t = live ? sdnn_argmax(z) : 0;  // valid in lanes 0..15
+        // lane 16 pg + c' takes the class of window c' from lane c'
+        const int tt = __shfl(t, lane & 15);
+        if ((lane >> 4) == pg) tv = tt;
       }
-      const int64_t k = kw + src;
-      const uint8_t f = __shfl(static_cast<int>(fl), src);
-      if (g == 0 && k < a.P) {
-        a.tau[k] = static_cast<uint8_t>(tau[0]);
-        a.tau[a.P + k] = static_cast<uint8_t>(tau[1]);
-        a.muhat[k] = muhat_of(a, k, f, tau[0], tau[1], smax);
-      }
+      tau_own[dir] = valid ? tv : 0;
+      // the next direction overwrites this wave's LDS rows
+      __builtin_amdgcn_wave_barrier();
+    }
+    if (in) {
+      a.tau[kl] = static_cast<uint8_t>(tau_own[0]);
+      a.tau[a.P + kl] = static_cast<uint8_t>(tau_own[1]);
+      a.muhat[kl] = muhat_of(a, kl, fl, tau_own[0], tau_own[1], smax);
     }
   }
 }
