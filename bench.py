@@ -468,8 +468,9 @@ def main():
                      "achieved": rf["hbm"]["achieved_GBps"], "peak": rf["hbm"]["peak_GBps"], "unit": "GB/s",
                      "frac": rf["hbm"]["frac"], "traffic": None,
                      "traffic_detail": None,
-                     "achieved_from": "algorithmic bytes of one launch (FP64 operand lines read once, derivatives "
-                                      "written once, the lines that step needs) / average launch time",
+                     "achieved_from": "algorithmic bytes of one launch (each operand line the step needs read once "
+                                      "in FP64, each derivative written once in the precision of its array) / "
+                                      "average launch time",
                      "avg_launch_ms": rf["avg_launch_ms"], "mfma": rf["mfma"],
                      "timing": "the last step's stage contraction, launches back to back between HIP events"},
         "wedge": wedge,

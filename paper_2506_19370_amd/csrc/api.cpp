@@ -261,6 +261,14 @@ double exact_flops(const std::vector<TaskSpec>& tasks) {
   return f;
 }
 
+// Algorithmic bytes of one line of a stage-contraction task: the operand
+// line read once in FP64, the result written once in the precision of its
+// array (FP32 stage derivatives in the mixed forms).
+double task_bytes(const fcs_ctx* c, const TaskSpec& t) {
+  const bool f32 = c->deriv_f32 && t.dst_arr != A_MU1 && t.dst_arr != A_MU2 && !(c->cross && t.dst_arr == A_W1);
+  return t.n * (8.0 + (f32 ? 4.0 : 8.0));
+}
+
 fcs_status upload(fcs_ctx* c, const char* name, const void* src, size_t bytes) {
   if (!bytes) return FCS_OK;
   HIPCHK(c, hipMemcpyAsync(c->ws + c->off.at(name), src, bytes, hipMemcpyHostToDevice, c->stream));
@@ -1219,7 +1227,7 @@ fcs_status stage_work(fcs_ctx* c, double* flops, double* bytes) {
       lines = static_cast<double>(live) * t.ncomp;
     }
     f += 2.0 * t.n * t.n * lines;
-    b += 2.0 * 8.0 * t.n * lines;  // each operand line read once, each output written once (FP64)
+    b += task_bytes(c, t) * lines;
   }
   *flops = f;
   *bytes = b;
@@ -1676,9 +1684,9 @@ extern "C" fcs_status fcs_profile_read(fcs_ctx* c, double* avg_ms, double* flops
   // before any profiled step)
   if (flops) *flops = c->prof_fn ? c->prof_flops / c->prof_fn : exact_flops(c->phase_tasks[PH_EULER]);
   if (bytes) {
-    // algorithmic bytes: each operand line read once, each output written once (FP64)
+    // algorithmic bytes: each operand line read once, each result written once
     double b = 0;
-    for (const auto& t : c->phase_tasks[PH_EULER]) b += 2.0 * 8.0 * t.n * static_cast<double>(t.nrow) * t.ncomp;
+    for (const auto& t : c->phase_tasks[PH_EULER]) b += task_bytes(c, t) * static_cast<double>(t.nrow) * t.ncomp;
     *bytes = c->prof_fn ? c->prof_bytes / c->prof_fn : b;
   }
   if (launches) *launches = c->prof_n;
