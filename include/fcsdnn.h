@@ -327,11 +327,15 @@ fcs_status fcs_modal_infer(const double* windows, int64_t nwin, uint8_t* tau, vo
  * eps 1e-8, step number t >= 1).  x: device, batch x 16 normalized windows
  * (FP32); labels: device int32; class_weight: device, 3 floats; params, m, v:
  * device FP32 (FCS_SDNN_NPARAM each), updated in place; loss: device float;
- * grads: device FP32 (FCS_SDNN_NPARAM) or NULL.  Activations are BF16 in the
- * products, FP32 elsewhere.  workspace: device, fcs_sdnn_train_workspace
- * bytes. */
+ * grads: device FP32 (FCS_SDNN_NPARAM) or NULL.  Default: forward and
+ * backward on the BF16 matrix cores (inputs, weights and hidden activations
+ * rounded to bf16, the back-propagated errors entering the products as two
+ * bf16 parts, FP32 accumulation and FP32 elsewhere; the batch sums in a fixed
+ * order, so a step is deterministic).  workspace: device,
+ * fcs_sdnn_train_workspace bytes. */
 size_t fcs_sdnn_train_workspace(int32_t batch);
-/* flags bit 0: FP32 activations (no bf16 rounding; gradient-check mode). */
+/* flags bit 0: FP32 activations and products, no bf16 rounding (the
+ * gradient-check mode; scalar FP32 kernels, not the matrix cores). */
 fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int32_t t, float lr,
                                const float* x, const int32_t* labels, const float* class_weight,
                                int32_t batch, float* loss, float* grads, int32_t flags,
@@ -341,7 +345,7 @@ fcs_status fcs_sdnn_train_step(float* params, float* m, float* v, int32_t t, flo
  * allocate device memory (code under HIP graph capture, tight serving or
  * training loops, harnesses that forbid hipMalloc).  Same arguments and
  * results without the workspace: the per-sample scratch is a library-owned
- * device array sized for FCS_SDNN_TRAIN_MAX_BATCH samples (9.1 MB), of which
+ * device array sized for FCS_SDNN_TRAIN_MAX_BATCH samples (9.8 MB), of which
  * each GPU holds its own copy from the first call on it until the process
  * ends.  The call allocates nothing.  batch > FCS_SDNN_TRAIN_MAX_BATCH (or any
  * argument fcs_sdnn_train_step rejects) -> FCS_EINVAL; a failed symbol lookup
