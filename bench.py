@@ -276,6 +276,8 @@ def measured_traffic(kernel, points):
         return None
     return {"bytes_per_launch": m["hbm_bytes_per_launch"], "read_bytes": m["hbm_read_bytes_per_launch"],
             "write_bytes": m["hbm_write_bytes_per_launch"],
+            "algorithmic_bytes_counted": m["algorithmic_bytes_per_launch"],
+            "counted_launches": m.get("counted_state"),
             "vs_algorithmic": m["hbm_bytes_per_launch"] / m["algorithmic_bytes_per_launch"],
             "from": "profiles/wedge_stage_contraction_traffic.md (rocprofv3 FETCH_SIZE x %.3f, WRITE_SIZE x %.3f)"
                     % (m["calibration"]["fetch_factor"], m["calibration"]["write_factor"])}

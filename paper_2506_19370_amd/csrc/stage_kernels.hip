@@ -173,111 +173,195 @@ __global__ void k_wall_apply(double* __restrict__ U, const WallLine* __restrict_
   if (ps) ps[k] = proxy_speed(r, 0.0, 0.0, E, gamma);
 }
 
+// Fluxes of one point as store_flux, with the contravariant metric terms of
+// its subpatch (used on affine subpatches) already loaded.
+__device__ __forceinline__ void store_flux_m(const FluxOut& fo, int64_t P, int64_t k, uint8_t f, double r, double mx,
+                                             double my, double E, const double (&m)[4]) {
+  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (f & kActive) {
+    const double p = pressure(r, mx, my, E, fo.gm1);
+    const double u = mx / r, w = my / r;
+    const double fx[4] = {mx, mx * u + p, mx * w, u * (E + p)};
+    const double fy[4] = {my, my * u, my * w + p, w * (E + p)};
+    if (f & kAffine) {
+      for (int q = 0; q < 4; ++q) {
+        v[q] = m[0] * fx[q] + m[1] * fy[q];
+        v[4 + q] = m[2] * fx[q] + m[3] * fy[q];
+      }
+    } else {
+      for (int q = 0; q < 4; ++q) {
+        v[q] = fx[q];
+        v[4 + q] = fy[q];
+      }
+    }
+  }
+  for (int q = 0; q < 8; ++q) fo.F[q * P + k] = v[q];
+}
+
 // DT: element type of the stage derivatives (double, or float in the mixed
 // forms, where the contractions themselves are FP32 or split BF16).
 // S: the stage (0..4), so that each instantiation reads only the registers
-// its combination uses and can issue all its loads up front.
-template <typename DT, int S>
-__global__ void k_stage(StageArgs a) {
+// its combination uses.  W1T: element type of the viscous first derivative
+// along q^1 (FP64 in the mixed forms when it feeds the mixed-derivative
+// contraction).
+//
+// A stage update is a stream of independent per-point loads, so the kernel
+// issues them in as few dependent rounds as the data allows: (1) the
+// point's flag, copy donor and subpatch; (2) everything the update reads at
+// the donor (the donor's own flag first where it is another point): stage
+// derivatives, mu and its derivatives, the stage input, U0 and the
+// accumulator, the subpatch's flux metrics; (3) only where mu or one of its
+// derivatives is nonzero, the viscous derivatives and metric terms.  No
+// loaded value is consumed inside a branch of its round, and inactive
+// points take the same path, storing zeros at the end.
+template <typename DT, int S, typename W1T>
+__global__ __launch_bounds__(256) void k_stage(StageArgs a) {
   const DT* DF1 = static_cast<const DT*>(a.DF1);
   const DT* DF2 = static_cast<const DT*>(a.DF2);
-  int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  const int64_t k = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
   const int64_t P = a.P;
   if (k >= P) return;
+  // round 1
   const uint8_t fk = a.flags[k];
-  if (!(fk & kActive)) {
-    for (int q = 0; q < 4; ++q) a.out[q * P + k] = 0.0;
-    if (a.flux.F) store_flux(a.flux, P, k, fk, 0.0, 0.0, 0.0, 0.0);
-    if (a.ps) a.ps[k] = double2{0.0, 0.0};
-    return;
-  }
   // A fringe point filled by a copy (its donor on a common lattice, never a
   // recipient itself) takes its donor's update here instead of in the fringe
   // kernel: the donor's inputs, this point's outputs and fluxes.  It keeps
   // its own accumulator slot, which holds the same values as the donor's
   // (both are formed from equal inputs), so the read-modify-write of the
   // fourth stage does not race with the donor's thread.
-  const int64_t ks = a.csrc ? a.csrc[k] : k;
-  const uint8_t f = ks == k ? fk : a.flags[ks];
+  // (without copy points the donor load re-reads the subpatch index: no
+  // branch, so no wait before the next round)
+  const int32_t ck = (a.csrc ? a.csrc : a.pid)[k];
+  const int32_t pk = a.pid[k];
+  const int64_t ks = a.csrc ? ck : k;
   const double dt = *a.dt;
-  double L[4];
-  if (f & kAffine) {
-    for (int q = 0; q < 4; ++q)
-      L[q] = -(static_cast<double>(DF1[q * P + ks]) + static_cast<double>(DF2[(4 + q) * P + ks]));
-  } else {
-    double t1x = a.t1x[ks], t1y = a.t1y[ks], t2x = a.t2x[ks], t2y = a.t2y[ks];
-    for (int q = 0; q < 4; ++q)
-      L[q] = -(t1x * static_cast<double>(DF1[q * P + ks]) + t1y * static_cast<double>(DF1[(4 + q) * P + ks]) +
-               t2x * static_cast<double>(DF2[q * P + ks]) + t2y * static_cast<double>(DF2[(4 + q) * P + ks]));
+  const bool act = fk & kActive;
+  // the donor's flag and subpatch (copy points only: one more round there)
+  uint8_t f = fk;
+  int32_t pks = pk;
+  if (ks != k) {
+    f = a.flags[ks];
+    pks = a.pid[ks];
   }
-  const double mu = a.visc ? a.mu[ks] : 0.0, mu1 = a.visc ? a.mu1[ks] : 0.0, mu2 = a.visc ? a.mu2[ks] : 0.0;
-  // Where mu and both of its derivatives vanish the viscous term is an exact
-  // zero: the derivatives of w there are not read (on skipped lines they
-  // may be those of an earlier step).
+  const bool aff = f & kAffine;
+
+  // round 2.  Stage derivatives: affine subpatches need d1 G^1 and d2 G^2
+  // only; the other subpatches also d1 G^2, d2 G^1 and the metric terms,
+  // whose loads read the affine entries' addresses (or entry 0) on affine
+  // points, so that they fetch nothing more from memory there.
+  DT d1a[4], d1b[4], d2a[4], d2b[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    d1a[q] = DF1[q * P + ks];
+    d2b[q] = DF2[(4 + q) * P + ks];
+    d1b[q] = DF1[(aff ? q : 4 + q) * P + ks];
+    d2a[q] = DF2[(aff ? 4 + q : q) * P + ks];
+  }
+  const int64_t km = aff ? 0 : ks;
+  const double t1x = a.t1x[km], t1y = a.t1y[km], t2x = a.t2x[km], t2y = a.t2y[km];
+  double mu = 0.0, mu1 = 0.0, mu2 = 0.0;
+  if (a.visc) {
+    mu = a.mu[ks];
+    mu1 = a.mu1[ks];
+    mu2 = a.mu2[ks];
+  }
+  double in[4], u0[4], ac[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    in[q] = a.in[q * P + ks];
+    if constexpr (S >= 1 && S <= 3) u0[q] = a.U0[q * P + ks];
+    if constexpr (S >= 3) ac[q] = a.acc[q * P + k];
+  }
+  double fm[4] = {0.0, 0.0, 0.0, 0.0};
+  if (a.flux.F) {
+    const PatchDev* pd = a.patches + pk;
+    fm[0] = pd->t1x;
+    fm[1] = pd->t1y;
+    fm[2] = pd->t2x;
+    fm[3] = pd->t2y;
+  }
+
+  double L[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double e1 = -(static_cast<double>(d1a[q]) + static_cast<double>(d2b[q]));
+    const double e2 = -(t1x * static_cast<double>(d1a[q]) + t1y * static_cast<double>(d1b[q]) +
+                        t2x * static_cast<double>(d2a[q]) + t2y * static_cast<double>(d2b[q]));
+    L[q] = aff ? e1 : e2;
+  }
+  // round 3.  Where mu and both of its derivatives vanish the viscous term
+  // is an exact zero: the derivatives of w there are not read (on skipped
+  // lines they may be those of an earlier step).
   if (mu != 0.0 || mu1 != 0.0 || mu2 != 0.0) {
-    double g11, g12, g22, l1, l2;
-    if (f & kAffine) {
-      // constant metrics of the subpatch; the index coordinates are harmonic
-      const PatchDev& pd = a.patches[a.pid[ks]];
-      g11 = pd.g11;
-      g12 = pd.g12;
-      g22 = pd.g22;
-      l1 = 0.0;
-      l2 = 0.0;
-    } else {
-      g11 = a.g11[ks];
-      g12 = a.g12[ks];
-      g22 = a.g22[ks];
-      l1 = a.lap1[ks];
-      l2 = a.lap2[ks];
-    }
-    const DT *W1 = static_cast<const DT*>(a.W1), *W2 = static_cast<const DT*>(a.W2);
-    const DT *W11 = static_cast<const DT*>(a.W11), *W22 = static_cast<const DT*>(a.W22);
-    const DT* W12 = static_cast<const DT*>(a.W12);
+    const PatchDev* pd = a.patches + pks;
+    // constant metrics on affine subpatches, whose index coordinates are
+    // harmonic (no Laplacian terms)
+    const double pg11 = pd->g11, pg12 = pd->g12, pg22 = pd->g22;
+    const double cg11 = a.g11[km], cg12 = a.g12[km], cg22 = a.g22[km], cl1 = a.lap1[km], cl2 = a.lap2[km];
+    const W1T* W1 = static_cast<const W1T*>(a.W1);
+    const DT *W2 = static_cast<const DT*>(a.W2), *W11 = static_cast<const DT*>(a.W11),
+             *W22 = static_cast<const DT*>(a.W22);
+    // without the mixed-derivative array the load re-reads W2's entry and
+    // the term is zero
+    const bool has12 = a.W12 != nullptr;
+    const DT* W12 = has12 ? static_cast<const DT*>(a.W12) : W2;
+    double w1[4], w2[4], w11[4], w22[4], w12[4];
+#pragma unroll
     for (int q = 0; q < 4; ++q) {
-      double w1 = a.w1_f64 ? static_cast<const double*>(a.W1)[q * P + ks] : static_cast<double>(W1[q * P + ks]);
-      double w2 = W2[q * P + ks], w11 = W11[q * P + ks], w22 = W22[q * P + ks];
-      double w12 = W12 ? static_cast<double>(W12[q * P + ks]) : 0.0;
-      double lap = g11 * w11 + 2.0 * g12 * w12 + g22 * w22 + l1 * w1 + l2 * w2;
-      double grad = g11 * mu1 * w1 + g12 * (mu1 * w2 + mu2 * w1) + g22 * mu2 * w2;
+      w1[q] = W1[q * P + ks];
+      w2[q] = W2[q * P + ks];
+      w11[q] = W11[q * P + ks];
+      w22[q] = W22[q * P + ks];
+      w12[q] = W12[q * P + ks];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) w12[q] = has12 ? w12[q] : 0.0;
+    const double g11 = aff ? pg11 : cg11, g12 = aff ? pg12 : cg12, g22 = aff ? pg22 : cg22;
+    const double l1 = aff ? 0.0 : cl1, l2 = aff ? 0.0 : cl2;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      double lap = g11 * w11[q] + 2.0 * g12 * w12[q] + g22 * w22[q] + l1 * w1[q] + l2 * w2[q];
+      double grad = g11 * mu1 * w1[q] + g12 * (mu1 * w2[q] + mu2 * w1[q]) + g22 * mu2 * w2[q];
       L[q] = L[q] + mu * lap + grad;
     }
   }
   double o[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    const double in = a.in[q * P + ks];
     if constexpr (S == 0) {
-      o[q] = in + a.c[0] * dt * L[q];  // the input of the first stage is U0
+      o[q] = in[q] + a.c[0] * dt * L[q];  // the input of the first stage is U0
     } else if constexpr (S == 1) {
-      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+      o[q] = a.c[1] * u0[q] + a.c[2] * in[q] + a.c[3] * dt * L[q];
     } else if constexpr (S == 2) {
-      a.acc[q * P + k] = a.c[4] * in;
-      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+      if (act) a.acc[q * P + k] = a.c[4] * in[q];
+      o[q] = a.c[1] * u0[q] + a.c[2] * in[q] + a.c[3] * dt * L[q];
     } else if constexpr (S == 3) {
-      const double acc = a.acc[q * P + k];
-      a.acc[q * P + k] = acc + a.c[4] * in + a.c[5] * dt * L[q];
-      o[q] = a.c[1] * a.U0[q * P + ks] + a.c[2] * in + a.c[3] * dt * L[q];
+      if (act) a.acc[q * P + k] = ac[q] + a.c[4] * in[q] + a.c[5] * dt * L[q];
+      o[q] = a.c[1] * u0[q] + a.c[2] * in[q] + a.c[3] * dt * L[q];
     } else {
-      o[q] = a.acc[q * P + k] + a.c[4] * in + a.c[5] * dt * L[q];
+      o[q] = ac[q] + a.c[4] * in[q] + a.c[5] * dt * L[q];
     }
   }
-  bool bad = false;
-  for (int q = 0; q < 4; ++q)
-    if (!isfinite(o[q])) bad = true;
-  if (!bad) {
-    const double p = pressure(o[0], o[1], o[2], o[3], a.gm1);
-    bad = !(o[0] > 0.0) || !(p > 0.0);
-  }
-  if (bad) *a.bad_flag = 1;
-  if (f & kBoundary) {
-    const double t = *a.bcs.t + a.bcs.frac * dt;
-    apply_bc(a.bcs.bc[a.bcs.bcidx[ks]], a.bcs.gamma, t, a.bcs.vortex, o[0], o[1], o[2], o[3]);
+  if (act) {
+    bool bad = false;
+    for (int q = 0; q < 4; ++q)
+      if (!isfinite(o[q])) bad = true;
+    if (!bad) {
+      const double p = pressure(o[0], o[1], o[2], o[3], a.gm1);
+      bad = !(o[0] > 0.0) || !(p > 0.0);
+    }
+    if (bad) *a.bad_flag = 1;
+    if (f & kBoundary) {
+      const double t = *a.bcs.t + a.bcs.frac * dt;
+      apply_bc(a.bcs.bc[a.bcs.bcidx[ks]], a.bcs.gamma, t, a.bcs.vortex, o[0], o[1], o[2], o[3]);
+    }
+  } else {
+    for (int q = 0; q < 4; ++q) o[q] = 0.0;
   }
   for (int q = 0; q < 4; ++q) a.out[q * P + k] = o[q];
-  if (a.flux.F) store_flux(a.flux, P, k, fk, o[0], o[1], o[2], o[3]);
+  if (a.flux.F) store_flux_m(a.flux, P, k, fk, o[0], o[1], o[2], o[3], fm);
   // the last stage also evaluates the next step's proxy (Alg. 3 input)
-  if (a.ps) a.ps[k] = proxy_speed(o[0], o[1], o[2], o[3], a.bcs.gamma);
+  if (a.ps) a.ps[k] = act ? proxy_speed(o[0], o[1], o[2], o[3], a.bcs.gamma) : double2{0.0, 0.0};
 }
 
 // Fringe fill (Sec. 3.3): rows 0 .. ncopy-1 copy one donor value (common
@@ -723,23 +807,25 @@ hipError_t launch_flux(const double* U, const uint8_t* flags, const FluxOut& fo,
   return hipGetLastError();
 }
 
-template <typename DT>
+template <typename DT, typename W1T>
 void launch_stage_dt(const StageArgs& a, hipStream_t s) {
   switch (a.stage) {
-    case 0: hipLaunchKernelGGL((k_stage<DT, 0>), grid_for(a.P), dim3(256), 0, s, a); break;
-    case 1: hipLaunchKernelGGL((k_stage<DT, 1>), grid_for(a.P), dim3(256), 0, s, a); break;
-    case 2: hipLaunchKernelGGL((k_stage<DT, 2>), grid_for(a.P), dim3(256), 0, s, a); break;
-    case 3: hipLaunchKernelGGL((k_stage<DT, 3>), grid_for(a.P), dim3(256), 0, s, a); break;
-    default: hipLaunchKernelGGL((k_stage<DT, 4>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 0: hipLaunchKernelGGL((k_stage<DT, 0, W1T>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 1: hipLaunchKernelGGL((k_stage<DT, 1, W1T>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 2: hipLaunchKernelGGL((k_stage<DT, 2, W1T>), grid_for(a.P), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL((k_stage<DT, 3, W1T>), grid_for(a.P), dim3(256), 0, s, a); break;
+    default: hipLaunchKernelGGL((k_stage<DT, 4, W1T>), grid_for(a.P), dim3(256), 0, s, a); break;
   }
 }
 
 hipError_t launch_stage(const StageArgs& a, hipStream_t s) {
   if (a.stage < 0 || a.stage > 4) return hipErrorInvalidValue;
-  if (a.deriv_f32)
-    launch_stage_dt<float>(a, s);
+  if (a.deriv_f32 && a.w1_f64)
+    launch_stage_dt<float, double>(a, s);
+  else if (a.deriv_f32)
+    launch_stage_dt<float, float>(a, s);
   else
-    launch_stage_dt<double>(a, s);
+    launch_stage_dt<double, double>(a, s);
   return hipGetLastError();
 }
 
