@@ -65,12 +65,14 @@ def parse():
     ap.add_argument("--tiled", action="store_true",
                     help="also run the tiled step channel at 1.17e7 points (FP64 and split-BF16)")
     ap.add_argument("--cpu-steps", type=int, default=3)
-    ap.add_argument("--classifier-lines", type=int, default=100_000,
+    ap.add_argument("--classifier-lines", type=int, default=1_000_000,
                     help="synthetic lines for training the classifier (10 %% held out)")
+    ap.add_argument("--classifier-epochs", type=int, default=3,
+                    help="passes over the training windows (each in a fresh seeded order)")
     return ap.parse_args()
 
 
-def train_classifier(F, W, torch, nlines=100_000, epochs=1, batch=8192, lr=1e-3):
+def train_classifier(F, W, torch, nlines=1_000_000, epochs=3, batch=8192, lr=1e-3):
     """Seeded training of the smoothness classifier on the GPU: synthetic
     lines through the solver's FC filter (d = 2, C = 27), 16-point windows,
     class-weighted Adam with the library's training kernels; 10 % of the
@@ -99,19 +101,29 @@ def train_classifier(F, W, torch, nlines=100_000, epochs=1, batch=8192, lr=1e-3)
         x = ((w - lo) / torch.where(rng_ > 0, rng_, torch.ones_like(rng_)))[keep].float().contiguous()
         return x, y[keep].int().contiguous(), w, y
 
+    log("classifier data: %d lines, labels and filter done" % nlines)
     x, y, _, _ = prep(wins[:ntrain], labt[:ntrain])
     counts = torch.bincount(y, minlength=3).double()
     cw = (counts.sum() / (3.0 * torch.clamp(counts, min=1.0))).float()
     g = W.rng(4, 52)
     params = torch.tensor(W.sdnn_blob(W.sdnn_init(g)), device="cuda")
     tr = F.SdnnTrainer(params, batch=batch, lr=lr)
-    nsteps = max(1, int(epochs * y.numel() // batch))
-    perm = torch.randperm(y.numel(), generator=torch.Generator().manual_seed(52)).to("cuda")
-    for s_ in range(nsteps):
-        sel = perm[(s_ * batch) % max(1, y.numel() - batch):][:batch]
-        tr.step(x[sel].contiguous(), y[sel].contiguous(), cw)
+    # each epoch reorders the windows once (seeded) and steps through
+    # contiguous batches of the reordered copy
+    torch.cuda.synchronize()
+    t_loop = time.perf_counter()
+    gen = torch.Generator().manual_seed(52)
+    per_epoch = max(1, y.numel() // batch)
+    nsteps = epochs * per_epoch
+    for _ in range(epochs):
+        perm = torch.randperm(y.numel(), generator=gen).to("cuda")
+        xs, ys = x[perm], y[perm]
+        for s_ in range(per_epoch):
+            tr.step(xs[s_ * batch:(s_ + 1) * batch], ys[s_ * batch:(s_ + 1) * batch], cw)
+        del xs, ys, perm
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
+    loop_s = time.perf_counter() - t_loop
     # held-out lines: raw windows through both classifiers (flat windows are
     # smooth by the classifiers' own rule)
     hw = wins[ntrain:].reshape(-1, 16).contiguous()
@@ -125,7 +137,7 @@ def train_classifier(F, W, torch, nlines=100_000, epochs=1, batch=8192, lr=1e-3)
                     "recall_per_class": [float(conf[c, c] / max(conf[c].sum(), 1)) for c in range(3)],
                     "confusion_true_by_predicted": conf.tolist()}
     info = {"lines": nlines, "train_lines": ntrain, "train_windows": int(y.numel()), "batch": batch,
-            "steps": nsteps, "epochs": epochs, "train_s": train_s, "heldout_windows": int(hy.size), **ev}
+            "steps": nsteps, "epochs": epochs, "train_s": train_s, "train_loop_s": loop_s, "heldout_windows": int(hy.size), **ev}
     return params.cpu().numpy(), info
 
 
@@ -453,7 +465,7 @@ def main():
     import workloads as W
 
     forms = [f for f in a.forms.split(",") if f]
-    weights, train_info = train_classifier(F, W, torch, nlines=a.classifier_lines)
+    weights, train_info = train_classifier(F, W, torch, nlines=a.classifier_lines, epochs=a.classifier_epochs)
     log("classifier trained on %d lines" % a.classifier_lines)
     wedge = wedge_run(F, W, torch, weights, forms, a.steps, a.warmup, eager=a.eager, stage_variant=a.stage_variant)
     head = forms[0]
