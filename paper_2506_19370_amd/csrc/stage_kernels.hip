@@ -26,9 +26,9 @@ __device__ __forceinline__ double pressure(double r, double mx, double my, doubl
 // Euler fluxes of one state as the 8 operand components of the stage
 // contraction: contravariant q^k_x f_x + q^k_y f_y on affine subpatches,
 // f_x and f_y otherwise; zero at inactive points.
-__device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t k, uint8_t f, double r, double mx,
-                                           double my, double E) {
-  double v[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+__device__ __forceinline__ void flux_of(const FluxOut& fo, int64_t k, uint8_t f, double r, double mx, double my,
+                                        double E, double (&v)[8]) {
+  for (int q = 0; q < 8; ++q) v[q] = 0.0;
   if (f & kActive) {
     const double p = pressure(r, mx, my, E, fo.gm1);
     const double u = mx / r, w = my / r;
@@ -48,6 +48,11 @@ __device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t
       }
     }
   }
+}
+__device__ __forceinline__ void store_flux(const FluxOut& fo, int64_t P, int64_t k, uint8_t f, double r, double mx,
+                                           double my, double E) {
+  double v[8];
+  flux_of(fo, k, f, r, mx, my, E, v);
   for (int q = 0; q < 8; ++q) fo.F[q * P + k] = v[q];
 }
 
@@ -367,31 +372,49 @@ __global__ __launch_bounds__(256) void k_stage(StageArgs a) {
 // Fringe fill (Sec. 3.3): rows 0 .. ncopy-1 copy one donor value (common
 // lattice), the rest evaluate an interpolation row; donors are never
 // recipients, so all rows are independent.  The fluxes of each filled point
-// follow when fo.F is set.
+// follow when fo.F is set.  Four lanes share a row: lane j of the four
+// accumulates the row's entries j, j + 4, ... (consecutive lanes read
+// consecutive entries), a butterfly over the four gives each of them the
+// same sums, and lane j stores field j and flux components j and j + 4.
+constexpr int kFringeLanes = 4;
 __global__ void k_fringe(double* __restrict__ U, const uint8_t* __restrict__ flags, const int64_t* __restrict__ pairs,
                          int ncopy, const int64_t* __restrict__ dst, const int32_t* __restrict__ ptr,
                          const int64_t* __restrict__ col, const double* __restrict__ val, int ninterp, int64_t P,
                          FluxOut fo, double2* __restrict__ ps, double gamma) {
-  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  int q = static_cast<int>(g / kFringeLanes);
+  const int j = static_cast<int>(g % kFringeLanes);
+  // rows are whole groups of four lanes, so a group is in or out together
   if (q >= ncopy + ninterp) return;
   double s[4] = {0, 0, 0, 0};
   int64_t k;
   if (q < ncopy) {
     k = pairs[2 * q];
     const int64_t src = pairs[2 * q + 1];
-    for (int m = 0; m < 4; ++m) s[m] = U[m * P + src];
+    if (j == 0)
+      for (int m = 0; m < 4; ++m) s[m] = U[m * P + src];
   } else {
     q -= ncopy;
     k = dst[q];
-    for (int e = ptr[q]; e < ptr[q + 1]; ++e) {
+    for (int e = ptr[q] + j; e < ptr[q + 1]; e += kFringeLanes) {
       const double w = val[e];
       const int64_t c = col[e];
       for (int m = 0; m < 4; ++m) s[m] += w * U[m * P + c];
     }
   }
-  for (int m = 0; m < 4; ++m) U[m * P + k] = s[m];
-  if (fo.F) store_flux(fo, P, k, flags[k], s[0], s[1], s[2], s[3]);
-  if (ps) ps[k] = proxy_speed(s[0], s[1], s[2], s[3], gamma);
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    s[m] += __shfl_xor(s[m], 1);
+    s[m] += __shfl_xor(s[m], 2);
+  }
+  U[j * P + k] = s[j];
+  if (fo.F) {
+    double v[8];
+    flux_of(fo, k, flags[k], s[0], s[1], s[2], s[3], v);
+    fo.F[j * P + k] = v[j];
+    fo.F[(4 + j) * P + k] = v[4 + j];
+  }
+  if (ps && j == 0) ps[k] = proxy_speed(s[0], s[1], s[2], s[3], gamma);
 }
 
 // Proxy (Mach number) and |u| + a at every point.
@@ -833,7 +856,8 @@ hipError_t launch_fringe(double* U, const uint8_t* flags, const int64_t* copy_pa
                          const int32_t* iptr, const int64_t* icol, const double* ival, int ninterp, int64_t P,
                          const FluxOut& fo, double2* ps, double gamma, hipStream_t s) {
   if (ncopy + ninterp)
-    hipLaunchKernelGGL(k_fringe, grid_for(ncopy + ninterp), dim3(256), 0, s, U, flags, copy_pairs, ncopy, idst, iptr,
+    hipLaunchKernelGGL(k_fringe, grid_for(static_cast<int64_t>(kFringeLanes) * (ncopy + ninterp)), dim3(256), 0, s, U,
+                       flags, copy_pairs, ncopy, idst, iptr,
                        icol, ival, ninterp, P, fo, ps, gamma);
   return hipGetLastError();
 }
